@@ -1,0 +1,226 @@
+"""DG right-hand side of Eq. (2) and SSP-RK3 time stepping (oracle).
+
+TEST INFRASTRUCTURE ONLY.
+
+Eq. (2) of the paper: for element ``i`` and basis function ``v_ij``,
+
+    d c_ij / dt = int_{Omega_i} F(U_i) . grad v_ij
+                  - sum_q int_{I_iq} v_ij F*(U_i, U_pq) . n_iq,
+
+with ``v_ij = phi_j / sqrt(det J_i)`` orthonormal on the physical element.
+
+* :func:`volume_rhs` -- the first (element-local) term, evaluated with the
+  collapsed volume rule of :mod:`oracle.quadrature` (``n = p + 1`` points per
+  direction):  ``rhs_ij = sqrt(det J) sum_q w_q sum_d d_d phi_j(xi_q) G_d(U_q)``
+  with the contravariant flux ``G_d = sum_e (J^-1)_{de} F_e``.
+* :func:`surface_rhs` -- the second term as a *plain loop over faces in id
+  order*, each face adding ``-|f| sum_q w_q v_Lj F*_q`` to its left element
+  and ``+|f| sum_q w_q v_Rj F*_q`` to its right element (``F*_q`` taken along
+  the L-to-R normal; the right element's outward normal is ``-n`` and the
+  Rusanov flux is conservative).  This is the order-dependent "race" form
+  that the paper's coloring makes safe on a GPU; its result does not
+  depend on any coloring or layout.
+* :func:`rk3_step` -- three-stage SSP Runge-Kutta in Shu-Osher form (the
+  time integrator is not named in the paper; this is the project's reading).
+
+Pins (``tests/test_oracle_dg.py``): free-stream preservation on periodic
+triangle and tetrahedral meshes; discrete conservation of the mode-0 mass;
+the ``p = 0`` surface term equals the first-order finite-volume Rusanov
+update ``-(1/|Omega|) sum |f| F* . n`` (times ``sqrt(|Omega|)``); order
+``p + 1`` convergence on the isentropic vortex; the SSP-RK3 amplification
+factor ``1 + z + z^2/2 + z^3/6`` on a linear problem.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+from . import basis, euler, quadrature
+
+
+class Discretization:
+    """Quadrature, basis values and per-face reference points for one mesh and order."""
+
+    def __init__(self, mesh, p: int):
+        self.mesh = mesh
+        self.p = p
+        self.dim = mesh.dim
+        self.n_p = basis.n_modes(self.dim, p)
+        self.M = self.dim + 2
+        if self.dim == 2:
+            self.vol_pts, self.vol_w = quadrature.tri_volume_rule(p + 1)
+            s, w = quadrature.gauss_legendre_01(p + 1)
+            self.face_bary = np.stack([1.0 - s, s], axis=1)
+            self.face_w = w
+        else:
+            if p > 1:
+                raise NotImplementedError("tetrahedral face rule only for p <= 1")
+            self.vol_pts, self.vol_w = quadrature.tet_volume_rule(p + 1)
+            self.face_bary, self.face_w = quadrature.tet_face_rule_p1()
+        self.vol_B = basis.eval_basis(self.dim, p, self.vol_pts)          # [Qv, Np]
+        self.vol_D = basis.eval_grad(self.dim, p, self.vol_pts)           # [Qv, dim, Np]
+        self.phi0 = float(basis.eval_basis(self.dim, 0, self.vol_pts[:1])[0, 0])
+        self._face_cache = {}
+
+    def face_local_positions(self, side: int) -> np.ndarray:
+        """``[E, nfv]`` local vertex index, in the element on ``side``, of each face vertex."""
+        mesh = self.mesh
+        e = mesh.face_elem[:, side]
+        ev = mesh.elem_vert[np.where(e >= 0, e, 0)]
+        match = ev[:, None, :] == mesh.face_vert[:, :, None]
+        pos = np.argmax(match, axis=2)
+        pos[e < 0] = 0
+        return pos
+
+    def face_basis(self, side: int) -> np.ndarray:
+        """``[E, Q, Np]`` basis values at the face quadrature points seen from ``side``."""
+        if side not in self._face_cache:
+            pos = self.face_local_positions(side)
+            ref = basis.REF_VERTS[self.dim][pos]                   # [E, nfv, dim]
+            pts = np.einsum("qv,evd->eqd", self.face_bary, ref)     # [E, Q, dim]
+            E, Q, _ = pts.shape
+            self._face_cache[side] = basis.eval_basis(self.dim, self.p, pts.reshape(E * Q, -1)).reshape(
+                E, Q, self.n_p)
+        return self._face_cache[side]
+
+
+def traces(B, C, detJ):
+    """``U(x_q) = sum_j c_j phi_j(xi_q) / sqrt(det J)`` -> ``[..., Q, M]``."""
+    return np.einsum("fqj,fmj->fqm", B, C) / np.sqrt(detJ)[:, None, None]
+
+
+def volume_rhs(d: Discretization, U: np.ndarray) -> np.ndarray:
+    mesh = d.mesh
+    sq = np.sqrt(mesh.detJ)
+    Uq = np.einsum("qj,kmj->kqm", d.vol_B, U) / sq[:, None, None]       # [K, Qv, M]
+    Fq = euler.physical_flux(Uq)                                        # [K, Qv, M, dim(e)]
+    G = np.einsum("kde,kqme->kqmd", mesh.Jinv, Fq)                      # contravariant
+    rhs = np.einsum("q,qdj,kqmd->kmj", d.vol_w, d.vol_D, G)
+    return rhs * sq[:, None, None]
+
+
+def surface_rhs(d: Discretization, U: np.ndarray, elems=None) -> np.ndarray:
+    """Surface term of Eq. (2) by a plain face loop (vectorised over faces, then
+    accumulated in face order with ``np.add.at``).
+
+    If ``elems`` is given, only faces touching those elements are evaluated
+    (rows of other elements are then incomplete and must not be used).
+    """
+    mesh = d.mesh
+    L = mesh.face_elem[:, 0]
+    R = mesh.face_elem[:, 1]
+    faces = np.arange(mesh.E)
+    if elems is not None:
+        sel = np.zeros(mesh.K, dtype=bool)
+        sel[np.asarray(elems)] = True
+        faces = faces[sel[L] | (R >= 0) & sel[np.where(R >= 0, R, 0)]]
+    Lf = L[faces]
+    Rf = R[faces]
+    inter = Rf >= 0
+    n = mesh.normal[faces]
+    BL = d.face_basis(0)[faces]
+    BR = d.face_basis(1)[faces]
+    UL = traces(BL, U[Lf], mesh.detJ[Lf])
+    Rs = np.where(inter, Rf, 0)
+    UR = traces(BR, U[Rs], mesh.detJ[Rs])
+    ghost = euler.wall_ghost(UL, n[:, None, :])
+    UR = np.where(inter[:, None, None], UR, ghost)
+    Fs = euler.rusanov(UL, UR, n[:, None, :])                            # [nf, Q, M]
+    scale_L = mesh.measure[faces] / np.sqrt(mesh.detJ[Lf])
+    scale_R = mesh.measure[faces] / np.sqrt(mesh.detJ[Rs])
+    dL = np.einsum("q,fqj,fqm->fmj", d.face_w, BL, Fs) * scale_L[:, None, None]
+    dR = np.einsum("q,fqj,fqm->fmj", d.face_w, BR, Fs) * scale_R[:, None, None]
+    rhs = np.zeros_like(U)
+    np.add.at(rhs, Lf, -dL)
+    np.add.at(rhs, Rf[inter], dR[inter])
+    return rhs
+
+
+def surface_abs(d: Discretization, U: np.ndarray) -> np.ndarray:
+    """Sum of absolute per-face contributions per entry (scale for parity tolerances)."""
+    mesh = d.mesh
+    L = mesh.face_elem[:, 0]
+    R = mesh.face_elem[:, 1]
+    inter = R >= 0
+    n = mesh.normal
+    BL = d.face_basis(0)
+    BR = d.face_basis(1)
+    Rs = np.where(inter, R, 0)
+    UL = traces(BL, U[L], mesh.detJ[L])
+    UR = np.where(inter[:, None, None], traces(BR, U[Rs], mesh.detJ[Rs]), euler.wall_ghost(UL, n[:, None, :]))
+    Fs = euler.rusanov(UL, UR, n[:, None, :])
+    aL = np.einsum("q,fqj,fqm->fmj", d.face_w, np.abs(BL), np.abs(Fs)) * (mesh.measure / np.sqrt(mesh.detJ[L]))[:, None, None]
+    aR = np.einsum("q,fqj,fqm->fmj", d.face_w, np.abs(BR), np.abs(Fs)) * (mesh.measure / np.sqrt(mesh.detJ[Rs]))[:, None, None]
+    out = np.zeros_like(U)
+    np.add.at(out, L, aL)
+    np.add.at(out, R[inter], aR[inter])
+    return out
+
+
+def rhs(d: Discretization, U: np.ndarray) -> np.ndarray:
+    return volume_rhs(d, U) + surface_rhs(d, U)
+
+
+def ssp_rk3(f, U: np.ndarray, dt: float) -> np.ndarray:
+    """One step of the three-stage SSP Runge-Kutta method in Shu-Osher form for ``U' = f(U)``."""
+    U1 = U + dt * f(U)
+    U2 = 0.75 * U + 0.25 * (U1 + dt * f(U1))
+    return U / 3.0 + 2.0 / 3.0 * (U2 + dt * f(U2))
+
+
+def rk3_step(d: Discretization, U: np.ndarray, dt: float) -> np.ndarray:
+    """One SSP-RK3 step of the semi-discrete DG system."""
+    return ssp_rk3(lambda V: rhs(d, V), U, dt)
+
+
+def mean_states(d: Discretization, U: np.ndarray) -> np.ndarray:
+    """Element means ``c_0 phi_0 / sqrt(det J)``."""
+    return U[:, :, 0] * d.phi0 / np.sqrt(d.mesh.detJ)[:, None]
+
+
+def inradius(mesh) -> np.ndarray:
+    per = np.zeros(mesh.K)
+    np.add.at(per, mesh.face_elem[:, 0], mesh.measure)
+    inter = mesh.face_elem[:, 1] >= 0
+    np.add.at(per, mesh.face_elem[inter, 1], mesh.measure[inter])
+    return mesh.dim * mesh.elem_measure / per
+
+
+def cfl_dt(d: Discretization, U: np.ndarray, cfl: float) -> float:
+    """``dt = cfl * min(2 r_in) / max(|u| + c)`` at the element means."""
+    m = mean_states(d, U)
+    vel = m[:, 1:-1] / m[:, :1]
+    smax = (np.linalg.norm(vel, axis=1) + euler.sound_speed(m)).max()
+    return float(cfl * (2.0 * inradius(d.mesh)).min() / smax)
+
+
+def physical_points(mesh, ref_pts: np.ndarray) -> np.ndarray:
+    """``x = x_0 + J xi`` for every element and reference point -> ``[K, nq, dim]``."""
+    x0 = mesh.elem_xyz[:, 0, :]
+    J = np.stack([mesh.elem_xyz[:, k + 1, :] - x0 for k in range(mesh.dim)], axis=2)
+    return x0[:, None, :] + np.einsum("ked,qd->kqe", J, ref_pts)
+
+
+def project(d: Discretization, func, extra: int = 3) -> np.ndarray:
+    """L2 projection ``c_ij = sqrt(det J) sum_q w_q u(x_q) phi_j(xi_q)``."""
+    mesh = d.mesh
+    n = d.p + 1 + extra
+    if d.dim == 2:
+        pts, w = quadrature.tri_volume_rule(n)
+    else:
+        pts, w = quadrature.tet_volume_rule(n)
+    B = basis.eval_basis(d.dim, d.p, pts)
+    X = physical_points(mesh, pts)
+    u = func(X.reshape(-1, d.dim)).reshape(mesh.K, len(w), -1)
+    return np.einsum("q,qj,kqm->kmj", w, B, u) * np.sqrt(mesh.detJ)[:, None, None]
+
+
+def l2_error(d: Discretization, U: np.ndarray, func, var: int = 0, extra: int = 3) -> float:
+    mesh = d.mesh
+    n = d.p + 1 + extra
+    pts, w = quadrature.tri_volume_rule(n) if d.dim == 2 else quadrature.tet_volume_rule(n)
+    B = basis.eval_basis(d.dim, d.p, pts)
+    X = physical_points(mesh, pts)
+    ex = func(X.reshape(-1, d.dim)).reshape(mesh.K, len(w), -1)[:, :, var]
+    num = np.einsum("qj,kj->kq", B, U[:, var, :]) / np.sqrt(mesh.detJ)[:, None]
+    return float(np.sqrt((np.einsum("q,kq->k", w, (num - ex) ** 2) * mesh.detJ).sum()))

@@ -1,0 +1,147 @@
+"""Face table and geometry of a conforming simplex mesh (oracle).
+
+TEST INFRASTRUCTURE ONLY.
+
+The paper stores the mesh connectivity face-wise: each edge (face) points to
+the two elements that share it, its left and right element (Section 1 and
+Section 5, "Mesh connectivity is stored as pointers", Table 5a).  The
+enumeration below is the reading used by this project (the paper gives
+none):
+
+* triangles are counter-clockwise; local edge ``k`` joins local vertices
+  ``k`` and ``(k + 1) mod 3``; tetrahedra have positive volume and local
+  face ``k`` is opposite local vertex ``k``, its vertices listed in
+  ascending local order;
+* faces are numbered in order of first visit when scanning elements
+  ``0..K-1`` and their local faces ``0..F-1``; the first visitor is the left
+  element ``L``, the second the right element ``R``; a third visitor, or a
+  non-positive element measure, is an error; faces with one visitor are
+  boundary faces (``R = -1``);
+* the unit normal points from ``L`` to ``R`` and is computed from ``L``'s
+  own (unwrapped) coordinates, which makes periodic seams work;
+* each face stores its vertex ids in ``L``'s order; quadrature points are
+  placed by barycentric weights on these vertices, and each side maps them
+  to its own reference coordinates through the position of the vertex ids
+  in its own element.
+
+Pins (``tests/test_oracle_mesh.py``): ``E = 3K/2`` on closed triangle
+meshes and ``E = 2K`` on closed tetrahedral ones; Euler's formula on the
+torus; every element's outward normals weighted by face measure sum to
+zero; the total measure equals the domain measure.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+from .basis import REF_VERTS
+
+
+def local_faces(dim: int):
+    """Local vertex lists of the faces of the reference element."""
+    if dim == 2:
+        return [(0, 1), (1, 2), (2, 0)]
+    return [(1, 2, 3), (0, 2, 3), (0, 1, 3), (0, 1, 2)]
+
+
+class MeshError(ValueError):
+    pass
+
+
+@dataclass
+class Mesh:
+    dim: int
+    K: int
+    E: int
+    elem_vert: np.ndarray      # [K, nv] vertex ids
+    elem_xyz: np.ndarray       # [K, nv, dim]
+    face_elem: np.ndarray      # [E, 2] (L, R), R = -1 on the boundary
+    face_local: np.ndarray     # [E, 2] local face index in L and R (-1)
+    face_vert: np.ndarray      # [E, nfv] vertex ids in L's order
+    elem_face: np.ndarray      # [K, F] face id of each local face
+    normal: np.ndarray         # [E, dim] unit normal, L -> R
+    measure: np.ndarray        # [E] face length / area
+    detJ: np.ndarray           # [K]
+    Jinv: np.ndarray           # [K, dim, dim], Jinv[d, e] = d xi_d / d x_e
+    elem_measure: np.ndarray   # [K]
+
+    @property
+    def n_boundary(self) -> int:
+        return int((self.face_elem[:, 1] < 0).sum())
+
+    def face_ref_points(self, f: int, side: int, bary: np.ndarray) -> np.ndarray:
+        """Reference coordinates on side ``side`` (0 = L, 1 = R) of the points with
+        barycentric weights ``bary[q, :]`` on the face's vertices (L's order)."""
+        e = self.face_elem[f, side]
+        verts = list(self.elem_vert[e])
+        ref = REF_VERTS[self.dim]
+        loc = [verts.index(v) for v in self.face_vert[f]]
+        return bary @ ref[loc]
+
+
+def build_mesh(elem_vert, elem_xyz) -> Mesh:
+    ev = np.asarray(elem_vert, dtype=np.int64)
+    xyz = np.asarray(elem_xyz, dtype=np.float64)
+    K, nv = ev.shape
+    dim = xyz.shape[2]
+    if (dim, nv) not in ((2, 3), (3, 4)):
+        raise MeshError("only triangles and tetrahedra are supported")
+    lf = local_faces(dim)
+    F = len(lf)
+
+    # Jacobians: columns are the edge vectors from local vertex 0
+    J = np.stack([xyz[:, d + 1, :] - xyz[:, 0, :] for d in range(dim)], axis=2)  # J[k, e, d] = dx_e/dxi_d
+    detJ = np.linalg.det(J)
+    if (detJ <= 0).any():
+        raise MeshError("element %d has non-positive measure" % int(np.argmin(detJ)))
+    Jinv = np.linalg.inv(J)  # Jinv[k, d, e] = dxi_d/dx_e
+    elem_measure = detJ / (2.0 if dim == 2 else 6.0)
+
+    key_to_face = {}
+    face_elem = []
+    face_local = []
+    face_vert = []
+    elem_face = np.full((K, F), -1, dtype=np.int64)
+    for i in range(K):
+        for k, loc in enumerate(lf):
+            vids = tuple(int(ev[i, a]) for a in loc)
+            key = tuple(sorted(vids))
+            f = key_to_face.get(key)
+            if f is None:
+                f = len(face_elem)
+                key_to_face[key] = f
+                face_elem.append([i, -1])
+                face_local.append([k, -1])
+                face_vert.append(vids)
+            else:
+                if face_elem[f][1] != -1:
+                    raise MeshError("face %r has more than two elements" % (key,))
+                face_elem[f][1] = i
+                face_local[f][1] = k
+            elem_face[i, k] = f
+    face_elem = np.array(face_elem, dtype=np.int64)
+    face_local = np.array(face_local, dtype=np.int64)
+    face_vert = np.array(face_vert, dtype=np.int64)
+    E = len(face_elem)
+
+    # geometry from L's own coordinates (vectorised over faces)
+    LF = np.array(lf, dtype=np.int64)
+    L = face_elem[:, 0]
+    P = xyz[L[:, None], LF[face_local[:, 0]], :]          # [E, nfv, dim]
+    if dim == 2:
+        t = P[:, 1] - P[:, 0]
+        measure = np.hypot(t[:, 0], t[:, 1])
+        normal = np.stack([t[:, 1], -t[:, 0]], axis=1) / measure[:, None]
+    else:
+        c = np.cross(P[:, 1] - P[:, 0], P[:, 2] - P[:, 0])
+        ar = np.linalg.norm(c, axis=1)
+        normal = c / ar[:, None]
+        opp = xyz[L].mean(axis=1)
+        flip = np.einsum("ij,ij->i", P[:, 0] - opp, normal) < 0
+        normal[flip] *= -1.0
+        measure = 0.5 * ar
+    return Mesh(dim=dim, K=K, E=E, elem_vert=ev, elem_xyz=xyz, face_elem=face_elem,
+                face_local=face_local, face_vert=face_vert, elem_face=elem_face,
+                normal=normal, measure=measure, detJ=detJ, Jinv=Jinv, elem_measure=elem_measure)

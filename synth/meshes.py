@@ -1,0 +1,245 @@
+"""Seeded synthetic meshes shaped like the paper's workloads.
+
+Every generator returns a dict with
+
+* ``elem_vert`` -- int32 ``[K, nv]`` vertex ids.  On periodic meshes the
+  images of a vertex share one id, so faces across the periodic seam are
+  matched by id like any other face.
+* ``elem_xyz`` -- float64 ``[K, nv, dim]`` *unwrapped* vertex coordinates
+  of each element (an element that straddles the seam keeps its own
+  geometric copy of the vertices), ordered counter-clockwise in 2D and
+  with positive signed volume in 3D.
+* ``n_vert`` -- number of distinct vertex ids.
+
+The meshes stand in for the paper's triangular, tetrahedral and refined
+meshes (its Tables 1 and 3), which are not distributed with it.
+"""
+
+from __future__ import annotations
+
+import itertools
+
+import numpy as np
+
+
+def periodic_tri(n: int, jitter: float = 0.1, seed: int = 1, length: float = 1.0):
+    """``n x n`` cells on the periodic square, each split along the same diagonal.
+
+    Vertex ``(i, j)`` sits at ``(i h, j h)`` plus a displacement drawn from
+    ``U(-jitter h, jitter h)`` per coordinate; the displacement of a vertex is
+    shared by all its periodic images.  Every cell is cut from its lower-left
+    to its upper-right corner, so the edges fall into three direction classes
+    (horizontal, vertical, diagonal) -- on the torus the coloring problem is
+    then solvable with three colors.
+    Element ``2 (i + n j)`` is the lower-right triangle of cell ``(i, j)`` and
+    ``2 (i + n j) + 1`` the upper-left one.
+    """
+    if n < 3:
+        raise ValueError("periodic_tri needs n >= 3")
+    h = length / n
+    rng = np.random.default_rng(seed)
+    disp = rng.uniform(-jitter * h, jitter * h, size=(n, n, 2))
+    ii, jj = np.meshgrid(np.arange(n), np.arange(n), indexing="xy")
+    ii = ii.ravel()
+    jj = jj.ravel()
+
+    def vid(a, b):
+        return (a % n) + n * (b % n)
+
+    def pos(a, b):
+        base = np.stack([a * h, b * h], axis=-1).astype(np.float64)
+        return base + disp[a % n, b % n]
+
+    c00 = (ii, jj)
+    c10 = (ii + 1, jj)
+    c11 = (ii + 1, jj + 1)
+    c01 = (ii, jj + 1)
+    tri_a = [c00, c10, c11]  # lower-right, counter-clockwise
+    tri_b = [c00, c11, c01]  # upper-left, counter-clockwise
+    K = 2 * n * n
+    ev = np.empty((K, 3), dtype=np.int32)
+    xyz = np.empty((K, 3, 2), dtype=np.float64)
+    for t, tri in enumerate((tri_a, tri_b)):
+        for k, (a, b) in enumerate(tri):
+            ev[t::2, k] = vid(a, b)
+            xyz[t::2, k, :] = pos(a, b)
+    return {"elem_vert": ev, "elem_xyz": xyz, "n_vert": n * n, "h": h, "periodic": True}
+
+
+def _poisson_disc(radius: float, seed: int, max_fail: int = 12):
+    """Poisson-disc points in the unit square, with boundary points every ``radius``.
+
+    Boundary points (the four corners and equally spaced points, at least
+    ``radius`` apart, along each side) are placed first.  Interior points are
+    then added by parallel dart throwing on a grid of cells of side
+    ``radius / sqrt(2)``, which holds at most one point per cell: in each
+    round and for each of the nine phases ``(ix mod 3, iy mod 3)`` every
+    still-active empty cell of that phase proposes one uniform point, which
+    is accepted when no accepted point lies closer than ``radius``.  Cells
+    of one phase are three cells apart, so proposals of a phase never
+    conflict with each other.  A cell stops proposing after ``max_fail``
+    rejected proposals.
+    """
+    rng = np.random.default_rng(seed)
+    g = radius / np.sqrt(2.0)
+    G = int(np.ceil(1.0 / g))
+    grid = -np.ones((G + 4, G + 4), dtype=np.int64)  # 2-cell apron on each side
+
+    m = int(np.floor(1.0 / radius))
+    side = np.linspace(0.0, 1.0, m + 1)
+    bnd = set()
+    for t in side:
+        for p in ((t, 0.0), (t, 1.0), (0.0, t), (1.0, t)):
+            bnd.add((float(p[0]), float(p[1])))
+    coords = np.array(sorted(bnd), dtype=np.float64)
+    cx = np.minimum((coords[:, 0] / g).astype(np.int64), G - 1) + 2
+    cy = np.minimum((coords[:, 1] / g).astype(np.int64), G - 1) + 2
+    if len(set(zip(cx.tolist(), cy.tolist()))) != len(coords):
+        raise RuntimeError("two boundary points share a grid cell")
+    grid[cx, cy] = np.arange(len(coords))
+    npts = len(coords)
+
+    offs = [(dx, dy) for dx in range(-2, 3) for dy in range(-2, 3)]
+    phases = []
+    for px in range(3):
+        for py in range(3):
+            ax = np.arange(2 + px, G + 2, 3)
+            ay = np.arange(2 + py, G + 2, 3)
+            AX, AY = np.meshgrid(ax, ay, indexing="ij")
+            AX = AX.ravel()
+            AY = AY.ravel()
+            keep = grid[AX, AY] < 0
+            phases.append([AX[keep], AY[keep], np.zeros(keep.sum(), dtype=np.int64)])
+    while any(ph[0].size for ph in phases):
+        for ph in phases:
+            CX, CY, fails = ph
+            if CX.size == 0:
+                continue
+            u = rng.random((CX.size, 2))
+            cand = np.stack([(CX - 2 + u[:, 0]) * g, (CY - 2 + u[:, 1]) * g], axis=1)
+            ok = (cand[:, 0] < 1.0) & (cand[:, 1] < 1.0) & (cand[:, 0] > 0.0) & (cand[:, 1] > 0.0)
+            for dx, dy in offs:
+                nb = grid[CX + dx, CY + dy]
+                has = nb >= 0
+                if not has.any():
+                    continue
+                q = coords[np.where(has, nb, 0)]
+                d2 = ((q - cand) ** 2).sum(axis=1)
+                ok &= ~(has & (d2 < radius * radius))
+            acc = np.nonzero(ok)[0]
+            if acc.size:
+                ids = np.arange(npts, npts + acc.size)
+                grid[CX[acc], CY[acc]] = ids
+                coords = np.concatenate([coords, cand[acc]], axis=0)
+                npts += acc.size
+            fails = fails + (~ok)
+            alive = (~ok) & (fails < max_fail)
+            ph[0], ph[1], ph[2] = CX[alive], CY[alive], fails[alive]
+    return coords
+
+
+def poisson_delaunay(n_points: int = 500_000, seed: int = 2, radius: float | None = None):
+    """Delaunay triangulation of about ``n_points`` seeded Poisson-disc points.
+
+    The unit square has reflective walls, so the mesh is not periodic and
+    ``elem_xyz`` is simply the vertex coordinates.  The disc radius is
+    chosen from the measured packing density of the sampler
+    (``N ~ 0.645 / r^2``) unless given.  Triangles are ordered as Qhull
+    returns them and re-oriented counter-clockwise; zero-area triangles
+    (collinear boundary points) are dropped.
+    """
+    from scipy.spatial import Delaunay  # generator-only dependency
+
+    if radius is None:
+        radius = float(np.sqrt(0.6446 / n_points))
+    pts = _poisson_disc(radius, seed)
+    tri = Delaunay(pts)
+    ev = tri.simplices.astype(np.int32).copy()
+    xyz = pts[ev]
+    area2 = (xyz[:, 1, 0] - xyz[:, 0, 0]) * (xyz[:, 2, 1] - xyz[:, 0, 1]) - (
+        xyz[:, 2, 0] - xyz[:, 0, 0]
+    ) * (xyz[:, 1, 1] - xyz[:, 0, 1])
+    neg = area2 < 0
+    ev[neg, 1], ev[neg, 2] = ev[neg, 2].copy(), ev[neg, 1].copy()
+    keep = np.abs(area2) > 1e-14 * radius * radius
+    ev = np.ascontiguousarray(ev[keep])
+    xyz = np.ascontiguousarray(pts[ev])
+    return {"elem_vert": ev, "elem_xyz": xyz, "n_vert": len(pts), "h": radius, "periodic": False,
+            "points": pts}
+
+
+def kuhn_tets(n: int, jitter: float = 0.05, seed: int = 3, length: float = 1.0):
+    """``n^3`` periodic cubes, each split into the six Kuhn tetrahedra.
+
+    Every tetrahedron of cube ``(i, j, k)`` runs from the cube's corner
+    ``(0,0,0)`` to its corner ``(1,1,1)`` through one monotone lattice path
+    (one per permutation of the axes).  Vertices are displaced by
+    ``U(-jitter h, jitter h)`` per coordinate, identically for periodic
+    images.  Odd permutations list their vertices with the middle two
+    swapped so that every tetrahedron has positive volume.
+    Element ``6 (i + n j + n^2 k) + s`` uses the ``s``-th permutation of
+    ``itertools.permutations(range(3))``.
+    """
+    if n < 2:
+        raise ValueError("kuhn_tets needs n >= 2")
+    h = length / n
+    rng = np.random.default_rng(seed)
+    disp = rng.uniform(-jitter * h, jitter * h, size=(n, n, n, 3))
+    idx = np.arange(n)
+    I, J, Kc = np.meshgrid(idx, idx, idx, indexing="ij")
+    # cube order: i fastest, then j, then k
+    I = I.transpose(2, 1, 0).ravel()
+    J = J.transpose(2, 1, 0).ravel()
+    Kc = Kc.transpose(2, 1, 0).ravel()
+    ncube = n ** 3
+    perms = list(itertools.permutations(range(3)))
+    ev = np.empty((6 * ncube, 4), dtype=np.int32)
+    xyz = np.empty((6 * ncube, 4, 3), dtype=np.float64)
+
+    def vid(a, b, c):
+        return (a % n) + n * (b % n) + n * n * (c % n)
+
+    def pos(a, b, c):
+        base = np.stack([a * h, b * h, c * h], axis=-1).astype(np.float64)
+        return base + disp[a % n, b % n, c % n]
+
+    for s, perm in enumerate(perms):
+        corner = [np.zeros(3, dtype=np.int64)]
+        for ax in perm:
+            nxt = corner[-1].copy()
+            nxt[ax] += 1
+            corner.append(nxt)
+        # parity of the permutation decides the vertex order
+        inv = sum(1 for x in range(3) for y in range(x + 1, 3) if perm[x] > perm[y])
+        order = [0, 1, 2, 3] if inv % 2 == 0 else [0, 2, 1, 3]
+        for slot, c in enumerate(order):
+            off = corner[c]
+            a, b, cc = I + off[0], J + off[1], Kc + off[2]
+            ev[s::6, slot] = vid(a, b, cc)
+            xyz[s::6, slot, :] = pos(a, b, cc)
+    # orientation check (input sanity, not part of the method)
+    vol = element_measure(xyz)
+    if (vol <= 0).any():
+        flip = vol <= 0
+        ev[flip, 1], ev[flip, 2] = ev[flip, 2].copy(), ev[flip, 1].copy()
+        xyz[flip, 1], xyz[flip, 2] = xyz[flip, 2].copy(), xyz[flip, 1].copy()
+    return {"elem_vert": ev, "elem_xyz": xyz, "n_vert": n ** 3, "h": h, "periodic": True}
+
+
+def element_measure(elem_xyz: np.ndarray) -> np.ndarray:
+    """Signed area (triangles) or volume (tetrahedra) of each element."""
+    x = np.asarray(elem_xyz, dtype=np.float64)
+    if x.shape[1] == 3 and x.shape[2] == 2:
+        a = x[:, 1] - x[:, 0]
+        b = x[:, 2] - x[:, 0]
+        return 0.5 * (a[:, 0] * b[:, 1] - a[:, 1] * b[:, 0])
+    if x.shape[1] == 4 and x.shape[2] == 3:
+        a = x[:, 1] - x[:, 0]
+        b = x[:, 2] - x[:, 0]
+        c = x[:, 3] - x[:, 0]
+        return np.einsum("ij,ij->i", a, np.cross(b, c)) / 6.0
+    raise ValueError("unsupported element shape %r" % (x.shape,))
+
+
+def element_centroid(elem_xyz: np.ndarray) -> np.ndarray:
+    return np.asarray(elem_xyz, dtype=np.float64).mean(axis=1)
