@@ -1,0 +1,184 @@
+"""Benchmark of the colored DG surface pass on one MI355X.
+
+Workload (default): Delaunay triangulation of ~500 k seeded Poisson-disc
+points in the unit square (~1 M triangles, ~1.5 M edges), reflective walls,
+2D Euler with p = 2 (N_p = 6, M = 4), shock-tube state with seeded noise in
+the higher modes, float64.  One step = one full surface right-hand side over
+all colors (3 launches, one per color, ordered on the stream).
+
+Prints one JSON line with the metric (surface DOF-updates/s), the roofline
+of the surface kernel (algorithmic HBM bytes / measured time vs 8 TB/s),
+the same pass with the atomic and buffered-gather variants, the volume term
+and one SSP-RK3 step for context, and the CPU oracle timed on the host.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(n_face: int, n_interior: int, rec: int, elt: int, dim: int) -> int:
+    """Bytes one colored pass must move: per face side, read the DOF record and
+    read + write the RHS record; per face, its geometry (dim + 3 doubles),
+    both element ids (2 x int32) and both table codes (2 x uint8)."""
+    sides = n_face + n_interior
+    return sides * 3 * rec * elt + n_face * ((dim + 3) * 8 + 8 + 2)
+
+
+def timed(fn, steps, warmup, stream):
+    import torch
+
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    t0.record(stream)
+    for _ in range(steps):
+        fn()
+    t1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    return t0.elapsed_time(t1) / steps, wall
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--points", type=int, default=500_000)
+    ap.add_argument("--p", type=int, default=2)
+    ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--only", choices=["all", "colored"], default="all",
+                    help="'colored' times the colored pass only (for profiling)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (requested --gpus %d)" % args.gpus,
+              file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_1601_07613_amd as dgc
+    import synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+
+    t = time.perf_counter()
+    m = synth.poisson_delaunay(args.points, seed=args.seed)
+    gen_s = time.perf_counter() - t
+    log("mesh generated: K=%d in %.1fs" % (len(m["elem_vert"]), gen_s))
+    t = time.perf_counter()
+    M = dgc.Mesh.build(m["elem_vert"], m["elem_xyz"])
+    build_s = time.perf_counter() - t
+    cst = M.color(seed=0)
+    D = dgc.DeviceMesh(M, args.p)
+    info = D.info
+    K, E, nb = info["n_elem"], info["n_face"], info["n_boundary"]
+    log("host preprocessing: build %.2fs, color %.0f ms, layout %.0f ms; E=%d" % (
+        build_s, cst["color_ms"], cst["layout_ms"], E))
+
+    meas = synth.element_measure(m["elem_xyz"])
+    st = synth.shock_tube_states(synth.element_centroid(m["elem_xyz"]))
+    U = synth.perturbed_dofs(meas, st, D.n_p, eps=0.01, seed=args.seed + 100)
+    Ug = torch.from_numpy(D.to_layout(U)).cuda()
+    rhs = torch.zeros_like(Ug)
+    stream = torch.cuda.current_stream()
+    rec = D.n_var * D.n_p
+    ab = algorithmic_bytes(E, E - nb, rec, 8, D.dim)
+
+    ms, wall = timed(lambda: D.surface_rhs(Ug, rhs, "colored"), args.steps, args.warmup, stream)
+    log("colored pass: %.1f us (wall %.2fs for %d steps)" % (ms * 1e3, wall, args.steps))
+    dof = K * D.n_var * D.n_p
+    value = dof / (ms * 1e-3)
+    achieved = ab / (ms * 1e-3) / 1e9
+
+    extra = {}
+    if args.only == "all":
+        ws = D.workspace("surface", "gather")
+        extra["atomic_us"] = timed(lambda: D.surface_rhs(Ug, rhs, "atomic"), args.steps, args.warmup, stream)[0] * 1e3
+        extra["gather_us"] = timed(lambda: D.surface_rhs(Ug, rhs, "gather", ws=ws), args.steps, args.warmup,
+                                   stream)[0] * 1e3
+        extra["volume_us"] = timed(lambda: D.volume_rhs(Ug, rhs), args.steps, args.warmup, stream)[0] * 1e3
+        wsr = D.workspace("rk", "colored")
+        Ur = Ug.clone()
+        extra["rk3_step_us"] = timed(lambda: D.rk_step(Ur, 1e-7, ws=wsr), max(args.steps // 5, 3), 2, stream)[0] * 1e3
+        extra["colored_over_atomic"] = extra["atomic_us"] / (ms * 1e3)
+        extra["colored_over_gather"] = extra["gather_us"] / (ms * 1e3)
+        for k, v in extra.items():
+            log("%s: %.2f" % (k, v))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import dg
+        from oracle.mesh import build_mesh
+
+        O = build_mesh(m["elem_vert"], m["elem_xyz"])
+        d = dg.Discretization(O, args.p)
+        d.face_basis(0)
+        d.face_basis(1)
+        reps = 2
+        t = time.perf_counter()
+        for _ in range(reps):
+            dg.surface_rhs(d, U)
+        cpu_s = (time.perf_counter() - t) / reps
+        cpu = {"value": dof / cpu_s, "unit": "DOF-updates/s", "cores": 1, "kind": "oracle",
+               "sample": "the full surface term of this workload (%d elements, %d faces), %d repetitions, "
+                         "numpy float64, single process" % (K, E, reps)}
+        log("cpu oracle: %.2f s per surface term" % cpu_s)
+
+    out = {
+        "metric": "surface-integral DOF-updates/s",
+        "value": value,
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "Delaunay triangulation of %d seeded Poisson-disc points in the unit square (%d triangles, "
+                        "%d edges, %d wall edges), 2D Euler p=%d (N_p=%d, M=4), shock tube, colored surface pass, "
+                        "paper layout" % (m["n_vert"], K, E, nb, args.p, D.n_p, ),
+            "n_elem": K, "n_face": E, "p": args.p, "n_colors": info["n_colors"], "variant": "colored",
+        },
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_pass": ab},
+        "cpu_baseline": cpu,
+        "host_preprocess": {"generate_s": gen_s, "build_s": build_s, "color_ms": cst["color_ms"],
+                            "layout_ms": cst["layout_ms"], "conflicts_after_greedy": cst["conflicts_after_greedy"]},
+        "variants_us": extra,
+    }
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

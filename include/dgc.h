@@ -1,0 +1,281 @@
+/*
+ * dgc.h -- C ABI of libdgc: race-free DG surface integrals on edge-colored
+ * unstructured meshes, for AMD Instinct MI355X (gfx950).
+ *
+ * Method: A. Giuliani and L. Krivodonova, "Edge coloring in unstructured CFD
+ * codes" (arXiv:1601.07613).  The surface term of the DG scheme (Eq. 2) is
+ * evaluated one face per work item; two faces that share an element would
+ * race on that element's right-hand side (Section 1, Figure 1).  The faces
+ * are therefore colored so that no element has two faces of one color
+ * (Sections 2-3) and processed one color at a time with a barrier between
+ * colors (Algorithm 1).  The coloring also drives an element renumbering and
+ * face reordering that make the memory accesses of the face kernel
+ * contiguous (Section 5, Tables 5-6).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every function returns a dgc_status: 0 (DGC_OK) on success, a negative
+ *   code on failure.  dgc_last_error() then returns a thread-local message.
+ *   Nothing is thrown across the ABI and no entry point writes outside the
+ *   buffers and sizes it is given.
+ * - Host objects (dgc_mesh) are owned by the library: create them with
+ *   dgc_mesh_build / dgc_mesh_refine, release them with dgc_mesh_free.
+ * - Device buffers are owned by the caller (raw device pointers, e.g. from a
+ *   framework's caching allocator).  Device entry points only enqueue work on
+ *   the given stream (a hipStream_t passed as void*, NULL = the null stream)
+ *   and return; asynchronous faults surface at the caller's synchronisation.
+ *   The library allocates no device memory and keeps no device state.
+ * - Colors are 0-based (the paper's color c is color c-1 here).
+ * - Element ids in device arrays are *layout* ids (after the renumbering of
+ *   Section 5); DOF and right-hand-side arrays are indexed by layout ids.
+ * - DOF / RHS layout on the device: element-major records,
+ *   U[k][m][j] = U[(k * M + m) * N_p + j] for layout element k, conserved
+ *   variable m (rho, rho u, rho v[, rho w], E) and mode j.  The coefficient
+ *   multiplies v_kj = phi_j / sqrt(det J_k), phi_j the orthonormal Dubiner
+ *   function on the unit reference element (mode order: total degree
+ *   ascending, then the second collapsed index ascending).
+ */
+#ifndef DGC_H
+#define DGC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DGC_OK = 0,
+    DGC_E_ARG = -1,              /* bad argument: null pointer, size, enum, buffer too small */
+    DGC_E_MESH = -2,             /* non-positive element measure, face shared by >2 elements */
+    DGC_E_NOT_COLORED = -3,      /* operation needs a colored and laid-out mesh */
+    DGC_E_COLOR_CAP = -4,        /* coloring move cap reached; mesh left uncolored */
+    DGC_E_COLORING_INVALID = -5, /* a supplied coloring has an element with two faces of one color */
+    DGC_E_UNSUPPORTED = -6,      /* element type / order / variant / precision not built */
+    DGC_E_WORKSPACE = -7,        /* workspace missing or smaller than dgc_workspace_bytes */
+    DGC_E_HIP = -8,              /* a HIP runtime call failed (message names it) */
+    DGC_E_ALLOC = -9             /* host allocation failed */
+} dgc_status;
+
+enum { DGC_TRI = 0, DGC_TET = 2 };
+
+/* dgc_color_edges flags: one coloring algorithm | one layout */
+#define DGC_COLOR_PAPER      0x01u /* modified greedy + conflict resolution (Section 3.1) */
+#define DGC_COLOR_GREEDY_STD 0x02u /* standard greedy, first free color (Section 1) */
+#define DGC_LAYOUT_PAPER     0x10u /* renumber elements + reorder faces (Section 5) */
+#define DGC_LAYOUT_RENUMBER  0x20u /* renumber elements only (Table 5) */
+#define DGC_LAYOUT_NONE      0x40u /* faces grouped by color, elements unchanged */
+
+#define DGC_MAX_COLORS 8
+
+typedef struct dgc_mesh dgc_mesh;
+
+typedef struct {
+    int64_t conflicts_after_greedy; /* faces left uncolored by the modified greedy stage */
+    int64_t swaps;                  /* conflict moves that keep the conflict count */
+    int64_t loop_breaks;            /* loop escapes that add one conflict */
+    int64_t deferrals;              /* conflicts re-queued (no same-colored pair to break) */
+    int32_t n_colors;
+    int32_t pad_;
+    int64_t count[DGC_MAX_COLORS];  /* faces per color */
+    double color_ms;                /* host wall time of the coloring */
+    double layout_ms;               /* host wall time of renumbering + reordering */
+} dgc_color_stats;
+
+typedef struct {
+    int32_t elem_type;       /* DGC_TRI or DGC_TET */
+    int32_t dim;             /* 2 or 3 */
+    int32_t n_vert_per_elem; /* 3 or 4 */
+    int32_t n_face_per_elem; /* conforming faces per element: 3 or 4 */
+    int32_t max_slots;       /* max faces (incl. hanging sub-faces) of one element */
+    int32_t n_colors;        /* 0 until colored */
+    int64_t n_elem;
+    int64_t n_face;
+    int64_t n_boundary;
+    int64_t color_off[DGC_MAX_COLORS + 1]; /* layout positions: color c = [off[c], off[c+1]) */
+    int32_t n_orient;        /* orientation codes per local face (table index = f*n_orient+o) */
+    int32_t max_level;       /* refinement level reached (0 = conforming base) */
+} dgc_mesh_info_t;
+
+/* Build the face table and geometry of a conforming mesh (face-wise
+ * connectivity, Section 5 "stored as pointers"; left/right elements,
+ * Section 3).
+ *   elem_type  DGC_TRI (3 vertices, counter-clockwise, 2D) or DGC_TET
+ *              (4 vertices, positive volume, 3D).
+ *   elem_vert  host int32 [n_elem][nv]: vertex ids; periodic images of a
+ *              vertex share one id.
+ *   elem_xyz   host f64 [n_elem][nv][dim]: each element's own (unwrapped)
+ *              vertex coordinates; geometry of a face is taken from its
+ *              left element.
+ * Faces are numbered by first visit scanning elements 0..K-1 and local faces
+ * 0..F-1 (triangle edge k joins local vertices k, k+1 mod 3; tetrahedron
+ * face k is opposite vertex k); the first visitor is the left element, the
+ * second the right one, a face with one visitor is a reflective wall.
+ * Errors: DGC_E_ARG, DGC_E_MESH (non-positive measure, face with >2 elements),
+ * DGC_E_ALLOC.  On success *out owns a new mesh. */
+dgc_status dgc_mesh_build(int32_t elem_type, int64_t n_elem, const int32_t *elem_vert,
+                          const double *elem_xyz, dgc_mesh **out);
+
+/* Color the faces (Section 3.1) and lay the mesh out (Section 5).
+ * DGC_COLOR_PAPER uses 3 colors for triangles and 4 for tetrahedra: a
+ * modified greedy pass with random non-conflicting colors (SplitMix64 seeded
+ * with `seed`), then conflict resolution by count-preserving swaps, loop
+ * breaks that uncolor a same-colored pair, and deferral of a conflict whose
+ * elements hold no such pair.  Moves are capped by max_swaps (<0: 1000 x
+ * n_face); reaching the cap returns DGC_E_COLOR_CAP and leaves the mesh
+ * uncolored (a caller may retry with another seed).
+ * DGC_COLOR_GREEDY_STD gives each face, in id order, the smallest color
+ * free on both elements (at most 5 colors for triangles, 7 for tetrahedra).
+ * Layout: the first color's k-th face (interior faces first) gets left
+ * element k and right element N_1 + k; the faces of later colors are sorted
+ * by ascending left element (Tables 5 and 6).  stats may be NULL.
+ * Errors: DGC_E_ARG, DGC_E_COLOR_CAP, DGC_E_UNSUPPORTED (refined meshes are
+ * colored by dgc_mesh_refine). */
+dgc_status dgc_color_edges(dgc_mesh *m, uint64_t seed, int64_t max_swaps, uint32_t flags,
+                           dgc_color_stats *stats);
+
+/* Install a caller-supplied coloring (host int8 [n_face], original face ids)
+ * and lay the mesh out with the given DGC_LAYOUT_* flag.  The coloring is
+ * checked exactly: an uncolored face, a color >= DGC_MAX_COLORS or an
+ * element with two faces of one color returns DGC_E_COLORING_INVALID and
+ * leaves the mesh unchanged. */
+dgc_status dgc_set_colors(dgc_mesh *m, const int8_t *colors, uint32_t layout_flags);
+
+/* Split the flagged leaf triangles of a colored mesh into four (midpoint
+ * split, Section 3.2), first splitting coarser neighbours so that adjacent
+ * leaves differ by at most one level, and color the new mesh by the
+ * closed-form map of Section 3.2: child edges of a parent edge of color c
+ * take c and (c + 3) mod 6 (the first child is the one at the parent edge's
+ * recorded start vertex); interior edges take the color of the parallel
+ * parent edge.  A hanging edge is split into its two sub-edges; the fine
+ * element is the left element and the coarse one the right element.
+ *   flags     host uint8 [n_elem of parent]: nonzero = refine this leaf.
+ *   n_closure out (may be NULL): leaves split only to restore the 2:1 balance.
+ * The result is colored (up to 6 colors) and laid out (DGC_LAYOUT_PAPER).
+ * Errors: DGC_E_ARG, DGC_E_NOT_COLORED, DGC_E_UNSUPPORTED (tetrahedra). */
+dgc_status dgc_mesh_refine(const dgc_mesh *parent, const uint8_t *flags, dgc_mesh **out,
+                           int64_t *n_closure);
+
+dgc_status dgc_mesh_info(const dgc_mesh *m, dgc_mesh_info_t *info);
+
+/* Arrays that dgc_mesh_export can copy out (host memory, caller-owned). */
+enum {
+    /* original face ids */
+    DGC_ARR_FACE_ELEM = 1,   /* int32 [E][2]: left, right original element (-1 = wall) */
+    DGC_ARR_FACE_LOCAL = 2,  /* int8  [E][2]: local face index in left / right element */
+    DGC_ARR_COLOR = 3,       /* int8  [E]: color of each face (-1 if uncolored) */
+    DGC_ARR_FACE_NORMAL = 4, /* f64   [E][dim]: unit normal, left -> right */
+    DGC_ARR_FACE_MEASURE = 5,/* f64   [E]: length / area */
+    DGC_ARR_ELEM_DETJ = 6,   /* f64   [K]: det of the reference-to-physical Jacobian */
+    DGC_ARR_ELEM_FACE = 7,   /* int32 [K][max_slots]: face ids of each element, -1 padded */
+    /* layout */
+    DGC_ARR_ELEM_NEW = 10,   /* int32 [K]: layout id of original element i */
+    DGC_ARR_FACE_ORDER = 11, /* int32 [E]: original face id at layout position k */
+    DGC_ARR_COLOR_OFF = 12,  /* int64 [n_colors + 1] */
+    /* device-ready arrays, layout order, structure-of-arrays */
+    DGC_ARR_DEV_FACE_LR = 20,   /* int32 [2][E]: layout ids of left / right element (-1 = wall) */
+    DGC_ARR_DEV_FACE_CODE = 21, /* uint8 [2][E]: table code of the left / right side */
+    DGC_ARR_DEV_FACE_GEO = 22,  /* f64 [dim+3][E]: n_0..n_{dim-1}, |f|, 1/sqrt(detJ_L), 1/sqrt(detJ_R) (0 at walls) */
+    DGC_ARR_DEV_ELEM_GEO = 23,  /* f64 [dim*dim+1][K]: (J^-1)_{de} row-major, then sqrt(det J) */
+    DGC_ARR_DEV_ELEM_SLOTS = 24,/* int32 [max_slots][K]: 2*face+side of each element's faces, -1 padded */
+    /* refinement bookkeeping */
+    DGC_ARR_ELEM_LEVEL = 30,    /* int8 [K]: refinement level of each leaf (original ids) */
+    DGC_ARR_ELEM_XYZ = 31,      /* f64 [K][nv][dim]: element vertex coordinates (original ids) */
+    DGC_ARR_ELEM_VERT = 32      /* int32 [K][nv]: element vertex ids (original ids) */
+};
+
+/* Copy array `which` into dst (bytes available).  *needed (if not NULL)
+ * receives the size in bytes; call with dst = NULL to query it.
+ * Errors: DGC_E_ARG (unknown array, dst too small), DGC_E_NOT_COLORED (a
+ * layout array of an uncolored mesh). */
+dgc_status dgc_mesh_export(const dgc_mesh *m, int32_t which, void *dst, size_t bytes, size_t *needed);
+
+void dgc_mesh_free(dgc_mesh *m);
+const char *dgc_last_error(void);
+
+/* Basis and quadrature tables for an element type and order (Eq. 2 with an
+ * orthonormal basis; the quadrature is not given by the paper: Gauss-Legendre
+ * with p+1 points on edges, the symmetric 3-point rule on tetrahedron faces
+ * (p = 1), collapsed Gauss-Jacobi rules with p+1 points per direction in the
+ * volume).  Layout of the f64 array (offsets in doubles, from info):
+ *   trace [n_codes][n_qf][n_p]  phi_j at face point q seen through code c
+ *   proj  [n_codes][n_qf][n_p]  w_q * trace (face weights sum to 1)
+ *   vb    [n_qv][n_p]           phi_j at volume point q
+ *   vd    [dim][n_qv][n_p]      w_q * d phi_j / d xi_d at volume point q
+ * Code c = f * n_orient + o addresses local face f seen with orientation o:
+ * o = 0 the face's own point order, 2D: 1 reversed, 2 / 3 reversed points on
+ * the first / second half of the edge (hanging edge seen from the coarse
+ * side); 3D: the o-th permutation (lexicographic) of the three points. */
+typedef struct {
+    int32_t elem_type, p, dim, n_p, n_qf, n_qv, n_codes, n_orient;
+    int64_t off_trace, off_proj, off_vb, off_vd, total; /* in doubles */
+} dgc_table_info;
+
+dgc_status dgc_tables(int32_t elem_type, int32_t p, dgc_table_info *info, double *dst, size_t bytes,
+                      size_t *needed);
+
+/* ---------------------------------------------------------------------- */
+/* Device entry points                                                     */
+/* ---------------------------------------------------------------------- */
+
+enum { DGC_SURF_COLORED = 0, DGC_SURF_ATOMIC = 1, DGC_SURF_GATHER = 2 };
+enum { DGC_F64 = 0, DGC_F32 = 1 };
+
+/* Device view of one laid-out mesh at one order.  Every pointer is a device
+ * pointer to the matching DGC_ARR_DEV_* / dgc_tables array, copied to the
+ * device by the caller; color_off is a host copy. */
+typedef struct {
+    int32_t elem_type, p, n_p, n_var, n_qf, n_qv, n_codes, n_orient;
+    int32_t n_colors, max_slots;
+    int64_t n_elem, n_face;
+    int64_t color_off[DGC_MAX_COLORS + 1];
+    const int32_t *face_lr;    /* [2][n_face] */
+    const uint8_t *face_code;  /* [2][n_face] */
+    const double *face_geo;    /* [dim+3][n_face] */
+    const double *elem_geo;    /* [dim*dim+1][n_elem] */
+    const int32_t *elem_slots; /* [max_slots][n_elem] (GATHER only; may be NULL otherwise) */
+    const double *tables;      /* dgc_tables layout for (elem_type, p) */
+} dgc_dmesh;
+
+/* Volume term of Eq. (2): rhs = int F(U) . grad v (overwrites rhs).
+ * U, rhs: device [n_elem][n_var][n_p] (f64, or f32 for DGC_F32). */
+dgc_status dgc_volume_rhs(const dgc_dmesh *dm, const void *U, void *rhs, int32_t precision, void *stream);
+
+/* Surface term of Eq. (2), accumulated: rhs -= sum_faces int v F* . n.
+ * DGC_SURF_COLORED: one launch per color, the launches ordered on `stream`
+ *   (the "synchronize threads" of Algorithm 1); each face updates its left
+ *   and right element with plain read-modify-write, race-free because no
+ *   element has two faces of one color.  Needs no workspace.
+ * DGC_SURF_ATOMIC: one launch over all faces, atomic adds (Section 1).
+ * DGC_SURF_GATHER: the buffered alternative of Section 1: face j writes its
+ *   left / right contributions to slots 2j, 2j+1 of a workspace of
+ *   2 * n_face * n_var * n_p values (the memory of Table 4), then a second
+ *   kernel adds each element's slots to rhs.
+ * Errors: DGC_E_ARG, DGC_E_NOT_COLORED (COLORED without colors),
+ * DGC_E_WORKSPACE, DGC_E_UNSUPPORTED, DGC_E_HIP (launch failure). */
+dgc_status dgc_surface_rhs(const dgc_dmesh *dm, const void *U, void *rhs, int32_t variant,
+                           int32_t precision, void *ws, size_t ws_bytes, void *stream);
+
+/* One SSP-RK3 step (Shu-Osher form) of U (device f64, updated in place):
+ * three stages of volume term + surface term (`variant`) + combination.
+ * DGC_F32 evaluates both terms on an f32 shadow of the stage state and
+ * accumulates the stages in f64.  ws holds the stage states and the RHS. */
+dgc_status dgc_rk_step(const dgc_dmesh *dm, double *U, double dt, int32_t variant, int32_t precision,
+                       void *ws, size_t ws_bytes, void *stream);
+
+enum { DGC_WS_SURFACE = 0, DGC_WS_RK_STEP = 1 };
+
+/* Workspace size in bytes for dgc_surface_rhs (what = DGC_WS_SURFACE) or
+ * dgc_rk_step (DGC_WS_RK_STEP) with the given variant and precision. */
+dgc_status dgc_workspace_bytes(const dgc_dmesh *dm, int32_t what, int32_t variant, int32_t precision,
+                               size_t *bytes);
+
+/* Library build identification (static string). */
+const char *dgc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DGC_H */

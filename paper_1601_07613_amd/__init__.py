@@ -1,0 +1,207 @@
+"""MI355X-native edge-colored DG surface integrals (Giuliani & Krivodonova, arXiv:1601.07613).
+
+Thin Python binding over ``libdgc.so`` (C ABI in ``include/dgc.h``).  Every
+step of the path runs in the native library: host C++ for the mesh build,
+coloring and layout, HIP kernels for the volume and surface terms and the
+SSP-RK3 stages.  PyTorch only provides device memory and the stream.  There
+is no CPU fallback: if the library is missing the import fails.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import (  # noqa: F401
+    DGC_COLOR_GREEDY_STD, DGC_COLOR_PAPER, DGC_F32, DGC_F64, DGC_LAYOUT_NONE, DGC_LAYOUT_PAPER,
+    DGC_LAYOUT_RENUMBER, DGC_SURF_ATOMIC, DGC_SURF_COLORED, DGC_SURF_GATHER, DGC_TET, DGC_TRI, DgcError,
+)
+
+_L = _lib.load()
+
+VARIANTS = {"colored": DGC_SURF_COLORED, "atomic": DGC_SURF_ATOMIC, "gather": DGC_SURF_GATHER}
+PRECISIONS = {"f64": DGC_F64, "f32": DGC_F32}
+LAYOUTS = {"paper": DGC_LAYOUT_PAPER, "renumber": DGC_LAYOUT_RENUMBER, "none": DGC_LAYOUT_NONE}
+ALGORITHMS = {"paper": DGC_COLOR_PAPER, "greedy": DGC_COLOR_GREEDY_STD}
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class Mesh:
+    """Host mesh owned by the library (face table, geometry, coloring, layout)."""
+
+    def __init__(self, handle: C.c_void_p):
+        self._h = handle
+
+    @classmethod
+    def build(cls, elem_vert, elem_xyz) -> "Mesh":
+        ev = np.ascontiguousarray(elem_vert, dtype=np.int32)
+        xyz = np.ascontiguousarray(elem_xyz, dtype=np.float64)
+        et = DGC_TRI if ev.shape[1] == 3 else DGC_TET
+        h = C.c_void_p()
+        _lib.check(_L.dgc_mesh_build(et, ev.shape[0], _ptr(ev), _ptr(xyz), C.byref(h)), "dgc_mesh_build")
+        return cls(h)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _L.dgc_mesh_free(h)
+            self._h = None
+
+    def color(self, seed: int = 0, max_swaps: int = -1, algorithm: str = "paper", layout: str = "paper") -> dict:
+        st = _lib.ColorStats()
+        flags = ALGORITHMS[algorithm] | LAYOUTS[layout]
+        _lib.check(_L.dgc_color_edges(self._h, seed, max_swaps, flags, C.byref(st)), "dgc_color_edges")
+        return {
+            "conflicts_after_greedy": st.conflicts_after_greedy, "swaps": st.swaps,
+            "loop_breaks": st.loop_breaks, "deferrals": st.deferrals, "n_colors": st.n_colors,
+            "count": list(st.count[: st.n_colors]), "color_ms": st.color_ms, "layout_ms": st.layout_ms,
+        }
+
+    def set_colors(self, colors, layout: str = "paper") -> None:
+        c = np.ascontiguousarray(colors, dtype=np.int8)
+        _lib.check(_L.dgc_set_colors(self._h, _ptr(c), LAYOUTS[layout]), "dgc_set_colors")
+
+    def refine(self, flags) -> tuple["Mesh", int]:
+        f = np.ascontiguousarray(flags, dtype=np.uint8)
+        h = C.c_void_p()
+        ncl = C.c_int64()
+        _lib.check(_L.dgc_mesh_refine(self._h, _ptr(f), C.byref(h), C.byref(ncl)), "dgc_mesh_refine")
+        return Mesh(h), int(ncl.value)
+
+    def info(self) -> dict:
+        i = _lib.MeshInfo()
+        _lib.check(_L.dgc_mesh_info(self._h, C.byref(i)), "dgc_mesh_info")
+        d = {name: getattr(i, name) for name, _ in _lib.MeshInfo._fields_}
+        d["color_off"] = list(i.color_off[: i.n_colors + 1]) if i.n_colors else []
+        return d
+
+    def export(self, name: str) -> np.ndarray:
+        which, dtype = _lib.ARR[name]
+        need = C.c_size_t()
+        _lib.check(_L.dgc_mesh_export(self._h, which, None, 0, C.byref(need)), "dgc_mesh_export")
+        out = np.empty(need.value // np.dtype(dtype).itemsize, dtype=dtype)
+        _lib.check(_L.dgc_mesh_export(self._h, which, _ptr(out), out.nbytes, None), "dgc_mesh_export")
+        return out
+
+
+def tables(elem_type: int, p: int):
+    info = _lib.TableInfo()
+    need = C.c_size_t()
+    _lib.check(_L.dgc_tables(elem_type, p, C.byref(info), None, 0, C.byref(need)), "dgc_tables")
+    out = np.empty(need.value // 8, dtype=np.float64)
+    _lib.check(_L.dgc_tables(elem_type, p, C.byref(info), _ptr(out), out.nbytes, None), "dgc_tables")
+    return {name: getattr(info, name) for name, _ in _lib.TableInfo._fields_}, out
+
+
+def _stream_ptr(stream=None):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class DeviceMesh:
+    """Device-resident arrays of one laid-out mesh at order ``p`` (torch tensors)."""
+
+    def __init__(self, mesh: Mesh, p: int, device="cuda", with_slots: bool = True):
+        import torch
+
+        info = mesh.info()
+        if not info["n_colors"]:
+            raise DgcError(-3, "DeviceMesh", "mesh is not colored")
+        self.mesh = mesh
+        self.p = p
+        self.info = info
+        self.dim = info["dim"]
+        tinfo, tab = tables(info["elem_type"], p)
+        self.tinfo = tinfo
+        self.n_p = tinfo["n_p"]
+        self.n_var = self.dim + 2
+        self.K = info["n_elem"]
+        self.E = info["n_face"]
+        dev = torch.device(device)
+
+        def up(a):
+            return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+        self.face_lr = up(mesh.export("dev_face_lr"))
+        self.face_code = up(mesh.export("dev_face_code"))
+        self.face_geo = up(mesh.export("dev_face_geo"))
+        self.elem_geo = up(mesh.export("dev_elem_geo"))
+        self.elem_slots = up(mesh.export("dev_elem_slots")) if with_slots else None
+        self.tables = up(tab)
+        self.elem_new = mesh.export("elem_new").astype(np.int64)
+        dm = _lib.DMesh()
+        dm.elem_type = info["elem_type"]
+        dm.p = p
+        dm.n_p = tinfo["n_p"]
+        dm.n_var = self.n_var
+        dm.n_qf = tinfo["n_qf"]
+        dm.n_qv = tinfo["n_qv"]
+        dm.n_codes = tinfo["n_codes"]
+        dm.n_orient = tinfo["n_orient"]
+        dm.n_colors = info["n_colors"]
+        dm.max_slots = info["max_slots"]
+        dm.n_elem = self.K
+        dm.n_face = self.E
+        for c, v in enumerate(info["color_off"]):
+            dm.color_off[c] = v
+        dm.face_lr = self.face_lr.data_ptr()
+        dm.face_code = self.face_code.data_ptr()
+        dm.face_geo = self.face_geo.data_ptr()
+        dm.elem_geo = self.elem_geo.data_ptr()
+        dm.elem_slots = self.elem_slots.data_ptr() if self.elem_slots is not None else None
+        dm.tables = self.tables.data_ptr()
+        self.dm = dm
+
+    # -- DOF permutation between original element ids and layout ids --------
+    def to_layout(self, U: np.ndarray) -> np.ndarray:
+        out = np.empty_like(U)
+        out[self.elem_new] = U
+        return out
+
+    def from_layout(self, Ul: np.ndarray) -> np.ndarray:
+        return Ul[self.elem_new]
+
+    def alloc(self, precision: str = "f64", zero: bool = True):
+        import torch
+
+        dt = torch.float64 if precision == "f64" else torch.float32
+        shape = (self.K, self.n_var, self.n_p)
+        return torch.zeros(shape, dtype=dt, device=self.face_lr.device) if zero else torch.empty(
+            shape, dtype=dt, device=self.face_lr.device)
+
+    def workspace_bytes(self, what: str = "surface", variant: str = "colored", precision: str = "f64") -> int:
+        b = C.c_size_t()
+        w = _lib.DGC_WS_SURFACE if what == "surface" else _lib.DGC_WS_RK_STEP
+        _lib.check(_L.dgc_workspace_bytes(C.byref(self.dm), w, VARIANTS[variant], PRECISIONS[precision], C.byref(b)),
+                   "dgc_workspace_bytes")
+        return int(b.value)
+
+    def workspace(self, what: str = "surface", variant: str = "colored", precision: str = "f64"):
+        import torch
+
+        n = self.workspace_bytes(what, variant, precision)
+        return torch.empty(max(n, 1), dtype=torch.uint8, device=self.face_lr.device)
+
+    def volume_rhs(self, U, rhs, precision: str = "f64", stream=None):
+        _lib.check(_L.dgc_volume_rhs(C.byref(self.dm), U.data_ptr(), rhs.data_ptr(), PRECISIONS[precision],
+                                     _stream_ptr(stream)), "dgc_volume_rhs")
+
+    def surface_rhs(self, U, rhs, variant: str = "colored", precision: str = "f64", ws=None, stream=None):
+        wp = ws.data_ptr() if ws is not None else None
+        wb = ws.numel() * ws.element_size() if ws is not None else 0
+        _lib.check(_L.dgc_surface_rhs(C.byref(self.dm), U.data_ptr(), rhs.data_ptr(), VARIANTS[variant],
+                                      PRECISIONS[precision], wp, wb, _stream_ptr(stream)), "dgc_surface_rhs")
+
+    def rk_step(self, U, dt: float, variant: str = "colored", precision: str = "f64", ws=None, stream=None):
+        if ws is None:
+            ws = self.workspace("rk", variant, precision)
+        _lib.check(_L.dgc_rk_step(C.byref(self.dm), U.data_ptr(), float(dt), VARIANTS[variant],
+                                  PRECISIONS[precision], ws.data_ptr(), ws.numel(), _stream_ptr(stream)),
+                   "dgc_rk_step")

@@ -1,0 +1,264 @@
+// Basis and quadrature tables for the device kernels.
+//
+// Basis: orthonormal Dubiner polynomials on the unit triangle / tetrahedron
+// (the paper's Eq. 2 needs an orthonormal modal basis; the family is this
+// project's reading), evaluated in collapsed coordinates with normalised
+// Jacobi polynomials; gradients by the chain rule through the collapsed map.
+// Quadrature: Gauss-Jacobi nodes by Newton's method with deflation on the
+// Jacobi polynomial, weights by the Christoffel formula
+//   w_k = 2^(a+b+1) G(n+a+1) G(n+b+1) / (G(n+a+b+1) n!) / ((1-x_k^2) P_n'(x_k)^2).
+#include <cmath>
+
+#include "internal.hpp"
+
+namespace dgc {
+
+namespace {
+
+const double kPi = 3.14159265358979323846;
+
+// P_n^(a,b)(x) and its derivative
+void jacobi_pd(int n, double a, double b, double x, double *P, double *dP) {
+    // value by the three-term recurrence
+    auto val = [](int nn, double al, double be, double xx) {
+        double p0 = 1.0;
+        if (nn == 0) return p0;
+        double p1 = 0.5 * ((al + be + 2.0) * xx + (al - be));
+        for (int k = 1; k < nn; ++k) {
+            double c = 2.0 * k + al + be;
+            double num = (c + 1.0) * ((c + 2.0) * c * xx + al * al - be * be) * p1 - 2.0 * (k + al) * (k + be) * (c + 2.0) * p0;
+            double den = 2.0 * (k + 1) * (k + al + be + 1.0) * c;
+            p0 = p1;
+            p1 = num / den;
+        }
+        return p1;
+    };
+    *P = val(n, a, b, x);
+    *dP = n == 0 ? 0.0 : 0.5 * (n + a + b + 1.0) * val(n - 1, a + 1.0, b + 1.0, x);
+}
+
+double jacobi_h(int n, double a, double b) {  // squared norm
+    return std::pow(2.0, a + b + 1.0) / (2.0 * n + a + b + 1.0) * std::tgamma(n + a + 1.0) * std::tgamma(n + b + 1.0) /
+           (std::tgamma(n + a + b + 1.0) * std::tgamma(n + 1.0));
+}
+
+// normalised Jacobi value and derivative
+void pnorm(int n, double a, double b, double x, double *v, double *d) {
+    double P, dP;
+    jacobi_pd(n, a, b, x, &P, &dP);
+    double s = 1.0 / std::sqrt(jacobi_h(n, a, b));
+    *v = P * s;
+    *d = dP * s;
+}
+
+void gauss_jacobi(int n, double a, double b, std::vector<double> &x, std::vector<double> &w) {
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int k = 0; k < n; ++k) {
+        // Chebyshev-like initial guess, averaged with the previous root
+        double r = -std::cos((2.0 * k + 1.0) * kPi / (2.0 * n));
+        if (k > 0) r = 0.5 * (r + x[k - 1]);
+        for (int it = 0; it < 200; ++it) {
+            double P, dP;
+            jacobi_pd(n, a, b, r, &P, &dP);
+            double s = 0.0;
+            for (int i = 0; i < k; ++i) s += 1.0 / (r - x[i]);
+            double delta = P / (dP - s * P);
+            r -= delta;
+            if (std::fabs(delta) < 1e-16) break;
+        }
+        x[k] = r;
+    }
+    double c = std::pow(2.0, a + b + 1.0) * std::tgamma(n + a + 1.0) * std::tgamma(n + b + 1.0) /
+               (std::tgamma(n + a + b + 1.0) * std::tgamma(n + 1.0));
+    for (int k = 0; k < n; ++k) {
+        double P, dP;
+        jacobi_pd(n, a, b, x[k], &P, &dP);
+        w[k] = c / ((1.0 - x[k] * x[k]) * dP * dP);
+    }
+}
+
+int nmodes(int dim, int p) { return dim == 2 ? (p + 1) * (p + 2) / 2 : (p + 1) * (p + 2) * (p + 3) / 6; }
+
+// value and reference gradient of every mode at a point of the unit element
+void dubiner(int dim, int p, const double *xi, double *phi, double *grad /* [dim][Np] or null */) {
+    const int np = nmodes(dim, p);
+    int m = 0;
+    if (dim == 2) {
+        double r = 2.0 * xi[0] - 1.0, s = 2.0 * xi[1] - 1.0;
+        double one_s = 1.0 - s;
+        double a = std::fabs(one_s) > 1e-15 ? 2.0 * (1.0 + r) / one_s - 1.0 : -1.0;
+        double b = s;
+        const double C = 2.0 * std::sqrt(2.0);
+        for (int d = 0; d <= p; ++d) {
+            for (int j = 0; j <= d; ++j) {
+                int i = d - j;
+                double fa, dfa, gb, dgb;
+                pnorm(i, 0.0, 0.0, a, &fa, &dfa);
+                pnorm(j, 2.0 * i + 1.0, 0.0, b, &gb, &dgb);
+                double w = std::pow(1.0 - b, i);
+                double g = gb * w;
+                double dg = dgb * w - (i > 0 ? i * gb * std::pow(1.0 - b, i - 1) : 0.0);
+                phi[m] = C * fa * g;
+                if (grad) {
+                    double dr = C * dfa * g * 2.0 / (1.0 - b);
+                    double ds = C * (dfa * g * (1.0 + a) / (1.0 - b) + fa * dg);
+                    grad[0 * np + m] = 2.0 * dr;
+                    grad[1 * np + m] = 2.0 * ds;
+                }
+                ++m;
+            }
+        }
+        return;
+    }
+    double r = 2.0 * xi[0] - 1.0, s = 2.0 * xi[1] - 1.0, t = 2.0 * xi[2] - 1.0;
+    double st = s + t;
+    double a = std::fabs(st) > 1e-15 ? -2.0 * (1.0 + r) / st - 1.0 : -1.0;
+    double b = std::fabs(1.0 - t) > 1e-15 ? 2.0 * (1.0 + s) / (1.0 - t) - 1.0 : -1.0;
+    double c = t;
+    const double C = 8.0;  // sqrt(8) (unit element) x 2 sqrt(2) (biunit normalisation)
+    double da_dr = -2.0 / st, da_ds = 2.0 * (1.0 + r) / (st * st), da_dt = da_ds;
+    double db_ds = 2.0 / (1.0 - t), db_dt = 2.0 * (1.0 + s) / ((1.0 - t) * (1.0 - t));
+    for (int d = 0; d <= p; ++d) {
+        for (int k = 0; k <= d; ++k) {
+            for (int j = 0; j <= d - k; ++j) {
+                int i = d - j - k;
+                double fa, dfa, gb, dgb, hc, dhc;
+                pnorm(i, 0.0, 0.0, a, &fa, &dfa);
+                pnorm(j, 2.0 * i + 1.0, 0.0, b, &gb, &dgb);
+                pnorm(k, 2.0 * i + 2.0 * j + 2.0, 0.0, c, &hc, &dhc);
+                double wb = std::pow(1.0 - b, i), wc = std::pow(1.0 - c, i + j);
+                double g = gb * wb, h = hc * wc;
+                double dg = dgb * wb - (i > 0 ? i * gb * std::pow(1.0 - b, i - 1) : 0.0);
+                double dh = dhc * wc - (i + j > 0 ? (i + j) * hc * std::pow(1.0 - c, i + j - 1) : 0.0);
+                phi[m] = C * fa * g * h;
+                if (grad) {
+                    double dr = C * dfa * g * h * da_dr;
+                    double ds = C * (dfa * g * h * da_ds + fa * dg * h * db_ds);
+                    double dt = C * (dfa * g * h * da_dt + fa * dg * h * db_dt + fa * g * dh);
+                    grad[0 * np + m] = 2.0 * dr;
+                    grad[1 * np + m] = 2.0 * ds;
+                    grad[2 * np + m] = 2.0 * dt;
+                }
+                ++m;
+            }
+        }
+    }
+}
+
+const double kRefTri[3][2] = {{0, 0}, {1, 0}, {0, 1}};
+const double kRefTet[4][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+const int kTriEdge[3][2] = {{0, 1}, {1, 2}, {2, 0}};
+const int kTetFace[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
+const int kPerm3[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+
+}  // namespace
+
+dgc_status build_tables(int32_t elem_type, int p, dgc_table_info *info, std::vector<double> *out) {
+    if (elem_type != DGC_TRI && elem_type != DGC_TET) return fail(DGC_E_ARG, "unknown element type");
+    const int dim = elem_type == DGC_TRI ? 2 : 3;
+    if (p < 0 || (dim == 2 && p > 5) || (dim == 3 && p > 1))
+        return fail(DGC_E_UNSUPPORTED, "order p=" + std::to_string(p) + " is not supported for this element");
+    dgc_table_info ti{};
+    ti.elem_type = elem_type;
+    ti.p = p;
+    ti.dim = dim;
+    ti.n_p = nmodes(dim, p);
+    const int n = p + 1;
+    ti.n_qv = dim == 2 ? n * n : n * n * n;
+    ti.n_qf = dim == 2 ? p + 1 : 3;
+    ti.n_orient = dim == 2 ? 4 : 6;
+    const int nfaces = dim == 2 ? 3 : 4;
+    ti.n_codes = nfaces * ti.n_orient;
+    const int np = ti.n_p, qf = ti.n_qf, qv = ti.n_qv;
+    ti.off_trace = 0;
+    ti.off_proj = ti.off_trace + (int64_t)ti.n_codes * qf * np;
+    ti.off_vb = ti.off_proj + (int64_t)ti.n_codes * qf * np;
+    ti.off_vd = ti.off_vb + (int64_t)qv * np;
+    ti.total = ti.off_vd + (int64_t)dim * qv * np;
+    if (info) *info = ti;
+    if (!out) return DGC_OK;
+    out->assign(ti.total, 0.0);
+    double *T = out->data();
+
+    // face rule
+    std::vector<double> fs, fw;
+    if (dim == 2) {
+        gauss_jacobi(qf, 0.0, 0.0, fs, fw);
+        for (int q = 0; q < qf; ++q) {
+            fs[q] = 0.5 * (fs[q] + 1.0);
+            fw[q] *= 0.5;
+        }
+    } else {
+        fw.assign(3, 1.0 / 3.0);
+    }
+    std::vector<double> phi(np), grad(dim * np);
+    for (int f = 0; f < nfaces; ++f) {
+        for (int o = 0; o < ti.n_orient; ++o) {
+            const int code = f * ti.n_orient + o;
+            for (int q = 0; q < qf; ++q) {
+                double xi[3] = {0, 0, 0};
+                if (dim == 2) {
+                    double t;
+                    switch (o) {
+                        case 0: t = fs[q]; break;
+                        case 1: t = 1.0 - fs[q]; break;
+                        case 2: t = 0.5 - 0.5 * fs[q]; break;
+                        default: t = 1.0 - 0.5 * fs[q]; break;
+                    }
+                    const double *A = kRefTri[kTriEdge[f][0]], *B = kRefTri[kTriEdge[f][1]];
+                    xi[0] = A[0] + t * (B[0] - A[0]);
+                    xi[1] = A[1] + t * (B[1] - A[1]);
+                } else {
+                    int cq = kPerm3[o][q];  // canonical point of this face seen by point q
+                    for (int v = 0; v < 3; ++v) {
+                        double bw = v == cq ? 2.0 / 3.0 : 1.0 / 6.0;
+                        const double *V = kRefTet[kTetFace[f][v]];
+                        for (int e = 0; e < 3; ++e) xi[e] += bw * V[e];
+                    }
+                }
+                dubiner(dim, p, xi, phi.data(), nullptr);
+                for (int j = 0; j < np; ++j) {
+                    T[ti.off_trace + ((int64_t)code * qf + q) * np + j] = phi[j];
+                    T[ti.off_proj + ((int64_t)code * qf + q) * np + j] = fw[q] * phi[j];
+                }
+            }
+        }
+    }
+
+    // volume rule: collapsed Gauss-Jacobi product
+    std::vector<double> xa, wa, xb, wb, xc, wc;
+    gauss_jacobi(n, 0.0, 0.0, xa, wa);
+    gauss_jacobi(n, 1.0, 0.0, xb, wb);
+    if (dim == 3) gauss_jacobi(n, 2.0, 0.0, xc, wc);
+    int q = 0;
+    auto put = [&](const double *xi, double w) {
+        dubiner(dim, p, xi, phi.data(), grad.data());
+        for (int j = 0; j < np; ++j) {
+            T[ti.off_vb + (int64_t)q * np + j] = phi[j];
+            for (int d = 0; d < dim; ++d) T[ti.off_vd + ((int64_t)d * qv + q) * np + j] = w * grad[d * np + j];
+        }
+        ++q;
+    };
+    if (dim == 2) {
+        for (int i = 0; i < n; ++i)
+            for (int k = 0; k < n; ++k) {
+                double r = 0.5 * (1.0 + xa[i]) * (1.0 - xb[k]) - 1.0, s = xb[k];
+                double xi[2] = {0.5 * (1.0 + r), 0.5 * (1.0 + s)};
+                put(xi, wa[i] * wb[k] / 8.0);
+            }
+    } else {
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j)
+                for (int k = 0; k < n; ++k) {
+                    double r = 0.25 * (1.0 + xa[i]) * (1.0 - xb[j]) * (1.0 - xc[k]) - 1.0;
+                    double s = 0.5 * (1.0 + xb[j]) * (1.0 - xc[k]) - 1.0;
+                    double t = xc[k];
+                    double xi[3] = {0.5 * (1.0 + r), 0.5 * (1.0 + s), 0.5 * (1.0 + t)};
+                    put(xi, wa[i] * wb[j] * wc[k] / 64.0);
+                }
+    }
+    return DGC_OK;
+}
+
+}  // namespace dgc

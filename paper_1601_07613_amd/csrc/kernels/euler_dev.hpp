@@ -1,0 +1,82 @@
+// Device-side Euler physics: Rusanov flux along a unit normal and the
+// reflective-wall mirror state.  Ideal gas, gamma = 1.4, conserved variables
+// (rho, rho u[, rho v[, rho w]], E).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace dgc_dev {
+
+constexpr double kGamma = 1.4;
+
+template <class T>
+__device__ __forceinline__ T dev_sqrt(T x);
+template <>
+__device__ __forceinline__ double dev_sqrt<double>(double x) { return __builtin_sqrt(x); }
+template <>
+__device__ __forceinline__ float dev_sqrt<float>(float x) { return __builtin_sqrtf(x); }
+
+// F*(uL, uR, n) = (F(uL).n + F(uR).n)/2 - lambda (uR - uL)/2,
+// lambda = max(|uL.n| + cL, |uR.n| + cR), c = sqrt(gamma p / rho).
+template <int DIM, class T>
+__device__ __forceinline__ void rusanov(const T *uL, const T *uR, const T *n, T *F) {
+    constexpr int M = DIM + 2;
+    const T g1 = T(kGamma - 1.0);
+    const T irl = T(1) / uL[0], irr = T(1) / uR[0];
+    T unl = 0, unr = 0, kel = 0, ker = 0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        unl += uL[1 + d] * n[d];
+        unr += uR[1 + d] * n[d];
+        kel += uL[1 + d] * uL[1 + d];
+        ker += uR[1 + d] * uR[1 + d];
+    }
+    unl *= irl;
+    unr *= irr;
+    const T pl = g1 * (uL[M - 1] - T(0.5) * kel * irl);
+    const T pr = g1 * (uR[M - 1] - T(0.5) * ker * irr);
+    const T cl = dev_sqrt<T>(T(kGamma) * pl * irl);
+    const T cr = dev_sqrt<T>(T(kGamma) * pr * irr);
+    const T al = (unl < 0 ? -unl : unl) + cl;
+    const T ar = (unr < 0 ? -unr : unr) + cr;
+    const T lam = al > ar ? al : ar;
+    F[0] = T(0.5) * (uL[0] * unl + uR[0] * unr) - T(0.5) * lam * (uR[0] - uL[0]);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d)
+        F[1 + d] = T(0.5) * (uL[1 + d] * unl + uR[1 + d] * unr + (pl + pr) * n[d]) - T(0.5) * lam * (uR[1 + d] - uL[1 + d]);
+    F[M - 1] = T(0.5) * ((uL[M - 1] + pl) * unl + (uR[M - 1] + pr) * unr) - T(0.5) * lam * (uR[M - 1] - uL[M - 1]);
+}
+
+// mirror state across a wall: momentum reflected, density and energy kept
+template <int DIM, class T>
+__device__ __forceinline__ void wall_ghost(const T *u, const T *n, T *g) {
+    constexpr int M = DIM + 2;
+    T mn = 0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) mn += u[1 + d] * n[d];
+    g[0] = u[0];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) g[1 + d] = u[1 + d] - T(2) * mn * n[d];
+    g[M - 1] = u[M - 1];
+}
+
+// physical flux F(u) in direction e for all variables: out[m]
+template <int DIM, class T>
+__device__ __forceinline__ void phys_flux(const T *u, T *Fx /* [M][DIM] */) {
+    constexpr int M = DIM + 2;
+    const T ir = T(1) / u[0];
+    T ke = 0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) ke += u[1 + d] * u[1 + d];
+    const T p = T(kGamma - 1.0) * (u[M - 1] - T(0.5) * ke * ir);
+#pragma unroll
+    for (int e = 0; e < DIM; ++e) {
+        const T ve = u[1 + e] * ir;
+        Fx[0 * DIM + e] = u[1 + e];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) Fx[(1 + d) * DIM + e] = u[1 + d] * ve + (d == e ? p : T(0));
+        Fx[(M - 1) * DIM + e] = (u[M - 1] + p) * ve;
+    }
+}
+
+}  // namespace dgc_dev

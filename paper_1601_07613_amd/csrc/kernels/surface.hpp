@@ -1,0 +1,177 @@
+// Surface term of Eq. (2): one work-item per face.
+//
+// For a face with left element L and right element R (layout ids), unit
+// normal n (L -> R), measure |f| and the reciprocal square roots of the two
+// Jacobian determinants, the work-item
+//   1. evaluates both traces at the face quadrature points,
+//        u_X(q) = (1/sqrt(det J_X)) sum_j trace[code_X][q][j] c_X[m][j],
+//      the right trace being the mirror state on a wall;
+//   2. evaluates the Rusanov flux F*_q along n at every point;
+//   3. projects:  delta_X[m][j] = |f| / sqrt(det J_X) sum_q proj[code_X][q][j] F*_q[m]
+//      and applies rhs[L] -= delta_L, rhs[R] += delta_R.
+// MODE selects how step 3 reaches memory:
+//   kColored  plain read-modify-write; the caller launches one color at a
+//             time (Algorithm 1), so no two work-items of a launch touch the
+//             same element;
+//   kAtomic   hardware floating-point atomic adds, all faces in one launch;
+//   kGather   writes -delta_L / +delta_R to buffer slots 2k / 2k+1 of face
+//             position k; a second kernel sums each element's slots.
+// The basis tables of all face codes are staged once per work-group in LDS.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "euler_dev.hpp"
+
+namespace dgc_dev {
+
+enum { kColored = 0, kAtomic = 1, kGather = 2 };
+
+template <class T>
+__device__ __forceinline__ void atomic_add(T *addr, T v) {
+    unsafeAtomicAdd(addr, v);
+}
+
+template <int DIM, int NP, int Q, int MODE, class T>
+__global__ __launch_bounds__(256) void surface_kernel(
+    int64_t f_begin, int64_t f_end, int64_t n_face, int64_t n_elem,
+    const int32_t *__restrict__ face_lr, const uint8_t *__restrict__ face_code,
+    const double *__restrict__ face_geo, const double *__restrict__ tab_trace,
+    const double *__restrict__ tab_proj, int n_codes,
+    const T *__restrict__ U, T *__restrict__ rhs, T *__restrict__ buf) {
+    constexpr int M = DIM + 2;
+    constexpr int REC = M * NP;
+    extern __shared__ unsigned char smem_raw[];
+    T *s_tr = reinterpret_cast<T *>(smem_raw);
+    T *s_pr = s_tr + n_codes * Q * NP;
+    const int ntab = n_codes * Q * NP;
+    for (int i = threadIdx.x; i < ntab; i += blockDim.x) {
+        s_tr[i] = T(tab_trace[i]);
+        s_pr[i] = T(tab_proj[i]);
+    }
+    __syncthreads();
+
+    const int64_t k = f_begin + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= f_end) return;
+
+    const int32_t L = face_lr[k];
+    const int32_t R = face_lr[n_face + k];
+    const int cL = face_code[k];
+    const int cR = face_code[n_face + k];
+    // a malformed face (ids or codes out of range) is skipped, never dereferenced
+    if (L < 0 || L >= n_elem || R >= n_elem || cL >= n_codes || cR >= n_codes) return;
+    T n[DIM];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) n[d] = T(face_geo[d * n_face + k]);
+    const double len = face_geo[DIM * n_face + k];
+    const double isL = face_geo[(DIM + 1) * n_face + k];
+    const double isR = face_geo[(DIM + 2) * n_face + k];
+
+    // traces at the face points
+    T qL[Q][M], qR[Q][M];
+    {
+        const T *uL = U + (size_t)L * REC;
+        const T *tl = s_tr + cL * Q * NP;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            T c[NP];
+#pragma unroll
+            for (int j = 0; j < NP; ++j) c[j] = uL[m * NP + j];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                T a = 0;
+#pragma unroll
+                for (int j = 0; j < NP; ++j) a += tl[q * NP + j] * c[j];
+                qL[q][m] = a * T(isL);
+            }
+        }
+    }
+    if (R >= 0) {
+        const T *uR = U + (size_t)R * REC;
+        const T *tr = s_tr + cR * Q * NP;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            T c[NP];
+#pragma unroll
+            for (int j = 0; j < NP; ++j) c[j] = uR[m * NP + j];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                T a = 0;
+#pragma unroll
+                for (int j = 0; j < NP; ++j) a += tr[q * NP + j] * c[j];
+                qR[q][m] = a * T(isR);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) wall_ghost<DIM, T>(qL[q], n, qR[q]);
+    }
+
+    // numerical flux at every point
+    T Fs[Q][M];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) rusanov<DIM, T>(qL[q], qR[q], n, Fs[q]);
+
+    // projection and accumulation, left side
+    {
+        const T sL = T(len * isL);
+        const T *pl = s_pr + cL * Q * NP;
+        T *dst = MODE == kGather ? buf + (size_t)(2 * k) * REC : rhs + (size_t)L * REC;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+#pragma unroll
+            for (int j = 0; j < NP; ++j) {
+                T a = 0;
+#pragma unroll
+                for (int q = 0; q < Q; ++q) a += pl[q * NP + j] * Fs[q][m];
+                a *= sL;
+                if (MODE == kColored) dst[m * NP + j] -= a;
+                else if (MODE == kAtomic) atomic_add<T>(dst + m * NP + j, -a);
+                else dst[m * NP + j] = -a;
+            }
+        }
+    }
+    if (R >= 0) {
+        const T sR = T(len * isR);
+        const T *pr = s_pr + cR * Q * NP;
+        T *dst = MODE == kGather ? buf + (size_t)(2 * k + 1) * REC : rhs + (size_t)R * REC;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+#pragma unroll
+            for (int j = 0; j < NP; ++j) {
+                T a = 0;
+#pragma unroll
+                for (int q = 0; q < Q; ++q) a += pr[q * NP + j] * Fs[q][m];
+                a *= sR;
+                if (MODE == kColored) dst[m * NP + j] += a;
+                else if (MODE == kAtomic) atomic_add<T>(dst + m * NP + j, a);
+                else dst[m * NP + j] = a;
+            }
+        }
+    }
+}
+
+// Second pass of the buffered variant: rhs[k] += sum of element k's slots.
+template <int DIM, int NP, class T>
+__global__ __launch_bounds__(256) void gather_kernel(int64_t n_elem, int max_slots, int64_t n_slots_total,
+                                                     const int32_t *__restrict__ elem_slots,
+                                                     const T *__restrict__ buf, T *__restrict__ rhs) {
+    constexpr int REC = (DIM + 2) * NP;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_elem) return;
+    T acc[REC];
+    T *dst = rhs + (size_t)k * REC;
+#pragma unroll
+    for (int i = 0; i < REC; ++i) acc[i] = dst[i];
+    for (int s = 0; s < max_slots; ++s) {
+        const int32_t slot = elem_slots[(int64_t)s * n_elem + k];
+        if (slot < 0 || slot >= n_slots_total) continue;
+        const T *src = buf + (size_t)slot * REC;
+#pragma unroll
+        for (int i = 0; i < REC; ++i) acc[i] += src[i];
+    }
+#pragma unroll
+    for (int i = 0; i < REC; ++i) dst[i] = acc[i];
+}
+
+}  // namespace dgc_dev

@@ -1,0 +1,244 @@
+"""HIP kernels (through the C ABI) against the CPU oracle on the same seeded inputs.
+
+Tolerance (float64): for every conserved variable m,
+    max |gpu - oracle| <= 1e-12 * max |contribution sums| of that variable,
+where the scale is the oracle's sum of absolute per-face (surface) or
+per-point (volume) contributions, so cancellation cannot hide an error.
+Integer outputs (layouts) are compared exactly in test_host_parity.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import dg
+from oracle.mesh import build_mesh
+from tests.helpers import make_input
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _dgc():
+    import paper_1601_07613_amd as dgc
+
+    return dgc
+
+
+def _states(m, K):
+    cen = synth.element_centroid(m["elem_xyz"])
+    if m["elem_xyz"].shape[2] == 3:
+        return synth.density_wave_states(cen)
+    return synth.shock_tube_states(cen)
+
+
+class Case:
+    def __init__(self, kind, size, seed, p, cseed=0, eps=0.02):
+        import torch
+
+        dgc = _dgc()
+        m = make_input(kind, size, seed)
+        self.m = m
+        self.O = build_mesh(m["elem_vert"], m["elem_xyz"])
+        self.d = dg.Discretization(self.O, p)
+        self.M = dgc.Mesh.build(m["elem_vert"], m["elem_xyz"])
+        self.stats = self.M.color(seed=cseed)
+        self.D = dgc.DeviceMesh(self.M, p)
+        self.U = synth.perturbed_dofs(self.O.elem_measure, _states(m, self.O.K), self.d.n_p, eps=eps, seed=seed + 100)
+        self.Ug = torch.from_numpy(self.D.to_layout(self.U)).cuda()
+        print("case", kind, size, seed, "p", p, "K", self.O.K, "E", self.O.E, flush=True)
+
+    def surface(self, variant, rhs0=None, D=None):
+        import torch
+
+        D = D or self.D
+        rhs = torch.zeros_like(self.Ug) if rhs0 is None else rhs0.clone()
+        ws = D.workspace("surface", variant) if variant == "gather" else None
+        D.surface_rhs(self.Ug, rhs, variant=variant, ws=ws)
+        torch.cuda.synchronize()
+        return rhs
+
+    def to_host(self, t):
+        return self.D.from_layout(t.cpu().numpy())
+
+
+def _check(got, ref, scale, what):
+    s = np.asarray(scale).max(axis=(0, 2))
+    err = np.abs(got - ref).max(axis=(0, 2)) / s
+    assert err.max() <= TOL, "%s: relative error per variable %s" % (what, err)
+
+
+def _volume_abs(d, U):
+    from oracle import euler
+
+    mesh = d.mesh
+    sq = np.sqrt(mesh.detJ)
+    Uq = np.einsum("qj,kmj->kqm", d.vol_B, U) / sq[:, None, None]
+    Fq = euler.physical_flux(Uq)
+    G = np.abs(np.einsum("kde,kqme->kqmd", mesh.Jinv, Fq))
+    return np.einsum("q,qdj,kqmd->kmj", d.vol_w, np.abs(d.vol_D), G) * sq[:, None, None]
+
+
+@pytest.mark.parametrize("p", [0, 1, 2, 3])
+@pytest.mark.parametrize("variant", ["colored", "atomic", "gather"])
+def test_surface_periodic_triangles(p, variant):
+    c = Case("periodic", 16, 1, p)
+    got = c.to_host(c.surface(variant))
+    _check(got, dg.surface_rhs(c.d, c.U), dg.surface_abs(c.d, c.U), "surface %s p=%d" % (variant, p))
+
+
+@pytest.mark.parametrize("variant", ["colored", "atomic", "gather"])
+def test_surface_delaunay_walls_ragged(variant):
+    c = Case("delaunay", 12000, 2, 2)
+    assert c.O.E % 256 != 0 and c.O.n_boundary > 0
+    got = c.to_host(c.surface(variant))
+    _check(got, dg.surface_rhs(c.d, c.U), dg.surface_abs(c.d, c.U), "surface delaunay " + variant)
+
+
+@pytest.mark.parametrize("p", [0, 1])
+@pytest.mark.parametrize("variant", ["colored", "atomic", "gather"])
+def test_surface_tets(p, variant):
+    c = Case("tets", 6, 3, p)
+    assert c.stats["n_colors"] == 4
+    got = c.to_host(c.surface(variant))
+    _check(got, dg.surface_rhs(c.d, c.U), dg.surface_abs(c.d, c.U), "surface tets %s p=%d" % (variant, p))
+
+
+@pytest.mark.parametrize("kind,size,p", [("periodic", 16, 0), ("periodic", 16, 1), ("periodic", 16, 2),
+                                         ("periodic", 16, 3), ("delaunay", 6000, 2), ("tets", 5, 0),
+                                         ("tets", 5, 1)])
+def test_volume(kind, size, p):
+    import torch
+
+    c = Case(kind, size, 4, p)
+    rhs = torch.full_like(c.Ug, 7.0)  # overwritten by the kernel
+    c.D.volume_rhs(c.Ug, rhs)
+    torch.cuda.synchronize()
+    _check(c.to_host(rhs), dg.volume_rhs(c.d, c.U), _volume_abs(c.d, c.U), "volume %s p=%d" % (kind, p))
+
+
+def test_surface_accumulates_onto_volume_term():
+    import torch
+
+    c = Case("periodic", 16, 5, 2)
+    rhs = torch.zeros_like(c.Ug)
+    c.D.volume_rhs(c.Ug, rhs)
+    out = c.surface("colored", rhs0=rhs)
+    ref = dg.rhs(c.d, c.U)
+    scale = dg.surface_abs(c.d, c.U) + _volume_abs(c.d, c.U)
+    _check(c.to_host(out), ref, scale, "volume + surface")
+
+
+def test_colored_is_race_free_and_bitwise_deterministic():
+    """Permuting the faces inside every color cannot change a single bit of the
+    colored result (each element is touched once per color), and two runs agree."""
+    import torch
+
+    c = Case("delaunay", 8000, 6, 2)
+    a = c.surface("colored")
+    b = c.surface("colored")
+    assert torch.equal(a, b)
+    D = c.D
+    off = D.info["color_off"]
+    rng = np.random.default_rng(0)
+    perm = np.concatenate([off[k] + rng.permutation(off[k + 1] - off[k]) for k in range(len(off) - 1)])
+    pt = torch.from_numpy(perm).cuda()
+    E = D.E
+    saved = (D.face_lr, D.face_code, D.face_geo)
+    D.face_lr = D.face_lr.view(2, E)[:, pt].contiguous().view(-1)
+    D.face_code = D.face_code.view(2, E)[:, pt].contiguous().view(-1)
+    D.face_geo = D.face_geo.view(-1, E)[:, pt].contiguous().view(-1)
+    D.dm.face_lr, D.dm.face_code, D.dm.face_geo = D.face_lr.data_ptr(), D.face_code.data_ptr(), D.face_geo.data_ptr()
+    try:
+        p = c.surface("colored")
+    finally:
+        D.face_lr, D.face_code, D.face_geo = saved
+        D.dm.face_lr, D.dm.face_code, D.dm.face_geo = (D.face_lr.data_ptr(), D.face_code.data_ptr(),
+                                                       D.face_geo.data_ptr())
+    assert torch.equal(a, p)
+
+
+def test_empty_color_and_tiny_mesh():
+    import torch
+
+    dgc = _dgc()
+    # a valid coloring whose color 2 is empty (colors 0, 1, 3)
+    c = Case("periodic", 6, 7, 1)
+    col = c.M.export("color").astype(np.int8)
+    col[col == 2] = 3
+    c.M.set_colors(col)
+    D = dgc.DeviceMesh(c.M, 1)
+    assert D.info["n_colors"] == 4 and D.info["color_off"][2] == D.info["color_off"][3]
+    Ug = torch.from_numpy(D.to_layout(c.U)).cuda()
+    rhs = torch.zeros_like(Ug)
+    D.surface_rhs(Ug, rhs)
+    torch.cuda.synchronize()
+    _check(D.from_layout(rhs.cpu().numpy()), dg.surface_rhs(c.d, c.U), dg.surface_abs(c.d, c.U), "empty color")
+    # smallest periodic mesh the generator makes: 3 x 3 x 2 triangles
+    t = Case("periodic", 3, 8, 2)
+    _check(t.to_host(t.surface("colored")), dg.surface_rhs(t.d, t.U), dg.surface_abs(t.d, t.U), "tiny mesh")
+
+
+def test_rk3_100_steps_vortex():
+    """16 x 16 periodic p = 1 isentropic vortex, 100 SSP-RK3 steps at CFL 0.1."""
+    import torch
+
+    m = make_input("periodic", 16, 1)
+    O = build_mesh(m["elem_vert"], m["elem_xyz"])
+    d = dg.Discretization(O, 1)
+    U0 = dg.project(d, lambda X: synth.isentropic_vortex(X, 0.0))
+    dt = dg.cfl_dt(d, U0, 0.1)
+    dgc = _dgc()
+    M = dgc.Mesh.build(m["elem_vert"], m["elem_xyz"])
+    M.color(seed=1)
+    D = dgc.DeviceMesh(M, 1)
+    Ug = torch.from_numpy(D.to_layout(U0)).cuda()
+    ws = D.workspace("rk", "colored")
+    U = U0.copy()
+    for _ in range(100):
+        D.rk_step(Ug, dt, ws=ws)
+        U = dg.rk3_step(d, U, dt)
+    torch.cuda.synchronize()
+    got = D.from_layout(Ug.cpu().numpy())
+    err = np.abs(got - U).max() / np.abs(U).max()
+    assert err <= TOL, err
+
+
+def test_workspace_errors_on_device():
+    import torch
+
+    dgc = _dgc()
+    c = Case("periodic", 8, 9, 1)
+    rhs = torch.zeros_like(c.Ug)
+    small = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(dgc.DgcError) as e:
+        c.D.surface_rhs(c.Ug, rhs, variant="gather", ws=small)
+    assert e.value.name == "DGC_E_WORKSPACE"
+    with pytest.raises(dgc.DgcError) as e:
+        c.D.rk_step(c.Ug, 1e-3, ws=small)
+    assert e.value.name == "DGC_E_WORKSPACE"
+    torch.cuda.synchronize()
+    assert float(rhs.abs().max()) == 0.0
+
+
+@pytest.fixture(scope="module")
+def full_c1():
+    """The full Delaunay workload (~500 k Poisson-disc points, ~1 M triangles, p = 2)."""
+    c = Case("delaunay", 500_000, 2, 2, cseed=0, eps=0.01)
+    return c
+
+
+def test_full_size_sampled(full_c1):
+    c = full_c1
+    got = c.to_host(c.surface("colored"))
+    rng = np.random.default_rng(42)
+    S = np.unique(np.concatenate([rng.choice(c.O.K, 3000, replace=False), [0, c.O.K - 1]]))
+    ref = dg.surface_rhs(c.d, c.U, elems=S)
+    scale = dg.surface_abs(c.d, c.U)[S]
+    _check(got[S], ref[S], scale, "full-size sampled colored")
+    # the other variants agree with the colored one on every entry
+    for v in ("atomic", "gather"):
+        other = c.to_host(c.surface(v))
+        _check(other, got, dg.surface_abs(c.d, c.U), "full-size %s vs colored" % v)

@@ -1,0 +1,195 @@
+"""Native host preprocessing (C ABI) against the oracle: bit-exact integer
+arrays (face table, colors, layouts), geometry and basis tables to rounding."""
+import ctypes as C
+import json
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import basis as obasis, quadrature as oquad
+from oracle.coloring import color_faces, greedy_standard
+from oracle.layout import make_layout
+from oracle.mesh import build_mesh
+from tests.helpers import make_input
+
+dgc = pytest.importorskip("paper_1601_07613_amd")
+from paper_1601_07613_amd import _lib  # noqa: E402
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_tables.json")))
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "dgc.h")
+
+CASES = [("periodic", 16, 1), ("periodic", 37, 4), ("delaunay", 8000, 2), ("tets", 5, 3)]
+
+
+def test_every_declared_symbol_is_exported():
+    text = open(HEADER).read()
+    names = set(re.findall(r"^\s*(?:dgc_status|void|const char \*)\s*\*?(dgc_\w+)\s*\(", text, re.M))
+    assert {"dgc_mesh_build", "dgc_color_edges", "dgc_volume_rhs", "dgc_surface_rhs", "dgc_rk_step"} <= names
+    lib = C.CDLL(str(_lib.LIB_PATH))
+    for n in sorted(names):
+        assert hasattr(lib, n), n
+    assert set(_lib.exported_symbols()) <= names
+
+
+@pytest.mark.parametrize("kind,size,seed", CASES)
+def test_mesh_build_matches_oracle(kind, size, seed):
+    m = make_input(kind, size, seed)
+    O = build_mesh(m["elem_vert"], m["elem_xyz"])
+    M = dgc.Mesh.build(m["elem_vert"], m["elem_xyz"])
+    info = M.info()
+    assert (info["n_elem"], info["n_face"], info["n_boundary"]) == (O.K, O.E, O.n_boundary)
+    assert np.array_equal(M.export("face_elem").reshape(-1, 2), O.face_elem)
+    assert np.array_equal(M.export("face_local").reshape(-1, 2), O.face_local)
+    assert np.array_equal(M.export("elem_face").reshape(O.K, -1), O.elem_face)
+    assert np.allclose(M.export("face_normal").reshape(O.E, -1), O.normal, rtol=0, atol=1e-15)
+    assert np.allclose(M.export("face_measure"), O.measure, rtol=1e-14, atol=0)
+    assert np.allclose(M.export("elem_detj"), O.detJ, rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("kind,size,seed", CASES)
+@pytest.mark.parametrize("cseed", [0, 11])
+def test_coloring_and_layout_bit_exact(kind, size, seed, cseed):
+    m = make_input(kind, size, seed)
+    O = build_mesh(m["elem_vert"], m["elem_xyz"])
+    M = dgc.Mesh.build(m["elem_vert"], m["elem_xyz"])
+    st = M.color(seed=cseed)
+    color, ost = color_faces(O, seed=cseed)
+    assert np.array_equal(M.export("color").astype(np.int64), color)
+    for key in ("conflicts_after_greedy", "swaps", "loop_breaks", "deferrals", "count"):
+        assert st[key] == ost[key], key
+    for mode in ("paper", "renumber", "none"):
+        M.set_colors(color, layout=mode)
+        new, order, off = make_layout(O, color, mode)
+        assert np.array_equal(M.export("elem_new"), new)
+        assert np.array_equal(M.export("face_order"), order)
+        assert np.array_equal(M.export("color_off"), off)
+
+
+def test_device_arrays_follow_layout():
+    m = make_input("delaunay", 3000, 5)
+    O = build_mesh(m["elem_vert"], m["elem_xyz"])
+    M = dgc.Mesh.build(m["elem_vert"], m["elem_xyz"])
+    M.color(seed=3)
+    new = M.export("elem_new")
+    order = M.export("face_order")
+    lr = M.export("dev_face_lr").reshape(2, -1)
+    assert np.array_equal(lr[0], new[O.face_elem[order, 0]])
+    R = O.face_elem[order, 1]
+    assert np.array_equal(lr[1], np.where(R >= 0, new[np.where(R >= 0, R, 0)], -1))
+    geo = M.export("dev_face_geo").reshape(5, -1)
+    assert np.allclose(geo[:2].T, O.normal[order], atol=1e-15)
+    assert np.allclose(geo[3], 1 / np.sqrt(O.detJ[O.face_elem[order, 0]]), rtol=1e-14)
+    slots = M.export("dev_elem_slots").reshape(3, -1)
+    # every (face, side) slot appears exactly once
+    used = np.sort(slots[slots >= 0])
+    expect = np.sort(np.concatenate([2 * np.arange(O.E), 2 * np.nonzero(R >= 0)[0] + 1]))
+    assert np.array_equal(used, expect)
+
+
+def test_standard_greedy_bit_exact():
+    m = make_input("delaunay", 4000, 6)
+    O = build_mesh(m["elem_vert"], m["elem_xyz"])
+    M = dgc.Mesh.build(m["elem_vert"], m["elem_xyz"])
+    st = M.color(algorithm="greedy")
+    g = greedy_standard(O)
+    assert np.array_equal(M.export("color").astype(np.int64), g)
+    assert st["n_colors"] == g.max() + 1 <= 5
+
+
+def test_invalid_coloring_rejected_and_cap():
+    m = make_input("periodic", 8, 1)
+    O = build_mesh(m["elem_vert"], m["elem_xyz"])
+    M = dgc.Mesh.build(m["elem_vert"], m["elem_xyz"])
+    color, _ = color_faces(O, seed=0)
+    bad = color.copy()
+    bad[O.elem_face[3, 1]] = bad[O.elem_face[3, 0]]
+    with pytest.raises(dgc.DgcError) as e:
+        M.set_colors(bad)
+    assert e.value.name == "DGC_E_COLORING_INVALID"
+    assert M.info()["n_colors"] == 0
+    with pytest.raises(dgc.DgcError) as e:
+        M.color(seed=0, max_swaps=0)
+    assert e.value.name == "DGC_E_COLOR_CAP"
+    M.color(seed=1)  # a retry with another seed succeeds
+    assert M.info()["n_colors"] == 3
+
+
+def test_mesh_errors():
+    m = make_input("periodic", 4, 1)
+    xyz = m["elem_xyz"].copy()
+    xyz[2, [1, 2]] = xyz[2, [2, 1]]
+    with pytest.raises(dgc.DgcError) as e:
+        dgc.Mesh.build(m["elem_vert"], xyz)
+    assert e.value.name == "DGC_E_MESH"
+
+
+@pytest.mark.parametrize("et,dim,p", [(0, 2, 0), (0, 2, 1), (0, 2, 2), (0, 2, 3), (2, 3, 0), (2, 3, 1)])
+def test_tables_match_oracle_basis(et, dim, p):
+    info, T = dgc.tables(et, p)
+    npm, qf, qv = info["n_p"], info["n_qf"], info["n_qv"]
+    tr = T[info["off_trace"]:info["off_proj"]].reshape(info["n_codes"], qf, npm)
+    pr = T[info["off_proj"]:info["off_vb"]].reshape(info["n_codes"], qf, npm)
+    vb = T[info["off_vb"]:info["off_vd"]].reshape(qv, npm)
+    vd = T[info["off_vd"]:].reshape(dim, qv, npm)
+    if dim == 2:
+        x, w = oquad.tri_volume_rule(p + 1)
+        s, fw = oquad.gauss_legendre_01(p + 1)
+        edges = [(0, 1), (1, 2), (2, 0)]
+        V = obasis.REF_VERTS[2]
+        maps = [s, 1 - s, 0.5 - 0.5 * s, 1 - 0.5 * s]
+        for f, (a, b) in enumerate(edges):
+            for o, t in enumerate(maps):
+                pts = V[a][None, :] + t[:, None] * (V[b] - V[a])[None, :]
+                ref = obasis.eval_basis(2, p, pts)
+                assert np.abs(tr[f * 4 + o] - ref).max() < 1e-13
+                assert np.abs(pr[f * 4 + o] - fw[:, None] * ref).max() < 1e-13
+    else:
+        x, w = oquad.tet_volume_rule(p + 1)
+        bary, fw = oquad.tet_face_rule_p1()
+        faces = [(1, 2, 3), (0, 2, 3), (0, 1, 3), (0, 1, 2)]
+        perms = [(0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)]
+        V = obasis.REF_VERTS[3]
+        for f, fv in enumerate(faces):
+            for o, pm in enumerate(perms):
+                pts = np.array([bary[pm[q]] @ V[list(fv)] for q in range(3)])
+                ref = obasis.eval_basis(3, p, pts)
+                assert np.abs(tr[f * 6 + o] - ref).max() < 1e-13
+    assert np.abs(vb - obasis.eval_basis(dim, p, x)).max() < 1e-13
+    G = obasis.eval_grad(dim, p, x)
+    for d in range(dim):
+        assert np.abs(vd[d] - w[:, None] * G[:, d, :]).max() < 1e-12
+
+
+def test_gather_workspace_is_table4_memory():
+    """The buffered variant's workspace is the paper's Table 4 formula
+    2 x N_p x N_eq x N_s x 8 bytes (mesh E, Euler, p = 1..5)."""
+    t4 = GOLDEN["table4_memory_saved_GB"]
+    for p, gb in zip(t4["p"], t4["GB"]):
+        info, _ = dgc.tables(0, p)
+        dm = _lib.DMesh()
+        dm.elem_type, dm.p, dm.n_p, dm.n_var = 0, p, info["n_p"], 4
+        dm.n_qf, dm.n_qv, dm.n_codes, dm.n_orient = info["n_qf"], info["n_qv"], info["n_codes"], info["n_orient"]
+        dm.n_elem, dm.n_face = 2514546, t4["sides"]
+        dm.face_lr = dm.face_code = dm.face_geo = dm.elem_geo = dm.tables = 0x1000  # never dereferenced
+        b = C.c_size_t()
+        _lib.check(_lib.load().dgc_workspace_bytes(C.byref(dm), 0, 2, 0, C.byref(b)), "ws")
+        assert math.floor(b.value / 1e9 * 100) / 100 == gb
+        assert b.value == 2 * info["n_p"] * 4 * t4["sides"] * 8
+
+
+def test_surface_entry_rejects_missing_workspace_without_launching():
+    info, _ = dgc.tables(0, 1)
+    dm = _lib.DMesh()
+    dm.elem_type, dm.p, dm.n_p, dm.n_var = 0, 1, info["n_p"], 4
+    dm.n_qf, dm.n_qv, dm.n_codes, dm.n_orient = info["n_qf"], info["n_qv"], info["n_codes"], info["n_orient"]
+    dm.n_elem, dm.n_face, dm.max_slots = 10, 15, 3
+    dm.face_lr = dm.face_code = dm.face_geo = dm.elem_geo = dm.tables = dm.elem_slots = 0x1000
+    L = _lib.load()
+    assert L.dgc_surface_rhs(C.byref(dm), 0x1000, 0x1000, 2, 0, None, 0, None) == -7  # DGC_E_WORKSPACE
+    assert L.dgc_surface_rhs(C.byref(dm), 0x1000, 0x1000, 0, 0, None, 0, None) == -3  # no colors
+    dm.p = 7
+    assert L.dgc_surface_rhs(C.byref(dm), 0x1000, 0x1000, 1, 0, None, 0, None) == -6  # unsupported order
