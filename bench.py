@@ -70,6 +70,8 @@ def main(argv=None):
     ap.add_argument("--only", choices=["all", "colored"], default="all",
                     help="'colored' times the colored pass only (for profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain device copy of known size (HBM counter calibration)")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -85,6 +87,17 @@ def main(argv=None):
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
+
+    if args.calibrate_copy:
+        # 1 GiB read + 1 GiB written per launch: the reference for FETCH_SIZE / WRITE_SIZE
+        n = (1 << 30) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 5}))
+        return 0
 
     t = time.perf_counter()
     m = synth.poisson_delaunay(args.points, seed=args.seed)

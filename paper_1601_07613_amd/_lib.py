@@ -100,14 +100,45 @@ def exported_symbols():
 _lib = None
 
 
+def _preload_torch_hip_runtime():
+    """Make the HIP runtime that PyTorch ships the one libdgc binds to.
+
+    libdgc.so needs ``libamdhip64.so.7``; when torch's copy (same soname) is
+    already mapped, the dynamic loader reuses it, so device pointers and
+    streams from torch and the library's launches share one runtime.
+    """
+    try:
+        import torch
+    except ImportError:
+        return None
+    path = os.path.join(os.path.dirname(torch.__file__), "lib", "libamdhip64.so")
+    if os.path.exists(path):
+        C.CDLL(path, mode=C.RTLD_GLOBAL)
+        return path
+    return None
+
+
+def hip_runtimes_mapped():
+    """Distinct libamdhip64 files mapped into this process."""
+    try:
+        with open("/proc/self/maps") as fh:
+            return sorted({line.split()[-1] for line in fh if "libamdhip64" in line})
+    except OSError:
+        return []
+
+
 def load():
     """Load ``libdgc.so`` from the package directory; raise ImportError when it is not built."""
     global _lib
     if _lib is not None:
         return _lib
     if not LIB_PATH.exists():
-        raise ImportError("libdgc.so is not built; run `python -m paper_1601_07613_amd.build`")
+        raise ImportError("libdgc.so is not built; run `python paper_1601_07613_amd/build.py`")
+    _preload_torch_hip_runtime()
     lib = C.CDLL(os.fspath(LIB_PATH))
+    rts = hip_runtimes_mapped()
+    if len(rts) > 1:
+        raise ImportError("two HIP runtimes are mapped (%s); import torch before libdgc" % ", ".join(rts))
     for name, (res, args) in _SIGS.items():
         fn = getattr(lib, name)
         fn.restype = res
