@@ -69,6 +69,8 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--only", choices=["all", "colored"], default="all",
                     help="'colored' times the colored pass only (for profiling)")
+    ap.add_argument("--form", choices=["default", "team", "thread"], default="default")
+    ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (HBM counter calibration)")
@@ -108,6 +110,7 @@ def main(argv=None):
     build_s = time.perf_counter() - t
     cst = M.color(seed=0)
     D = dgc.DeviceMesh(M, args.p)
+    D.set_launch(args.form, args.block)
     info = D.info
     K, E, nb = info["n_elem"], info["n_face"], info["n_boundary"]
     log("host preprocessing: build %.2fs, color %.0f ms, layout %.0f ms; E=%d" % (
@@ -138,6 +141,12 @@ def main(argv=None):
         wsr = D.workspace("rk", "colored")
         Ur = Ug.clone()
         extra["rk3_step_us"] = timed(lambda: D.rk_step(Ur, 1e-7, ws=wsr), max(args.steps // 5, 3), 2, stream)[0] * 1e3
+        for form in ("team", "thread"):
+            for block in (64, 128, 256):
+                D.set_launch(form, block)
+                extra["colored_%s_b%d_us" % (form, block)] = timed(lambda: D.surface_rhs(Ug, rhs, "colored"),
+                                                                   args.steps, args.warmup, stream)[0] * 1e3
+        D.set_launch(args.form, args.block)
         extra["colored_over_atomic"] = extra["atomic_us"] / (ms * 1e3)
         extra["colored_over_gather"] = extra["gather_us"] / (ms * 1e3)
         for k, v in extra.items():

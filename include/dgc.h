@@ -236,7 +236,16 @@ typedef struct {
     const double *elem_geo;    /* [dim*dim+1][n_elem] */
     const int32_t *elem_slots; /* [max_slots][n_elem] (GATHER only; may be NULL otherwise) */
     const double *tables;      /* dgc_tables layout for (elem_type, p) */
+    /* launch tuning (0 = library default); any valid choice gives the same
+     * result up to the rounding of the accumulation order */
+    int32_t surf_form;         /* DGC_FORM_TEAM or DGC_FORM_THREAD */
+    int32_t block_size;        /* work-items per work-group of the face kernels: 64, 128 or 256 */
 } dgc_dmesh;
+
+/* Face-kernel forms: DGC_FORM_TEAM gives each face a team of lanes (one lane
+ * per conserved variable) so that loads of one element record are
+ * contiguous across lanes; DGC_FORM_THREAD gives each face one work-item. */
+enum { DGC_FORM_DEFAULT = 0, DGC_FORM_TEAM = 1, DGC_FORM_THREAD = 2 };
 
 /* Volume term of Eq. (2): rhs = int F(U) . grad v (overwrites rhs).
  * U, rhs: device [n_elem][n_var][n_p] (f64, or f32 for DGC_F32). */

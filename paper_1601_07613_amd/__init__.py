@@ -157,7 +157,17 @@ class DeviceMesh:
         dm.elem_geo = self.elem_geo.data_ptr()
         dm.elem_slots = self.elem_slots.data_ptr() if self.elem_slots is not None else None
         dm.tables = self.tables.data_ptr()
+        dm.surf_form = 0
+        dm.block_size = 0
         self.dm = dm
+
+    FORMS = {"default": 0, "team": 1, "thread": 2}
+
+    def set_launch(self, form: str = "default", block: int = 0) -> None:
+        """Choose the face-kernel form (team of lanes per face, or one work-item
+        per face) and the work-group size (0 = library default)."""
+        self.dm.surf_form = self.FORMS[form]
+        self.dm.block_size = int(block)
 
     # -- DOF permutation between original element ids and layout ids --------
     def to_layout(self, U: np.ndarray) -> np.ndarray:

@@ -15,6 +15,7 @@ DGC_MAX_COLORS = 8
 DGC_SURF_COLORED, DGC_SURF_ATOMIC, DGC_SURF_GATHER = 0, 1, 2
 DGC_F64, DGC_F32 = 0, 1
 DGC_WS_SURFACE, DGC_WS_RK_STEP = 0, 1
+DGC_FORM_DEFAULT, DGC_FORM_TEAM, DGC_FORM_THREAD = 0, 1, 2
 
 STATUS = {
     0: "DGC_OK", -1: "DGC_E_ARG", -2: "DGC_E_MESH", -3: "DGC_E_NOT_COLORED", -4: "DGC_E_COLOR_CAP",
@@ -67,6 +68,7 @@ class DMesh(C.Structure):
         ("color_off", C.c_int64 * (DGC_MAX_COLORS + 1)),
         ("face_lr", C.c_void_p), ("face_code", C.c_void_p), ("face_geo", C.c_void_p),
         ("elem_geo", C.c_void_p), ("elem_slots", C.c_void_p), ("tables", C.c_void_p),
+        ("surf_form", C.c_int32), ("block_size", C.c_int32),
     ]
 
 

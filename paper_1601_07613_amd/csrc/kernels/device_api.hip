@@ -14,7 +14,7 @@ namespace {
 
 constexpr int kBlock = 256;
 
-inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+inline unsigned grid_for(int64_t n, int block = kBlock) { return (unsigned)((n + block - 1) / block); }
 
 dgc_status hip_check(const char *what) {
     hipError_t e = hipGetLastError();
@@ -35,6 +35,10 @@ dgc_status check_dm(const dgc_dmesh *dm, dgc_table_info *ti) {
         return fail(DGC_E_ARG, "dgc_dmesh: bad element / face count");
     if (!dm->face_lr || !dm->face_code || !dm->face_geo || !dm->elem_geo || !dm->tables)
         return fail(DGC_E_ARG, "dgc_dmesh: null device array");
+    if (dm->surf_form < DGC_FORM_DEFAULT || dm->surf_form > DGC_FORM_THREAD)
+        return fail(DGC_E_ARG, "dgc_dmesh: unknown surf_form");
+    if (dm->block_size != 0 && dm->block_size != 64 && dm->block_size != 128 && dm->block_size != 256)
+        return fail(DGC_E_ARG, "dgc_dmesh: block_size must be 0, 64, 128 or 256");
     return DGC_OK;
 }
 
@@ -62,9 +66,19 @@ struct Impl {
                             T *buf, hipStream_t st) {
         if (f1 <= f0) return DGC_OK;
         const size_t lds = 2 * (size_t)ti.n_codes * Q * NP * sizeof(T);
-        hipLaunchKernelGGL((dgc_dev::surface_kernel<DIM, NP, Q, MODE, T>), dim3(grid_for(f1 - f0)), dim3(kBlock), lds,
-                           st, f0, f1, dm->n_face, dm->n_elem, dm->face_lr, dm->face_code, dm->face_geo,
-                           dm->tables + ti.off_trace, dm->tables + ti.off_proj, ti.n_codes, U, rhs, buf);
+        const int block = dm->block_size ? dm->block_size : kBlock;
+        if (dm->surf_form == DGC_FORM_THREAD) {
+            hipLaunchKernelGGL((dgc_dev::surface_kernel<DIM, NP, Q, MODE, T>), dim3(grid_for(f1 - f0, block)),
+                               dim3(block), lds, st, f0, f1, dm->n_face, dm->n_elem, dm->face_lr, dm->face_code,
+                               dm->face_geo, dm->tables + ti.off_trace, dm->tables + ti.off_proj, ti.n_codes, U, rhs,
+                               buf);
+        } else {
+            constexpr int TEAM = DIM + 2 <= 4 ? 4 : 8;
+            hipLaunchKernelGGL((dgc_dev::surface_team_kernel<DIM, NP, Q, MODE, T>),
+                               dim3(grid_for((f1 - f0) * TEAM, block)), dim3(block), lds, st, f0, f1, dm->n_face,
+                               dm->n_elem, dm->face_lr, dm->face_code, dm->face_geo, dm->tables + ti.off_trace,
+                               dm->tables + ti.off_proj, ti.n_codes, U, rhs, buf);
+        }
         return hip_check("surface kernel launch");
     }
 

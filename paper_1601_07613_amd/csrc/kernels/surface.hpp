@@ -151,6 +151,163 @@ __global__ __launch_bounds__(256) void surface_kernel(
     }
 }
 
+// Value of lane k of the caller's team (TEAM consecutive lanes).  Teams of
+// four use a DPP quad broadcast (a register move, no LDS traffic); wider
+// teams use ds_bpermute through __shfl.
+template <int TEAM>
+__device__ __forceinline__ int team_bcast_i(int v, int k) {
+    if constexpr (TEAM == 4) {
+        switch (k) {
+            case 0: return __builtin_amdgcn_mov_dpp(v, 0x00, 0xF, 0xF, false);
+            case 1: return __builtin_amdgcn_mov_dpp(v, 0x55, 0xF, 0xF, false);
+            case 2: return __builtin_amdgcn_mov_dpp(v, 0xAA, 0xF, 0xF, false);
+            default: return __builtin_amdgcn_mov_dpp(v, 0xFF, 0xF, 0xF, false);
+        }
+    } else {
+        return __shfl(v, k, TEAM);
+    }
+}
+
+template <int TEAM>
+__device__ __forceinline__ double team_bcast(double v, int k) {
+    const int lo = team_bcast_i<TEAM>(__double2loint(v), k);
+    const int hi = team_bcast_i<TEAM>(__double2hiint(v), k);
+    return __hiloint2double(hi, lo);
+}
+
+template <int TEAM>
+__device__ __forceinline__ float team_bcast(float v, int k) {
+    return __int_as_float(team_bcast_i<TEAM>(__float_as_int(v), k));
+}
+
+// Team form of the face kernel: TEAM lanes per face (4 for M = 4, 8 for
+// M = 5); lane r < M owns conserved variable r.  Each lane reads and
+// updates the NP modes of its variable, so one load instruction of a team
+// touches one contiguous stretch of the element record instead of one
+// record per lane.  The traces of all variables are exchanged inside the
+// team and every lane evaluates the flux of the full state; lane r then
+// projects component r.  Same arithmetic and accumulation modes as
+// surface_kernel.
+template <int DIM, int NP, int Q, int MODE, class T>
+__global__ __launch_bounds__(256) void surface_team_kernel(
+    int64_t f_begin, int64_t f_end, int64_t n_face, int64_t n_elem,
+    const int32_t *__restrict__ face_lr, const uint8_t *__restrict__ face_code,
+    const double *__restrict__ face_geo, const double *__restrict__ tab_trace,
+    const double *__restrict__ tab_proj, int n_codes,
+    const T *__restrict__ U, T *__restrict__ rhs, T *__restrict__ buf) {
+    constexpr int M = DIM + 2;
+    constexpr int REC = M * NP;
+    constexpr int TEAM = M <= 4 ? 4 : 8;
+    extern __shared__ unsigned char smem_raw[];
+    T *s_tr = reinterpret_cast<T *>(smem_raw);
+    T *s_pr = s_tr + n_codes * Q * NP;
+    const int ntab = n_codes * Q * NP;
+    for (int i = threadIdx.x; i < ntab; i += blockDim.x) {
+        s_tr[i] = T(tab_trace[i]);
+        s_pr[i] = T(tab_proj[i]);
+    }
+    __syncthreads();
+
+    const int r = threadIdx.x % TEAM;
+    const int64_t k = f_begin + ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / TEAM;
+    if (k >= f_end) return;  // whole teams leave together
+    const int32_t L = face_lr[k];
+    const int32_t R = face_lr[n_face + k];
+    const int cL = face_code[k];
+    const int cR = face_code[n_face + k];
+    if (L < 0 || L >= n_elem || R >= n_elem || cL >= n_codes || cR >= n_codes) return;
+    T n[DIM];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) n[d] = T(face_geo[d * n_face + k]);
+    const double len = face_geo[DIM * n_face + k];
+    const double isL = face_geo[(DIM + 1) * n_face + k];
+    const double isR = face_geo[(DIM + 2) * n_face + k];
+    const bool own = r < M;
+
+    // my variable's traces on both sides
+    T tL[Q], tR[Q];
+    {
+        T c[NP];
+        const T *uL = U + (size_t)L * REC + r * NP;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) c[j] = own ? uL[j] : T(0);
+        const T *tl = s_tr + cL * Q * NP;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            T a = 0;
+#pragma unroll
+            for (int j = 0; j < NP; ++j) a += tl[q * NP + j] * c[j];
+            tL[q] = a * T(isL);
+        }
+    }
+    if (R >= 0) {
+        T c[NP];
+        const T *uR = U + (size_t)R * REC + r * NP;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) c[j] = own ? uR[j] : T(0);
+        const T *tr = s_tr + cR * Q * NP;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            T a = 0;
+#pragma unroll
+            for (int j = 0; j < NP; ++j) a += tr[q * NP + j] * c[j];
+            tR[q] = a * T(isR);
+        }
+    }
+
+    // full states at every point, flux of the full state, my component
+    T Fm[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        T uLq[M], uRq[M], F[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) uLq[m] = team_bcast<TEAM>(tL[q], m);
+        if (R >= 0) {
+#pragma unroll
+            for (int m = 0; m < M; ++m) uRq[m] = team_bcast<TEAM>(tR[q], m);
+        } else {
+            wall_ghost<DIM, T>(uLq, n, uRq);
+        }
+        rusanov<DIM, T>(uLq, uRq, n, F);
+        T f = F[0];
+#pragma unroll
+        for (int m = 1; m < M; ++m) f = r == m ? F[m] : f;
+        Fm[q] = f;
+    }
+    if (!own) return;
+
+    {
+        const T sL = T(len * isL);
+        const T *pl = s_pr + cL * Q * NP;
+        T *dst = (MODE == kGather ? buf + (size_t)(2 * k) * REC : rhs + (size_t)L * REC) + r * NP;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            T a = 0;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) a += pl[q * NP + j] * Fm[q];
+            a *= sL;
+            if (MODE == kColored) dst[j] -= a;
+            else if (MODE == kAtomic) atomic_add<T>(dst + j, -a);
+            else dst[j] = -a;
+        }
+    }
+    if (R >= 0) {
+        const T sR = T(len * isR);
+        const T *pr = s_pr + cR * Q * NP;
+        T *dst = (MODE == kGather ? buf + (size_t)(2 * k + 1) * REC : rhs + (size_t)R * REC) + r * NP;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            T a = 0;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) a += pr[q * NP + j] * Fm[q];
+            a *= sR;
+            if (MODE == kColored) dst[j] += a;
+            else if (MODE == kAtomic) atomic_add<T>(dst + j, a);
+            else dst[j] = a;
+        }
+    }
+}
+
 // Second pass of the buffered variant: rhs[k] += sum of element k's slots.
 template <int DIM, int NP, class T>
 __global__ __launch_bounds__(256) void gather_kernel(int64_t n_elem, int max_slots, int64_t n_slots_total,

@@ -83,26 +83,32 @@ def _volume_abs(d, U):
     return np.einsum("q,qdj,kqmd->kmj", d.vol_w, np.abs(d.vol_D), G) * sq[:, None, None]
 
 
+@pytest.mark.parametrize("form", ["team", "thread"])
 @pytest.mark.parametrize("p", [0, 1, 2, 3])
 @pytest.mark.parametrize("variant", ["colored", "atomic", "gather"])
-def test_surface_periodic_triangles(p, variant):
+def test_surface_periodic_triangles(p, variant, form):
     c = Case("periodic", 16, 1, p)
+    c.D.set_launch(form)
     got = c.to_host(c.surface(variant))
     _check(got, dg.surface_rhs(c.d, c.U), dg.surface_abs(c.d, c.U), "surface %s p=%d" % (variant, p))
 
 
+@pytest.mark.parametrize("form,block", [("team", 256), ("team", 64), ("thread", 256), ("thread", 128)])
 @pytest.mark.parametrize("variant", ["colored", "atomic", "gather"])
-def test_surface_delaunay_walls_ragged(variant):
+def test_surface_delaunay_walls_ragged(variant, form, block):
     c = Case("delaunay", 12000, 2, 2)
     assert c.O.E % 256 != 0 and c.O.n_boundary > 0
+    c.D.set_launch(form, block)
     got = c.to_host(c.surface(variant))
     _check(got, dg.surface_rhs(c.d, c.U), dg.surface_abs(c.d, c.U), "surface delaunay " + variant)
 
 
+@pytest.mark.parametrize("form", ["team", "thread"])
 @pytest.mark.parametrize("p", [0, 1])
 @pytest.mark.parametrize("variant", ["colored", "atomic", "gather"])
-def test_surface_tets(p, variant):
+def test_surface_tets(p, variant, form):
     c = Case("tets", 6, 3, p)
+    c.D.set_launch(form)
     assert c.stats["n_colors"] == 4
     got = c.to_host(c.surface(variant))
     _check(got, dg.surface_rhs(c.d, c.U), dg.surface_abs(c.d, c.U), "surface tets %s p=%d" % (variant, p))
@@ -234,6 +240,7 @@ def full_c1():
 
 def test_full_size_sampled(full_c1):
     c = full_c1
+    c.D.set_launch("default")
     got = c.to_host(c.surface("colored"))
     rng = np.random.default_rng(42)
     S = np.unique(np.concatenate([rng.choice(c.O.K, 3000, replace=False), [0, c.O.K - 1]]))
@@ -244,3 +251,7 @@ def test_full_size_sampled(full_c1):
     for v in ("atomic", "gather"):
         other = c.to_host(c.surface(v))
         _check(other, got, dg.surface_abs(c.d, c.U), "full-size %s vs colored" % v)
+    c.D.set_launch("thread")
+    other = c.to_host(c.surface("colored"))
+    c.D.set_launch("default")
+    _check(other, got, dg.surface_abs(c.d, c.U), "full-size thread form vs team form")
