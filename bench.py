@@ -69,8 +69,11 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--only", choices=["all", "colored"], default="all",
                     help="'colored' times the colored pass only (for profiling)")
-    ap.add_argument("--form", choices=["default", "team", "thread"], default="default")
+    ap.add_argument("--form", choices=["auto", "default", "team", "team_prefetch", "thread"], default="auto",
+                    help="face-kernel form; 'auto' runs the launch autotuner before timing")
     ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--xcd-remap", action="store_true")
+    ap.add_argument("--layout", choices=["paper", "paper_sfc", "renumber", "none"], default="paper")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (HBM counter calibration)")
@@ -101,6 +104,8 @@ def main(argv=None):
         print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 5}))
         return 0
 
+    from paper_1601_07613_amd.tune import autotune, time_call
+
     t = time.perf_counter()
     m = synth.poisson_delaunay(args.points, seed=args.seed)
     gen_s = time.perf_counter() - t
@@ -108,31 +113,46 @@ def main(argv=None):
     t = time.perf_counter()
     M = dgc.Mesh.build(m["elem_vert"], m["elem_xyz"])
     build_s = time.perf_counter() - t
-    cst = M.color(seed=0)
-    D = dgc.DeviceMesh(M, args.p)
-    D.set_launch(args.form, args.block)
-    info = D.info
-    K, E, nb = info["n_elem"], info["n_face"], info["n_boundary"]
-    log("host preprocessing: build %.2fs, color %.0f ms, layout %.0f ms; E=%d" % (
-        build_s, cst["color_ms"], cst["layout_ms"], E))
-
+    cst = M.color(seed=0, layout=args.layout)
+    colors = M.export("color")
     meas = synth.element_measure(m["elem_xyz"])
     st = synth.shock_tube_states(synth.element_centroid(m["elem_xyz"]))
-    U = synth.perturbed_dofs(meas, st, D.n_p, eps=0.01, seed=args.seed + 100)
-    Ug = torch.from_numpy(D.to_layout(U)).cuda()
-    rhs = torch.zeros_like(Ug)
+    p = args.p
     stream = torch.cuda.current_stream()
+    log("host preprocessing: build %.2fs, color %.0f ms, layout %.0f ms" % (build_s, cst["color_ms"], cst["layout_ms"]))
+
+    def device_mesh(layout):
+        M.set_colors(colors, layout=layout)
+        D = dgc.DeviceMesh(M, p)
+        U = synth.perturbed_dofs(meas, st, D.n_p, eps=0.01, seed=args.seed + 100)
+        Ug = torch.from_numpy(D.to_layout(U)).cuda()
+        return D, U, Ug, torch.zeros_like(Ug)
+
+    D, U, Ug, rhs = device_mesh(args.layout)
+    info = D.info
+    K, E, nb = info["n_elem"], info["n_face"], info["n_boundary"]
     rec = D.n_var * D.n_p
     ab = algorithmic_bytes(E, E - nb, rec, 8, D.dim)
+    dof = K * D.n_var * D.n_p
+
+    # clocks up: run the pass for ~0.5 s before any measurement
+    time_call(lambda: D.surface_rhs(Ug, rhs, "colored"), reps=200, warmup=5)
+    if args.form == "auto":
+        best, sweep = autotune(D, Ug, rhs)
+        log("autotuned launch: %s" % best)
+    else:
+        D.set_launch(args.form, args.block, args.xcd_remap)
+        best, sweep = {"form": args.form, "block": args.block, "xcd_remap": args.xcd_remap}, []
 
     ms, wall = timed(lambda: D.surface_rhs(Ug, rhs, "colored"), args.steps, args.warmup, stream)
     log("colored pass: %.1f us (wall %.2fs for %d steps)" % (ms * 1e3, wall, args.steps))
-    dof = K * D.n_var * D.n_p
     value = dof / (ms * 1e-3)
     achieved = ab / (ms * 1e-3) / 1e9
 
     extra = {}
     if args.only == "all":
+        for cfg, t_ms in sweep:
+            extra["colored_%s_b%d%s_us" % (cfg["form"], cfg["block"], "_xcd" if cfg["xcd_remap"] else "")] = t_ms * 1e3
         ws = D.workspace("surface", "gather")
         extra["atomic_us"] = timed(lambda: D.surface_rhs(Ug, rhs, "atomic"), args.steps, args.warmup, stream)[0] * 1e3
         extra["gather_us"] = timed(lambda: D.surface_rhs(Ug, rhs, "gather", ws=ws), args.steps, args.warmup,
@@ -141,16 +161,31 @@ def main(argv=None):
         wsr = D.workspace("rk", "colored")
         Ur = Ug.clone()
         extra["rk3_step_us"] = timed(lambda: D.rk_step(Ur, 1e-7, ws=wsr), max(args.steps // 5, 3), 2, stream)[0] * 1e3
-        for form in ("team", "thread"):
-            for block in (64, 128, 256):
-                D.set_launch(form, block)
-                extra["colored_%s_b%d_us" % (form, block)] = timed(lambda: D.surface_rhs(Ug, rhs, "colored"),
-                                                                   args.steps, args.warmup, stream)[0] * 1e3
-        D.set_launch(args.form, args.block)
+        D.set_launch("thread", 256)
+        extra["colored_thread_form_us"] = timed(lambda: D.surface_rhs(Ug, rhs, "colored"), args.steps, args.warmup,
+                                                stream)[0] * 1e3
+        D.set_launch(best["form"], best["block"], best["xcd_remap"])
         extra["colored_over_atomic"] = extra["atomic_us"] / (ms * 1e3)
         extra["colored_over_gather"] = extra["gather_us"] / (ms * 1e3)
-        for k, v in extra.items():
-            log("%s: %.2f" % (k, v))
+        # the other layouts of the same coloring, same launch
+        for lay in ("paper", "paper_sfc", "renumber", "none"):
+            if lay == args.layout:
+                continue
+            D2, _, Ug2, rhs2 = device_mesh(lay)
+            D2.set_launch(best["form"], best["block"], best["xcd_remap"])
+            extra["colored_layout_%s_us" % lay] = timed(lambda: D2.surface_rhs(Ug2, rhs2, "colored"), args.steps,
+                                                        args.warmup, stream)[0] * 1e3
+            del D2, Ug2, rhs2
+        M.set_colors(colors, layout=args.layout)
+        # measured streaming reference: device copy of 1 GiB
+        n = (1 << 30) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        cms = time_call(lambda: b.copy_(a), reps=20, warmup=3)
+        extra["copy_1GiB_GBs"] = 2 * n * 8 / (cms * 1e-3) / 1e9
+        del a, b
+        for k2, v in extra.items():
+            log("%s: %.2f" % (k2, v))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -187,8 +222,9 @@ def main(argv=None):
         "config": {
             "workload": "Delaunay triangulation of %d seeded Poisson-disc points in the unit square (%d triangles, "
                         "%d edges, %d wall edges), 2D Euler p=%d (N_p=%d, M=4), shock tube, colored surface pass, "
-                        "paper layout" % (m["n_vert"], K, E, nb, args.p, D.n_p, ),
+                        "%s layout" % (m["n_vert"], K, E, nb, args.p, D.n_p, args.layout),
             "n_elem": K, "n_face": E, "p": args.p, "n_colors": info["n_colors"], "variant": "colored",
+            "layout": args.layout, "launch": best,
         },
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,

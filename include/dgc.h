@@ -66,6 +66,8 @@ enum { DGC_TRI = 0, DGC_TET = 2 };
 #define DGC_LAYOUT_PAPER     0x10u /* renumber elements + reorder faces (Section 5) */
 #define DGC_LAYOUT_RENUMBER  0x20u /* renumber elements only (Table 5) */
 #define DGC_LAYOUT_NONE      0x40u /* faces grouped by color, elements unchanged */
+#define DGC_LAYOUT_PAPER_SFC 0x80u /* DGC_LAYOUT_PAPER with the first color's faces taken in
+                                      Morton order of their midpoints (an extension) */
 
 #define DGC_MAX_COLORS 8
 
@@ -238,14 +240,19 @@ typedef struct {
     const double *tables;      /* dgc_tables layout for (elem_type, p) */
     /* launch tuning (0 = library default); any valid choice gives the same
      * result up to the rounding of the accumulation order */
-    int32_t surf_form;         /* DGC_FORM_TEAM or DGC_FORM_THREAD */
+    int32_t surf_form;         /* DGC_FORM_* */
     int32_t block_size;        /* work-items per work-group of the face kernels: 64, 128 or 256 */
+    int32_t xcd_remap;         /* 1: work-groups are dealt round-robin to the 8 XCDs, so give
+                                  each XCD one contiguous range of faces (shared L2 lines) */
+    int32_t pad_;
 } dgc_dmesh;
 
 /* Face-kernel forms: DGC_FORM_TEAM gives each face a team of lanes (one lane
  * per conserved variable) so that loads of one element record are
- * contiguous across lanes; DGC_FORM_THREAD gives each face one work-item. */
-enum { DGC_FORM_DEFAULT = 0, DGC_FORM_TEAM = 1, DGC_FORM_THREAD = 2 };
+ * contiguous across lanes; DGC_FORM_TEAM_PREFETCH is the same with the
+ * right-hand-side reads of the colored update issued before the flux
+ * evaluation (the default); DGC_FORM_THREAD gives each face one work-item. */
+enum { DGC_FORM_DEFAULT = 0, DGC_FORM_TEAM = 1, DGC_FORM_THREAD = 2, DGC_FORM_TEAM_PREFETCH = 3 };
 
 /* Volume term of Eq. (2): rhs = int F(U) . grad v (overwrites rhs).
  * U, rhs: device [n_elem][n_var][n_p] (f64, or f32 for DGC_F32). */

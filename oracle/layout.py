@@ -26,7 +26,12 @@ Readings where the paper is silent:
   is exactly steps 2-3 (every element is touched by the first color).
 
 Modes: ``"paper"`` (steps 1-3), ``"renumber"`` (1-2 only, faces of later
-colors keep id order) and ``"none"`` (1 only, identity element numbering).
+colors keep id order), ``"none"`` (1 only, identity element numbering) and
+``"paper_sfc"`` -- an extension that is not in the paper: the interior and
+the boundary faces of the first color are each put in Morton (Z-curve)
+order of their midpoints (ties by id) before step 2.  Midpoints are taken
+from the left element's coordinates and quantised to ``2^31`` (2D) or
+``2^21`` (3D) cells of their bounding box.
 
 Returns ``elem_new[K]`` (new id of original element ``i``), ``face_order[E]``
 (original face id at each layout position) and ``color_off[F + 1]``.
@@ -41,6 +46,44 @@ from __future__ import annotations
 import numpy as np
 
 
+def morton_order(mesh, faces):
+    """``faces`` sorted by the Morton code of their midpoints, ties by id."""
+    from .mesh import local_faces
+
+    faces = list(faces)
+    if not faces:
+        return faces
+    dim = mesh.dim
+    lf = local_faces(dim)
+    bits = 31 if dim == 2 else 21
+    scale = float(2 ** bits)
+    mids = []
+    for f in faces:
+        x = mesh.elem_xyz[mesh.face_elem[f, 0]]
+        verts = lf[mesh.face_local[f, 0]]
+        m = []
+        for d in range(dim):
+            s = 0.0
+            for a in verts:
+                s += float(x[a, d])
+            m.append(s / dim)
+        mids.append(m)
+    mids = np.array(mids)
+    lo = mids.min(axis=0)
+    hi = mids.max(axis=0)
+    codes = []
+    for m in mids:
+        c = 0
+        for d in range(dim):
+            ext = hi[d] - lo[d] if hi[d] > lo[d] else 1.0
+            t = (m[d] - lo[d]) / ext * scale
+            q = int(scale) - 1 if t >= scale else (int(t) if t > 0 else 0)
+            for b in range(bits):
+                c |= ((q >> b) & 1) << (b * dim + d)
+        codes.append(c)
+    return [f for _, f in sorted(zip(codes, faces))]
+
+
 def make_layout(mesh, color, mode: str = "paper"):
     color = np.asarray(color, dtype=np.int64)
     if (color < 0).any():
@@ -51,7 +94,9 @@ def make_layout(mesh, color, mode: str = "paper"):
     groups = []
     for c in range(n_colors):
         ids = [f for f in range(mesh.E) if color[f] == c]
-        if c == 0 and mode != "none":
+        if c == 0 and mode == "paper_sfc":
+            ids = morton_order(mesh, [f for f in ids if R[f] >= 0]) + morton_order(mesh, [f for f in ids if R[f] < 0])
+        elif c == 0 and mode != "none":
             ids = [f for f in ids if R[f] >= 0] + [f for f in ids if R[f] < 0]
         groups.append(ids)
 
@@ -73,7 +118,7 @@ def make_layout(mesh, color, mode: str = "paper"):
     order = []
     off = [0]
     for c, ids in enumerate(groups):
-        if mode == "paper" and c > 0:
+        if mode in ("paper", "paper_sfc") and c > 0:
             ids = sorted(ids, key=lambda f: elem_new[L[f]])
         order.extend(ids)
         off.append(len(order))

@@ -16,14 +16,15 @@ import numpy as np
 from . import _lib
 from ._lib import (  # noqa: F401
     DGC_COLOR_GREEDY_STD, DGC_COLOR_PAPER, DGC_F32, DGC_F64, DGC_LAYOUT_NONE, DGC_LAYOUT_PAPER,
-    DGC_LAYOUT_RENUMBER, DGC_SURF_ATOMIC, DGC_SURF_COLORED, DGC_SURF_GATHER, DGC_TET, DGC_TRI, DgcError,
+    DGC_LAYOUT_PAPER_SFC, DGC_LAYOUT_RENUMBER, DGC_SURF_ATOMIC, DGC_SURF_COLORED, DGC_SURF_GATHER, DGC_TET, DGC_TRI, DgcError,
 )
 
 _L = _lib.load()
 
 VARIANTS = {"colored": DGC_SURF_COLORED, "atomic": DGC_SURF_ATOMIC, "gather": DGC_SURF_GATHER}
 PRECISIONS = {"f64": DGC_F64, "f32": DGC_F32}
-LAYOUTS = {"paper": DGC_LAYOUT_PAPER, "renumber": DGC_LAYOUT_RENUMBER, "none": DGC_LAYOUT_NONE}
+LAYOUTS = {"paper": DGC_LAYOUT_PAPER, "renumber": DGC_LAYOUT_RENUMBER, "none": DGC_LAYOUT_NONE,
+           "paper_sfc": DGC_LAYOUT_PAPER_SFC}
 ALGORITHMS = {"paper": DGC_COLOR_PAPER, "greedy": DGC_COLOR_GREEDY_STD}
 
 
@@ -159,15 +160,18 @@ class DeviceMesh:
         dm.tables = self.tables.data_ptr()
         dm.surf_form = 0
         dm.block_size = 0
+        dm.xcd_remap = 0
         self.dm = dm
 
-    FORMS = {"default": 0, "team": 1, "thread": 2}
+    FORMS = {"default": 0, "team": 1, "thread": 2, "team_prefetch": 3}
 
-    def set_launch(self, form: str = "default", block: int = 0) -> None:
+    def set_launch(self, form: str = "default", block: int = 0, xcd_remap: bool = False) -> None:
         """Choose the face-kernel form (team of lanes per face, or one work-item
-        per face) and the work-group size (0 = library default)."""
+        per face), the work-group size (0 = library default) and whether
+        work-groups are remapped to contiguous face ranges per XCD."""
         self.dm.surf_form = self.FORMS[form]
         self.dm.block_size = int(block)
+        self.dm.xcd_remap = int(bool(xcd_remap))
 
     # -- DOF permutation between original element ids and layout ids --------
     def to_layout(self, U: np.ndarray) -> np.ndarray:

@@ -10,7 +10,7 @@ LIB_PATH = Path(__file__).resolve().parent / "libdgc.so"
 
 DGC_TRI, DGC_TET = 0, 2
 DGC_COLOR_PAPER, DGC_COLOR_GREEDY_STD = 0x01, 0x02
-DGC_LAYOUT_PAPER, DGC_LAYOUT_RENUMBER, DGC_LAYOUT_NONE = 0x10, 0x20, 0x40
+DGC_LAYOUT_PAPER, DGC_LAYOUT_RENUMBER, DGC_LAYOUT_NONE, DGC_LAYOUT_PAPER_SFC = 0x10, 0x20, 0x40, 0x80
 DGC_MAX_COLORS = 8
 DGC_SURF_COLORED, DGC_SURF_ATOMIC, DGC_SURF_GATHER = 0, 1, 2
 DGC_F64, DGC_F32 = 0, 1
@@ -68,7 +68,7 @@ class DMesh(C.Structure):
         ("color_off", C.c_int64 * (DGC_MAX_COLORS + 1)),
         ("face_lr", C.c_void_p), ("face_code", C.c_void_p), ("face_geo", C.c_void_p),
         ("elem_geo", C.c_void_p), ("elem_slots", C.c_void_p), ("tables", C.c_void_p),
-        ("surf_form", C.c_int32), ("block_size", C.c_int32),
+        ("surf_form", C.c_int32), ("block_size", C.c_int32), ("xcd_remap", C.c_int32), ("pad_", C.c_int32),
     ]
 
 

@@ -76,7 +76,8 @@ dgc_status dgc_color_edges(dgc_mesh *h, uint64_t seed, int64_t max_swaps, uint32
     if (lay == 0) lay = DGC_LAYOUT_PAPER;
     if (alg == 0) alg = DGC_COLOR_PAPER;
     if ((alg != DGC_COLOR_PAPER && alg != DGC_COLOR_GREEDY_STD) ||
-        (lay != DGC_LAYOUT_PAPER && lay != DGC_LAYOUT_RENUMBER && lay != DGC_LAYOUT_NONE))
+        (lay != DGC_LAYOUT_PAPER && lay != DGC_LAYOUT_RENUMBER && lay != DGC_LAYOUT_NONE &&
+         lay != DGC_LAYOUT_PAPER_SFC))
         return fail(DGC_E_ARG, "dgc_color_edges: bad flags");
     try {
         dgc_color_stats st{};
@@ -109,7 +110,8 @@ dgc_status dgc_set_colors(dgc_mesh *h, const int8_t *colors, uint32_t layout_fla
     dgc::Mesh &m = h->m;
     uint32_t lay = layout_flags & 0xF0u;
     if (lay == 0) lay = DGC_LAYOUT_PAPER;
-    if (lay != DGC_LAYOUT_PAPER && lay != DGC_LAYOUT_RENUMBER && lay != DGC_LAYOUT_NONE)
+    if (lay != DGC_LAYOUT_PAPER && lay != DGC_LAYOUT_RENUMBER && lay != DGC_LAYOUT_NONE &&
+        lay != DGC_LAYOUT_PAPER_SFC)
         return fail(DGC_E_ARG, "dgc_set_colors: bad layout flag");
     std::vector<int8_t> c(colors, colors + m.E);
     std::string why;

@@ -9,23 +9,92 @@
 // On meshes where an element can miss a color (refined meshes), colors are
 // processed in order and each one first numbers its still-unnumbered left
 // elements, then its still-unnumbered right elements, before its sort.
+//
+// DGC_LAYOUT_PAPER_SFC (an extension, not in the paper): before step 2 the
+// faces of the first color are put in Morton (Z-curve) order of their
+// midpoints, interior faces still first.  Neighbouring pairs of the first
+// color then get neighbouring ids, so the right elements met by the later
+// colors lie close in memory to their left elements.
 #include <algorithm>
+#include <cmath>
 
 #include "internal.hpp"
 
 namespace dgc {
 
+int face_vertex(const Mesh &m, int local_face, int k);
+
+namespace {
+
+// Morton code of each listed face's midpoint (taken from its left element's
+// coordinates), quantised on the bounding box of those midpoints.
+std::vector<uint64_t> morton_codes(const Mesh &m, const std::vector<int32_t> &faces) {
+    const int dim = m.dim, nfv = dim;
+    const int bits = dim == 2 ? 31 : 21;
+    const double scale = std::ldexp(1.0, bits);
+    std::vector<double> mid(faces.size() * dim);
+    double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    for (size_t i = 0; i < faces.size(); ++i) {
+        const int32_t f = faces[i];
+        const double *x = &m.elem_xyz[(int64_t)m.face_L[f] * m.nv * dim];
+        for (int d = 0; d < dim; ++d) {
+            double s = 0.0;
+            for (int a = 0; a < nfv; ++a) s += x[face_vertex(m, m.face_fL[f], a) * dim + d];
+            const double v = s / nfv;
+            mid[i * dim + d] = v;
+            if (i == 0 || v < lo[d]) lo[d] = v;
+            if (i == 0 || v > hi[d]) hi[d] = v;
+        }
+    }
+    std::vector<uint64_t> code(faces.size(), 0);
+    for (size_t i = 0; i < faces.size(); ++i) {
+        uint64_t c = 0;
+        for (int d = 0; d < dim; ++d) {
+            const double ext = hi[d] > lo[d] ? hi[d] - lo[d] : 1.0;
+            const double t = (mid[i * dim + d] - lo[d]) / ext * scale;
+            uint64_t q = t >= scale ? (uint64_t)scale - 1 : (t > 0 ? (uint64_t)t : 0);
+            for (int b = 0; b < bits; ++b) c |= ((q >> b) & 1ull) << (b * dim + d);
+        }
+        code[i] = c;
+    }
+    return code;
+}
+
+void sort_by_morton(const Mesh &m, std::vector<int32_t> &faces) {
+    std::vector<uint64_t> code = morton_codes(m, faces);
+    std::vector<size_t> idx(faces.size());
+    for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
+    std::sort(idx.begin(), idx.end(), [&](size_t a, size_t b) {
+        if (code[a] != code[b]) return code[a] < code[b];
+        return faces[a] < faces[b];
+    });
+    std::vector<int32_t> out(faces.size());
+    for (size_t i = 0; i < idx.size(); ++i) out[i] = faces[idx[i]];
+    faces.swap(out);
+}
+
+}  // namespace
+
 dgc_status make_layout(Mesh &m, uint32_t flag) {
     const int nc = m.n_colors;
     if (nc <= 0) return fail(DGC_E_NOT_COLORED, "mesh is not colored");
     const bool renumber = flag != DGC_LAYOUT_NONE;
-    const bool reorder = flag == DGC_LAYOUT_PAPER;
+    const bool reorder = flag == DGC_LAYOUT_PAPER || flag == DGC_LAYOUT_PAPER_SFC;
 
     std::vector<std::vector<int32_t>> groups(nc);
     for (int64_t f = 0; f < m.E; ++f) groups[m.color[f]].push_back((int32_t)f);
     if (renumber) {
         std::vector<int32_t> &g0 = groups[0];
-        std::stable_partition(g0.begin(), g0.end(), [&](int32_t f) { return m.face_R[f] >= 0; });
+        if (flag == DGC_LAYOUT_PAPER_SFC) {
+            std::vector<int32_t> in, bd;
+            for (int32_t f : g0) (m.face_R[f] >= 0 ? in : bd).push_back(f);
+            sort_by_morton(m, in);
+            sort_by_morton(m, bd);
+            g0 = in;
+            g0.insert(g0.end(), bd.begin(), bd.end());
+        } else {
+            std::stable_partition(g0.begin(), g0.end(), [&](int32_t f) { return m.face_R[f] >= 0; });
+        }
     }
 
     m.elem_new.assign(m.K, -1);

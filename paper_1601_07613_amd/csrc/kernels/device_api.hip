@@ -35,7 +35,7 @@ dgc_status check_dm(const dgc_dmesh *dm, dgc_table_info *ti) {
         return fail(DGC_E_ARG, "dgc_dmesh: bad element / face count");
     if (!dm->face_lr || !dm->face_code || !dm->face_geo || !dm->elem_geo || !dm->tables)
         return fail(DGC_E_ARG, "dgc_dmesh: null device array");
-    if (dm->surf_form < DGC_FORM_DEFAULT || dm->surf_form > DGC_FORM_THREAD)
+    if (dm->surf_form < DGC_FORM_DEFAULT || dm->surf_form > DGC_FORM_TEAM_PREFETCH)
         return fail(DGC_E_ARG, "dgc_dmesh: unknown surf_form");
     if (dm->block_size != 0 && dm->block_size != 64 && dm->block_size != 128 && dm->block_size != 256)
         return fail(DGC_E_ARG, "dgc_dmesh: block_size must be 0, 64, 128 or 256");
@@ -71,13 +71,19 @@ struct Impl {
             hipLaunchKernelGGL((dgc_dev::surface_kernel<DIM, NP, Q, MODE, T>), dim3(grid_for(f1 - f0, block)),
                                dim3(block), lds, st, f0, f1, dm->n_face, dm->n_elem, dm->face_lr, dm->face_code,
                                dm->face_geo, dm->tables + ti.off_trace, dm->tables + ti.off_proj, ti.n_codes, U, rhs,
-                               buf);
+                               buf, dm->xcd_remap);
         } else {
             constexpr int TEAM = DIM + 2 <= 4 ? 4 : 8;
-            hipLaunchKernelGGL((dgc_dev::surface_team_kernel<DIM, NP, Q, MODE, T>),
-                               dim3(grid_for((f1 - f0) * TEAM, block)), dim3(block), lds, st, f0, f1, dm->n_face,
-                               dm->n_elem, dm->face_lr, dm->face_code, dm->face_geo, dm->tables + ti.off_trace,
-                               dm->tables + ti.off_proj, ti.n_codes, U, rhs, buf);
+            if (dm->surf_form == DGC_FORM_TEAM_PREFETCH || dm->surf_form == DGC_FORM_DEFAULT)
+                hipLaunchKernelGGL((dgc_dev::surface_team_kernel<DIM, NP, Q, MODE, T, true>),
+                                   dim3(grid_for((f1 - f0) * TEAM, block)), dim3(block), lds, st, f0, f1, dm->n_face,
+                                   dm->n_elem, dm->face_lr, dm->face_code, dm->face_geo, dm->tables + ti.off_trace,
+                                   dm->tables + ti.off_proj, ti.n_codes, U, rhs, buf, dm->xcd_remap);
+            else
+                hipLaunchKernelGGL((dgc_dev::surface_team_kernel<DIM, NP, Q, MODE, T, false>),
+                                   dim3(grid_for((f1 - f0) * TEAM, block)), dim3(block), lds, st, f0, f1, dm->n_face,
+                                   dm->n_elem, dm->face_lr, dm->face_code, dm->face_geo, dm->tables + ti.off_trace,
+                                   dm->tables + ti.off_proj, ti.n_codes, U, rhs, buf, dm->xcd_remap);
         }
         return hip_check("surface kernel launch");
     }

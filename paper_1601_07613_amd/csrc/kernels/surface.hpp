@@ -32,13 +32,24 @@ __device__ __forceinline__ void atomic_add(T *addr, T v) {
     unsafeAtomicAdd(addr, v);
 }
 
+// Work-groups of a launch are dealt round-robin to the 8 XCDs (each with its
+// own L2).  With remap set, XCD x processes one contiguous range of logical
+// work-groups instead of every eighth one; the map is a bijection of
+// [0, gridDim.x).
+__device__ __forceinline__ unsigned logical_block(int remap) {
+    const unsigned b = blockIdx.x;
+    if (!remap) return b;
+    const unsigned nb = gridDim.x, x = b % 8u, q = nb / 8u, r = nb % 8u;
+    return x * q + (x < r ? x : r) + b / 8u;
+}
+
 template <int DIM, int NP, int Q, int MODE, class T>
 __global__ __launch_bounds__(256) void surface_kernel(
     int64_t f_begin, int64_t f_end, int64_t n_face, int64_t n_elem,
     const int32_t *__restrict__ face_lr, const uint8_t *__restrict__ face_code,
     const double *__restrict__ face_geo, const double *__restrict__ tab_trace,
     const double *__restrict__ tab_proj, int n_codes,
-    const T *__restrict__ U, T *__restrict__ rhs, T *__restrict__ buf) {
+    const T *__restrict__ U, T *__restrict__ rhs, T *__restrict__ buf, int remap) {
     constexpr int M = DIM + 2;
     constexpr int REC = M * NP;
     extern __shared__ unsigned char smem_raw[];
@@ -51,7 +62,7 @@ __global__ __launch_bounds__(256) void surface_kernel(
     }
     __syncthreads();
 
-    const int64_t k = f_begin + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t k = f_begin + (int64_t)logical_block(remap) * blockDim.x + threadIdx.x;
     if (k >= f_end) return;
 
     const int32_t L = face_lr[k];
@@ -188,13 +199,13 @@ __device__ __forceinline__ float team_bcast(float v, int k) {
 // team and every lane evaluates the flux of the full state; lane r then
 // projects component r.  Same arithmetic and accumulation modes as
 // surface_kernel.
-template <int DIM, int NP, int Q, int MODE, class T>
+template <int DIM, int NP, int Q, int MODE, class T, bool PREFETCH>
 __global__ __launch_bounds__(256) void surface_team_kernel(
     int64_t f_begin, int64_t f_end, int64_t n_face, int64_t n_elem,
     const int32_t *__restrict__ face_lr, const uint8_t *__restrict__ face_code,
     const double *__restrict__ face_geo, const double *__restrict__ tab_trace,
     const double *__restrict__ tab_proj, int n_codes,
-    const T *__restrict__ U, T *__restrict__ rhs, T *__restrict__ buf) {
+    const T *__restrict__ U, T *__restrict__ rhs, T *__restrict__ buf, int remap) {
     constexpr int M = DIM + 2;
     constexpr int REC = M * NP;
     constexpr int TEAM = M <= 4 ? 4 : 8;
@@ -209,7 +220,7 @@ __global__ __launch_bounds__(256) void surface_team_kernel(
     __syncthreads();
 
     const int r = threadIdx.x % TEAM;
-    const int64_t k = f_begin + ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / TEAM;
+    const int64_t k = f_begin + ((int64_t)logical_block(remap) * blockDim.x + threadIdx.x) / TEAM;
     if (k >= f_end) return;  // whole teams leave together
     const int32_t L = face_lr[k];
     const int32_t R = face_lr[n_face + k];
@@ -223,6 +234,20 @@ __global__ __launch_bounds__(256) void surface_team_kernel(
     const double isL = face_geo[(DIM + 1) * n_face + k];
     const double isR = face_geo[(DIM + 2) * n_face + k];
     const bool own = r < M;
+
+    // optionally issue the right-hand-side reads of a colored update up front,
+    // so that they are in flight together with the DOF reads
+    T pre_L[NP], pre_R[NP];
+    if (PREFETCH && MODE == kColored && own) {
+        const T *a = rhs + (size_t)L * REC + r * NP;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) pre_L[j] = a[j];
+        if (R >= 0) {
+            const T *b = rhs + (size_t)R * REC + r * NP;
+#pragma unroll
+            for (int j = 0; j < NP; ++j) pre_R[j] = b[j];
+        }
+    }
 
     // my variable's traces on both sides
     T tL[Q], tR[Q];
@@ -286,7 +311,7 @@ __global__ __launch_bounds__(256) void surface_team_kernel(
 #pragma unroll
             for (int q = 0; q < Q; ++q) a += pl[q * NP + j] * Fm[q];
             a *= sL;
-            if (MODE == kColored) dst[j] -= a;
+            if (MODE == kColored) dst[j] = (PREFETCH ? pre_L[j] : dst[j]) - a;
             else if (MODE == kAtomic) atomic_add<T>(dst + j, -a);
             else dst[j] = -a;
         }
@@ -301,7 +326,7 @@ __global__ __launch_bounds__(256) void surface_team_kernel(
 #pragma unroll
             for (int q = 0; q < Q; ++q) a += pr[q * NP + j] * Fm[q];
             a *= sR;
-            if (MODE == kColored) dst[j] += a;
+            if (MODE == kColored) dst[j] = (PREFETCH ? pre_R[j] : dst[j]) + a;
             else if (MODE == kAtomic) atomic_add<T>(dst + j, a);
             else dst[j] = a;
         }

@@ -83,7 +83,7 @@ def _volume_abs(d, U):
     return np.einsum("q,qdj,kqmd->kmj", d.vol_w, np.abs(d.vol_D), G) * sq[:, None, None]
 
 
-@pytest.mark.parametrize("form", ["team", "thread"])
+@pytest.mark.parametrize("form", ["team", "team_prefetch", "thread"])
 @pytest.mark.parametrize("p", [0, 1, 2, 3])
 @pytest.mark.parametrize("variant", ["colored", "atomic", "gather"])
 def test_surface_periodic_triangles(p, variant, form):
@@ -93,12 +93,14 @@ def test_surface_periodic_triangles(p, variant, form):
     _check(got, dg.surface_rhs(c.d, c.U), dg.surface_abs(c.d, c.U), "surface %s p=%d" % (variant, p))
 
 
-@pytest.mark.parametrize("form,block", [("team", 256), ("team", 64), ("thread", 256), ("thread", 128)])
+@pytest.mark.parametrize("form,block,xcd", [("team", 256, False), ("team", 64, False), ("team", 256, True),
+                                            ("team_prefetch", 256, False), ("team_prefetch", 128, True),
+                                            ("thread", 256, False), ("thread", 128, True)])
 @pytest.mark.parametrize("variant", ["colored", "atomic", "gather"])
-def test_surface_delaunay_walls_ragged(variant, form, block):
+def test_surface_delaunay_walls_ragged(variant, form, block, xcd):
     c = Case("delaunay", 12000, 2, 2)
     assert c.O.E % 256 != 0 and c.O.n_boundary > 0
-    c.D.set_launch(form, block)
+    c.D.set_launch(form, block, xcd)
     got = c.to_host(c.surface(variant))
     _check(got, dg.surface_rhs(c.d, c.U), dg.surface_abs(c.d, c.U), "surface delaunay " + variant)
 
@@ -125,6 +127,22 @@ def test_volume(kind, size, p):
     c.D.volume_rhs(c.Ug, rhs)
     torch.cuda.synchronize()
     _check(c.to_host(rhs), dg.volume_rhs(c.d, c.U), _volume_abs(c.d, c.U), "volume %s p=%d" % (kind, p))
+
+
+@pytest.mark.parametrize("layout", ["paper_sfc", "renumber", "none"])
+def test_surface_other_layouts(layout):
+    import torch
+
+    dgc = _dgc()
+    c = Case("delaunay", 9000, 3, 2)
+    c.M.set_colors(c.M.export("color"), layout=layout)
+    D = dgc.DeviceMesh(c.M, 2)
+    D.set_launch("team", 256, True)
+    Ug = torch.from_numpy(D.to_layout(c.U)).cuda()
+    rhs = torch.zeros_like(Ug)
+    D.surface_rhs(Ug, rhs)
+    torch.cuda.synchronize()
+    _check(D.from_layout(rhs.cpu().numpy()), dg.surface_rhs(c.d, c.U), dg.surface_abs(c.d, c.U), "layout " + layout)
 
 
 def test_surface_accumulates_onto_volume_term():
