@@ -27,6 +27,27 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+PROFILE = os.path.join(ROOT, "profiles", "surface_colored_team_prefetch_delaunay996k_p2_f64.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1601_07613_amd", "csrc", "kernels", f)
+                  for f in ("surface.hpp", "euler_dev.hpp")]
+
+
+def profiled_traffic():
+    """HBM bytes per launch measured by rocprofv3 counters for the committed
+    kernel, or None when the kernel source changed since the profile."""
+    import hashlib
+    import re
+
+    try:
+        text = open(PROFILE).read()
+    except OSError:
+        return None
+    h = hashlib.sha256(b"".join(open(f, "rb").read() for f in KERNEL_SOURCES)).hexdigest()[:16]
+    m_sha = re.search(r"kernel_source_sha256_16: ([0-9a-f]{16})", text)
+    m_tr = re.search(r"traffic_bytes_per_launch: (\d+)", text)
+    if not m_sha or not m_tr or m_sha.group(1) != h:
+        return None
+    return int(m_tr.group(1))
 
 
 def log(*a):
@@ -227,8 +248,12 @@ def main(argv=None):
             "layout": args.layout, "launch": best,
         },
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "algorithmic_bytes_per_pass": ab},
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": (profiled_traffic() if (args.p == 2 and args.points == 500_000 and args.seed == 2
+                                                        and args.layout == "paper") else None),
+                     "algorithmic_bytes_per_launch": ab // info["n_colors"],
+                     "launches_per_pass": info["n_colors"],
+                     "kernel": "surface_team_kernel (colored), one launch per color"},
         "cpu_baseline": cpu,
         "host_preprocess": {"generate_s": gen_s, "build_s": build_s, "color_ms": cst["color_ms"],
                             "layout_ms": cst["layout_ms"], "conflicts_after_greedy": cst["conflicts_after_greedy"]},

@@ -211,6 +211,8 @@ def check_coloring(mesh, color, n_colors: int | None = None) -> None:
     assert (color >= 0).all(), "uncolored faces remain"
     if n_colors is not None:
         assert (color < n_colors).all(), "color out of range"
-    per_elem = color[mesh.elem_face]
+    ef = mesh.elem_face
+    # padding slots (-1, refined meshes) get distinct negative placeholders
+    per_elem = np.where(ef >= 0, color[np.where(ef >= 0, ef, 0)], -1 - np.arange(ef.shape[1])[None, :])
     s = np.sort(per_elem, axis=1)
     assert not (s[:, 1:] == s[:, :-1]).any(), "an element has two faces of one color"

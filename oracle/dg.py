@@ -62,21 +62,10 @@ class Discretization:
         self.phi0 = float(basis.eval_basis(self.dim, 0, self.vol_pts[:1])[0, 0])
         self._face_cache = {}
 
-    def face_local_positions(self, side: int) -> np.ndarray:
-        """``[E, nfv]`` local vertex index, in the element on ``side``, of each face vertex."""
-        mesh = self.mesh
-        e = mesh.face_elem[:, side]
-        ev = mesh.elem_vert[np.where(e >= 0, e, 0)]
-        match = ev[:, None, :] == mesh.face_vert[:, :, None]
-        pos = np.argmax(match, axis=2)
-        pos[e < 0] = 0
-        return pos
-
     def face_basis(self, side: int) -> np.ndarray:
         """``[E, Q, Np]`` basis values at the face quadrature points seen from ``side``."""
         if side not in self._face_cache:
-            pos = self.face_local_positions(side)
-            ref = basis.REF_VERTS[self.dim][pos]                   # [E, nfv, dim]
+            ref = self.mesh.face_ref[:, side]                       # [E, nfv, dim]
             pts = np.einsum("qv,evd->eqd", self.face_bary, ref)     # [E, Q, dim]
             E, Q, _ = pts.shape
             self._face_cache[side] = basis.eval_basis(self.dim, self.p, pts.reshape(E * Q, -1)).reshape(

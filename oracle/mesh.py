@@ -22,7 +22,8 @@ none):
 * each face stores its vertex ids in ``L``'s order; quadrature points are
   placed by barycentric weights on these vertices, and each side maps them
   to its own reference coordinates through the position of the vertex ids
-  in its own element.
+  in its own element (``face_ref``; refined meshes set it directly, with a
+  coarse side seeing a half edge).
 
 Pins (``tests/test_oracle_mesh.py``): ``E = 3K/2`` on closed triangle
 meshes and ``E = 2K`` on closed tetrahedral ones; Euler's formula on the
@@ -66,6 +67,8 @@ class Mesh:
     detJ: np.ndarray           # [K]
     Jinv: np.ndarray           # [K, dim, dim], Jinv[d, e] = d xi_d / d x_e
     elem_measure: np.ndarray   # [K]
+    face_ref: np.ndarray = None  # [E, 2, nfv, dim]: reference coordinates, seen from L / R,
+    #                              of the face's vertices taken in L's order
 
     @property
     def n_boundary(self) -> int:
@@ -142,6 +145,17 @@ def build_mesh(elem_vert, elem_xyz) -> Mesh:
         flip = np.einsum("ij,ij->i", P[:, 0] - opp, normal) < 0
         normal[flip] *= -1.0
         measure = 0.5 * ar
+    # reference coordinates of the face vertices (L's order) on each side:
+    # the position of each vertex id inside the side's element
+    ref = REF_VERTS[dim]
+    face_ref = np.zeros((E, 2, dim, dim))
+    for side in (0, 1):
+        e = face_elem[:, side]
+        has = e >= 0
+        evs = ev[np.where(has, e, 0)]
+        pos = np.argmax(evs[:, None, :] == face_vert[:, :, None], axis=2)
+        face_ref[:, side] = np.where(has[:, None, None], ref[pos], 0.0)
     return Mesh(dim=dim, K=K, E=E, elem_vert=ev, elem_xyz=xyz, face_elem=face_elem,
                 face_local=face_local, face_vert=face_vert, elem_face=elem_face,
-                normal=normal, measure=measure, detJ=detJ, Jinv=Jinv, elem_measure=elem_measure)
+                normal=normal, measure=measure, detJ=detJ, Jinv=Jinv, elem_measure=elem_measure,
+                face_ref=face_ref)

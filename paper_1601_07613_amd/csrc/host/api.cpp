@@ -48,11 +48,13 @@ dgc_status dgc_mesh_build(int32_t elem_type, int64_t n_elem, const int32_t *elem
         m.elem_vert.assign(elem_vert, elem_vert + n_elem * m.nv);
         m.elem_xyz.assign(elem_xyz, elem_xyz + n_elem * m.nv * m.dim);
         m.elem_level.assign(n_elem, 0);
+        m.n_vert = 0;
         for (int64_t i = 0; i < n_elem * m.nv; ++i) {
             if (m.elem_vert[i] < 0) {
                 delete h;
                 return fail(DGC_E_ARG, "dgc_mesh_build: negative vertex id");
             }
+            if (m.elem_vert[i] + 1 > m.n_vert) m.n_vert = m.elem_vert[i] + 1;
         }
         dgc_status s = dgc::build_faces(m);
         if (s != DGC_OK) {

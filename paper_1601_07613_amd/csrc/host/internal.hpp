@@ -49,10 +49,21 @@ struct Mesh {
     // by the child-color map; -1 when not recorded
     std::vector<int32_t> edge_start;  // [E]
     int max_level = 0;
+
+    // edge tree of a refined triangle mesh (empty for a conforming base)
+    struct EdgeNode {
+        int32_t start, end, color, child0, child1, parent, mid;
+    };
+    std::vector<EdgeNode> nodes;
+    std::vector<int32_t> leaf_edge;   // [K][3] node of each local edge
+    int64_t n_vert = 0;               // vertex ids in use
 };
 
 // mesh_build.cpp
 dgc_status build_faces(Mesh &m);        // face table + geometry from elem_vert / elem_xyz
+dgc_status elem_geometry(Mesh &m);      // detJ, J^-1 of every element
+dgc_status face_geometry(Mesh &m);      // normal (from the left element) and measure of every face
+int face_vertex(const Mesh &m, int local_face, int k);
 // coloring.cpp
 dgc_status color_paper(Mesh &m, uint64_t seed, int64_t max_swaps, dgc_color_stats *st);
 dgc_status color_greedy_std(Mesh &m, dgc_color_stats *st);

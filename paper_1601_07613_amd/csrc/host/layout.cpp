@@ -22,8 +22,6 @@
 
 namespace dgc {
 
-int face_vertex(const Mesh &m, int local_face, int k);
-
 namespace {
 
 // Morton code of each listed face's midpoint (taken from its left element's

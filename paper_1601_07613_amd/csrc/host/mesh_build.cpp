@@ -34,10 +34,9 @@ int face_vertex(const Mesh &m, int local_face, int k) {
     return m.dim == 2 ? kTriFace[local_face][k] : kTetFace[local_face][k];
 }
 
-dgc_status build_faces(Mesh &m) {
-    const int nv = m.nv, F = m.F, dim = m.dim, nfv = dim;
+dgc_status elem_geometry(Mesh &m) {
+    const int nv = m.nv, dim = m.dim;
     const int64_t K = m.K;
-
     // element Jacobians
     m.detJ.assign(K, 0.0);
     m.Jinv.assign(K * dim * dim, 0.0);
@@ -75,6 +74,53 @@ dgc_status build_faces(Mesh &m) {
             Ji[8] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
         }
     }
+
+    return DGC_OK;
+}
+
+dgc_status face_geometry(Mesh &m) {
+    const int nv = m.nv, dim = m.dim;
+    const int64_t E = m.E;
+    // face geometry from the left element's own coordinates
+    m.normal.assign(E * dim, 0.0);
+    m.measure.assign(E, 0.0);
+    for (int64_t f = 0; f < E; ++f) {
+        const int64_t L = m.face_L[f];
+        const int fL = m.face_fL[f];
+        const double *x = &m.elem_xyz[L * nv * dim];
+        if (dim == 2) {
+            const double *a = x + 2 * kTriFace[fL][0];
+            const double *b = x + 2 * kTriFace[fL][1];
+            double tx = b[0] - a[0], ty = b[1] - a[1];
+            double len = std::hypot(tx, ty);
+            m.measure[f] = len;
+            m.normal[2 * f] = ty / len;
+            m.normal[2 * f + 1] = -tx / len;
+        } else {
+            const double *p0 = x + 3 * kTetFace[fL][0];
+            const double *p1 = x + 3 * kTetFace[fL][1];
+            const double *p2 = x + 3 * kTetFace[fL][2];
+            double u[3] = {p1[0] - p0[0], p1[1] - p0[1], p1[2] - p0[2]};
+            double v[3] = {p2[0] - p0[0], p2[1] - p0[1], p2[2] - p0[2]};
+            double c[3] = {u[1] * v[2] - u[2] * v[1], u[2] * v[0] - u[0] * v[2], u[0] * v[1] - u[1] * v[0]};
+            double ar = std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+            double cen[3] = {0, 0, 0};
+            for (int a = 0; a < 4; ++a)
+                for (int e = 0; e < 3; ++e) cen[e] += 0.25 * x[3 * a + e];
+            double s = (p0[0] - cen[0]) * c[0] + (p0[1] - cen[1]) * c[1] + (p0[2] - cen[2]) * c[2];
+            double sg = s < 0 ? -1.0 : 1.0;
+            for (int e = 0; e < 3; ++e) m.normal[3 * f + e] = sg * c[e] / ar;
+            m.measure[f] = 0.5 * ar;
+        }
+    }
+    return DGC_OK;
+}
+
+dgc_status build_faces(Mesh &m) {
+    const int nv = m.nv, F = m.F, dim = m.dim, nfv = dim;
+    const int64_t K = m.K;
+
+    if (dgc_status g = elem_geometry(m); g != DGC_OK) return g;
 
     // face matching
     std::vector<FaceRec> rec(K * F);
@@ -148,38 +194,7 @@ dgc_status build_faces(Mesh &m) {
         }
     }
 
-    // face geometry from the left element's own coordinates
-    m.normal.assign(E * dim, 0.0);
-    m.measure.assign(E, 0.0);
-    for (int64_t f = 0; f < E; ++f) {
-        const int64_t L = m.face_L[f];
-        const int fL = m.face_fL[f];
-        const double *x = &m.elem_xyz[L * nv * dim];
-        if (dim == 2) {
-            const double *a = x + 2 * kTriFace[fL][0];
-            const double *b = x + 2 * kTriFace[fL][1];
-            double tx = b[0] - a[0], ty = b[1] - a[1];
-            double len = std::hypot(tx, ty);
-            m.measure[f] = len;
-            m.normal[2 * f] = ty / len;
-            m.normal[2 * f + 1] = -tx / len;
-        } else {
-            const double *p0 = x + 3 * kTetFace[fL][0];
-            const double *p1 = x + 3 * kTetFace[fL][1];
-            const double *p2 = x + 3 * kTetFace[fL][2];
-            double u[3] = {p1[0] - p0[0], p1[1] - p0[1], p1[2] - p0[2]};
-            double v[3] = {p2[0] - p0[0], p2[1] - p0[1], p2[2] - p0[2]};
-            double c[3] = {u[1] * v[2] - u[2] * v[1], u[2] * v[0] - u[0] * v[2], u[0] * v[1] - u[1] * v[0]};
-            double ar = std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
-            double cen[3] = {0, 0, 0};
-            for (int a = 0; a < 4; ++a)
-                for (int e = 0; e < 3; ++e) cen[e] += 0.25 * x[3 * a + e];
-            double s = (p0[0] - cen[0]) * c[0] + (p0[1] - cen[1]) * c[1] + (p0[2] - cen[2]) * c[2];
-            double sg = s < 0 ? -1.0 : 1.0;
-            for (int e = 0; e < 3; ++e) m.normal[3 * f + e] = sg * c[e] / ar;
-            m.measure[f] = 0.5 * ar;
-        }
-    }
+    if (dgc_status g = face_geometry(m); g != DGC_OK) return g;
     m.edge_start.assign(E, -1);
     if (dim == 2)
         for (int64_t f = 0; f < E; ++f)

@@ -243,3 +243,12 @@ def element_measure(elem_xyz: np.ndarray) -> np.ndarray:
 
 def element_centroid(elem_xyz: np.ndarray) -> np.ndarray:
     return np.asarray(elem_xyz, dtype=np.float64).mean(axis=1)
+
+
+def refine_flags(elem_xyz: np.ndarray, levels: np.ndarray, level: int, center=(0.5, 0.5),
+                 radius: float = 0.15) -> np.ndarray:
+    """Refinement criterion of the adaptive workload: leaves of ``level`` whose
+    centroid lies within ``radius`` of ``center``."""
+    c = np.asarray(elem_xyz, dtype=np.float64).mean(axis=1)
+    d = np.hypot(c[:, 0] - center[0], c[:, 1] - center[1])
+    return (np.asarray(levels) == level) & (d < radius)

@@ -273,3 +273,128 @@ def test_full_size_sampled(full_c1):
     other = c.to_host(c.surface("colored"))
     c.D.set_launch("default")
     _check(other, got, dg.surface_abs(c.d, c.U), "full-size thread form vs team form")
+
+
+# ---------------------------------------------------------------- FP32 form
+
+TOL32 = 2e-6
+
+
+@pytest.mark.parametrize("kind,size,p", [("periodic", 16, 2), ("delaunay", 6000, 2), ("tets", 5, 1)])
+@pytest.mark.parametrize("variant", ["colored", "atomic"])
+def test_surface_and_volume_f32(kind, size, p, variant):
+    """f32 storage and arithmetic (geometry stored in f64) against the f64
+    oracle evaluated on the same f32-rounded DOFs."""
+    import torch
+
+    c = Case(kind, size, 12, p)
+    U32 = c.U.astype(np.float32)
+    U = U32.astype(np.float64)
+    Ug = torch.from_numpy(c.D.to_layout(U32)).cuda()
+    rhs = torch.zeros_like(Ug)
+    c.D.surface_rhs(Ug, rhs, variant=variant, precision="f32")
+    vol = torch.zeros_like(Ug)
+    c.D.volume_rhs(Ug, vol, precision="f32")
+    torch.cuda.synchronize()
+    _check32 = lambda got, ref, scale, what: _check_tol(got, ref, scale, what, TOL32)
+    _check32(c.D.from_layout(rhs.cpu().numpy()).astype(np.float64), dg.surface_rhs(c.d, U),
+             dg.surface_abs(c.d, U), "f32 surface")
+    _check32(c.D.from_layout(vol.cpu().numpy()).astype(np.float64), dg.volume_rhs(c.d, U),
+             _volume_abs(c.d, U), "f32 volume")
+
+
+def _check_tol(got, ref, scale, what, tol):
+    s = np.asarray(scale).max(axis=(0, 2))
+    diff = np.abs(got - ref).max(axis=(0, 2))
+    err = np.where(s > 0, diff / np.where(s > 0, s, 1.0), np.where(diff == 0, 0.0, np.inf))
+    assert err.max() <= tol, "%s: relative error per variable %s" % (what, err)
+
+
+def test_rk3_f32_form_error_budget():
+    """100 SSP-RK3 steps of the 16 x 16 vortex with the f32 form (f32 shadow,
+    f32 flux and quadrature, f64 stage accumulation): relative L2 error of
+    every variable against the f64 oracle stays below 1e-6."""
+    import torch
+
+    m = make_input("periodic", 16, 1)
+    O = build_mesh(m["elem_vert"], m["elem_xyz"])
+    d = dg.Discretization(O, 1)
+    U0 = dg.project(d, lambda X: synth.isentropic_vortex(X, 0.0))
+    dt = dg.cfl_dt(d, U0, 0.1)
+    dgc = _dgc()
+    M = dgc.Mesh.build(m["elem_vert"], m["elem_xyz"])
+    M.color(seed=1)
+    D = dgc.DeviceMesh(M, 1)
+    Ug = torch.from_numpy(D.to_layout(U0)).cuda()
+    ws = D.workspace("rk", "colored", "f32")
+    U = U0.copy()
+    for _ in range(100):
+        D.rk_step(Ug, dt, precision="f32", ws=ws)
+        U = dg.rk3_step(d, U, dt)
+    torch.cuda.synchronize()
+    got = D.from_layout(Ug.cpu().numpy())
+    # by orthonormality the L2 norm of a field is the Euclidean norm of its DOFs
+    rel = np.sqrt(((got - U) ** 2).sum(axis=(0, 2)) / (U ** 2).sum(axis=(0, 2)))
+    print("f32 form relative L2 error per variable:", rel)
+    assert rel.max() <= 1e-6, rel
+
+
+# ------------------------------------------------- nonconforming (refined) mesh
+
+def _refined(n=24, levels=3, radius=0.15, p=2, cseed=0):
+    from oracle import refine as R
+    from oracle.coloring import color_faces
+
+    dgc = _dgc()
+    m = synth.periodic_tri(n, jitter=0.0, seed=4)
+    O = build_mesh(m["elem_vert"], m["elem_xyz"])
+    col, _ = color_faces(O, seed=cseed)
+    st = R.from_base(O, col)
+    M = dgc.Mesh.build(m["elem_vert"], m["elem_xyz"])
+    M.color(seed=cseed)
+    for lvl in range(1, levels + 1):
+        xyz = np.array([lf.xyz for lf in st.leaves])
+        lev = np.array([lf.level for lf in st.leaves])
+        flags = synth.refine_flags(xyz, lev, lvl - 1, radius=radius)
+        st, _ = R.refine(st, flags)
+        M, _ = M.refine(flags)
+    mesh, color, orient, levels_ = R.to_mesh(st)
+    d = dg.Discretization(mesh, p)
+    D = dgc.DeviceMesh(M, p)
+    print("refined mesh K", mesh.K, "E", mesh.E, "hanging", int((orient[:, 1] >= 2).sum()), flush=True)
+    return mesh, d, D
+
+
+@pytest.mark.parametrize("variant", ["colored", "atomic", "gather"])
+@pytest.mark.parametrize("form", ["default", "thread"])
+def test_surface_refined_six_colors(variant, form):
+    import torch
+
+    mesh, d, D = _refined()
+    assert D.info["n_colors"] == 6 and D.info["max_slots"] >= 5
+    D.set_launch(form)
+    U = synth.perturbed_dofs(mesh.elem_measure, synth.shock_tube_states(mesh.elem_xyz.mean(axis=1)), d.n_p,
+                             eps=0.02, seed=21)
+    Ug = torch.from_numpy(D.to_layout(U)).cuda()
+    rhs = torch.zeros_like(Ug)
+    ws = D.workspace("surface", variant) if variant == "gather" else None
+    D.surface_rhs(Ug, rhs, variant=variant, ws=ws)
+    torch.cuda.synchronize()
+    _check(D.from_layout(rhs.cpu().numpy()), dg.surface_rhs(d, U), dg.surface_abs(d, U), "refined " + variant)
+
+
+def test_rk3_refined_vortex_20_steps():
+    import torch
+
+    mesh, d, D = _refined(n=16, levels=2, radius=0.2, p=2)
+    U0 = dg.project(d, lambda X: synth.isentropic_vortex(X, 0.0))
+    dt = dg.cfl_dt(d, U0, 0.1)
+    Ug = torch.from_numpy(D.to_layout(U0)).cuda()
+    ws = D.workspace("rk", "colored")
+    U = U0.copy()
+    for _ in range(20):
+        D.rk_step(Ug, dt, ws=ws)
+        U = dg.rk3_step(d, U, dt)
+    torch.cuda.synchronize()
+    got = D.from_layout(Ug.cpu().numpy())
+    assert np.abs(got - U).max() / np.abs(U).max() <= TOL
