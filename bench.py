@@ -80,6 +80,94 @@ def timed(fn, steps, warmup, stream):
     return t0.elapsed_time(t1) / steps, wall
 
 
+def extra_workloads(dgc, synth, torch, steps, warmup, log):
+    """The other configurations, reported beside the headline: small periodic
+    mesh latency (c0), periodic Kuhn tetrahedra in f64 and f32 with the f32
+    form's error (c2), the adaptively refined nonconforming mesh (c3)."""
+    from paper_1601_07613_amd.tune import time_call
+
+    out = {}
+    stream = torch.cuda.current_stream()
+
+    def surf_stats(D, K, E, nb, elt, precision):
+        U = torch.zeros((K, D.n_var, D.n_p), dtype=torch.float64 if elt == 8 else torch.float32, device="cuda")
+        U[:, 0, 0] = 1.0
+        U[:, -1, 0] = 2.5
+        rhs = torch.zeros_like(U)
+        ms = time_call(lambda: D.surface_rhs(U, rhs, "colored", precision), reps=steps, warmup=warmup)
+        ab = algorithmic_bytes(E, E - nb, D.n_var * D.n_p, elt, D.dim)
+        return {"colored_us": ms * 1e3, "dof_updates_per_s": K * D.n_var * D.n_p / (ms * 1e-3),
+                "algorithmic_GBs": ab / (ms * 1e-3) / 1e9, "frac_of_8TBs": ab / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+    # c0: 16 x 16 x 2 periodic triangles, p = 1 (latency-bound)
+    m = synth.periodic_tri(16, seed=1)
+    M = dgc.Mesh.build(m["elem_vert"], m["elem_xyz"])
+    M.color(seed=1)
+    D = dgc.DeviceMesh(M, 1)
+    U = torch.zeros((D.K, 4, D.n_p), dtype=torch.float64, device="cuda")
+    U[:, 0, 0] = 0.1
+    U[:, 3, 0] = 0.25
+    rhs = torch.zeros_like(U)
+    ws = D.workspace("rk", "colored")
+    out["c0_periodic512_p1"] = {
+        "surface_pass_us": time_call(lambda: D.surface_rhs(U, rhs), reps=200, warmup=20) * 1e3,
+        "rk3_step_us": time_call(lambda: D.rk_step(U, 1e-9, ws=ws), reps=100, warmup=10) * 1e3,
+    }
+    log("c0: %s" % out["c0_periodic512_p1"])
+
+    # c2: 64^3 x 6 periodic Kuhn tetrahedra, p = 1, f64 and f32
+    t = synth.kuhn_tets(64, seed=3)
+    T = dgc.Mesh.build(t["elem_vert"], t["elem_xyz"])
+    cs = T.color(seed=0)
+    DT = dgc.DeviceMesh(T, 1)
+    info = DT.info
+    r64 = surf_stats(DT, info["n_elem"], info["n_face"], info["n_boundary"], 8, "f64")
+    r32 = surf_stats(DT, info["n_elem"], info["n_face"], info["n_boundary"], 4, "f32")
+    # f32 form error: 10 SSP-RK3 steps of the density wave from the same state
+    meas = synth.element_measure(t["elem_xyz"])
+    st = synth.density_wave_states(synth.element_centroid(t["elem_xyz"]))
+    U0 = synth.perturbed_dofs(meas, st, DT.n_p, eps=0.0)
+    h = 1.0 / 64
+    dt = 0.1 * 0.2 * h / (3 ** 0.5 + 1.2)
+    Ua = torch.from_numpy(DT.to_layout(U0)).cuda()
+    Ub = Ua.clone()
+    wa = DT.workspace("rk", "colored", "f64")
+    wb = DT.workspace("rk", "colored", "f32")
+    for _ in range(10):
+        DT.rk_step(Ua, dt, precision="f64", ws=wa)
+        DT.rk_step(Ub, dt, precision="f32", ws=wb)
+    torch.cuda.synchronize()
+    diff = ((Ub - Ua) ** 2).sum(dim=(0, 2)).sqrt() / (Ua ** 2).sum(dim=(0, 2)).sqrt()
+    rk64 = time_call(lambda: DT.rk_step(Ua, dt, precision="f64", ws=wa), reps=5, warmup=1)
+    rk32 = time_call(lambda: DT.rk_step(Ub, dt, precision="f32", ws=wb), reps=5, warmup=1)
+    out["c2_kuhn64_tets_p1"] = {
+        "n_elem": info["n_elem"], "n_face": info["n_face"], "n_colors": info["n_colors"],
+        "color_ms": cs["color_ms"], "f64": r64, "f32": r32,
+        "rk3_step_us": {"f64": rk64 * 1e3, "f32_form": rk32 * 1e3},
+        "f32_form_rel_L2_after_10_steps": [float(x) for x in diff.cpu()],
+    }
+    log("c2: %s" % out["c2_kuhn64_tets_p1"])
+    del DT, T, Ua, Ub, wa, wb
+
+    # c3: 128 x 128 x 2 periodic base refined to level 3 within r < 0.15, p = 2
+    m = synth.periodic_tri(128, jitter=0.0, seed=4)
+    A = dgc.Mesh.build(m["elem_vert"], m["elem_xyz"])
+    A.color(seed=0)
+    t0 = time.perf_counter()
+    for lvl in range(1, 4):
+        xyz = A.export("elem_xyz").reshape(-1, 3, 2)
+        lev = A.export("elem_level")
+        A, _ = A.refine(synth.refine_flags(xyz, lev, lvl - 1, radius=0.15))
+    refine_s = time.perf_counter() - t0
+    DA = dgc.DeviceMesh(A, 2)
+    info = DA.info
+    r = surf_stats(DA, info["n_elem"], info["n_face"], info["n_boundary"], 8, "f64")
+    out["c3_amr_level3_p2"] = {"n_elem": info["n_elem"], "n_face": info["n_face"], "n_colors": info["n_colors"],
+                               "refine_s": refine_s, "f64": r}
+    log("c3: %s" % out["c3_amr_level3_p2"])
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -198,6 +286,13 @@ def main(argv=None):
                                                         args.warmup, stream)[0] * 1e3
             del D2, Ug2, rhs2
         M.set_colors(colors, layout=args.layout)
+        # the f32 form of the same pass (f32 records, f64 geometry)
+        U32 = Ug.float()
+        r32 = torch.zeros_like(U32)
+        ms32 = time_call(lambda: D.surface_rhs(U32, r32, "colored", "f32"), reps=args.steps, warmup=args.warmup)
+        extra["colored_f32_us"] = ms32 * 1e3
+        extra["colored_f32_algorithmic_GBs"] = algorithmic_bytes(E, E - nb, rec, 4, D.dim) / (ms32 * 1e-3) / 1e9
+        del U32, r32
         # measured streaming reference: device copy of 1 GiB
         n = (1 << 30) // 8
         a = torch.ones(n, dtype=torch.float64, device="cuda")
@@ -207,6 +302,10 @@ def main(argv=None):
         del a, b
         for k2, v in extra.items():
             log("%s: %.2f" % (k2, v))
+
+    workloads = None
+    if args.only == "all":
+        workloads = extra_workloads(dgc, synth, torch, args.steps, args.warmup, log)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -258,6 +357,7 @@ def main(argv=None):
         "host_preprocess": {"generate_s": gen_s, "build_s": build_s, "color_ms": cst["color_ms"],
                             "layout_ms": cst["layout_ms"], "conflicts_after_greedy": cst["conflicts_after_greedy"]},
         "variants_us": extra,
+        "other_workloads": workloads,
     }
     print(json.dumps(out))
     return 0
