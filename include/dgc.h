@@ -287,6 +287,45 @@ enum { DGC_WS_SURFACE = 0, DGC_WS_RK_STEP = 1 };
 dgc_status dgc_workspace_bytes(const dgc_dmesh *dm, int32_t what, int32_t variant, int32_t precision,
                                size_t *bytes);
 
+/* Layout of the dgc_rk_step workspace for n = n_elem * n_var * n_p values:
+ * byte offsets of the stage states U1, U2 (f64), the stage right-hand side
+ * (f64, or f32 for DGC_F32) and, for DGC_F32, the f32 shadow of the stage
+ * state (off[3] is 0 otherwise); each part starts on a 256-byte boundary.
+ * *total is the size of that part of the workspace (a GATHER buffer follows
+ * it).  Lets a caller read the stage right-hand side, e.g. after a batched
+ * volume + surface evaluation. */
+dgc_status dgc_rk_workspace_layout(int64_t n, int32_t precision, size_t off[4], size_t *total);
+
+/* ---------------------------------------------------------------------- */
+/* Batched forms: many meshes of one element type and order per launch      */
+/* ---------------------------------------------------------------------- */
+
+/* Describe a batch of n_mesh meshes (same element type and order, each
+ * colored) so that one launch per color covers all of them: meshes are
+ * disjoint, so the union of their color-c faces is race-free (Algorithm 1).
+ * Writes a descriptor (header, one entry per mesh with its device pointers,
+ * and per-launch work-group -> mesh maps) into host_desc; the caller copies
+ * the same bytes to device memory and passes both copies to the batched
+ * calls.  U[i] is mesh i's f64 state, ws[i] its dgc_rk_step workspace
+ * (DGC_WS_RK_STEP bytes for `precision`), dt[i] its time step.  Call with
+ * host_desc = NULL to get the size.  The descriptor stays valid while the
+ * pointed-to buffers live; rebuild it when the batch membership or a dt
+ * changes.  Errors: DGC_E_ARG, DGC_E_NOT_COLORED, DGC_E_UNSUPPORTED. */
+dgc_status dgc_batch_describe(int32_t n_mesh, const dgc_dmesh *meshes, double *const *U, void *const *ws,
+                              const double *dt, int32_t precision, void *host_desc, size_t bytes, size_t *needed);
+
+/* Surface / volume term of every mesh of the batch for SSP-RK3 stage `stage`
+ * (0: input U, 1: U1, 2: U2; the f32 form reads the f32 shadow), accumulated
+ * into / written to each mesh's stage right-hand side in its workspace. */
+dgc_status dgc_surface_rhs_batched(const void *host_desc, const void *dev_desc, int32_t stage, void *stream);
+dgc_status dgc_volume_rhs_batched(const void *host_desc, const void *dev_desc, int32_t stage, void *stream);
+
+/* One SSP-RK3 step of every mesh of the batch with its own dt: a fixed
+ * sequence of 3 x (volume + one launch per color + combine) launches (plus
+ * one for the f32 shadow), independent of the number of meshes, so it can be
+ * captured once in a graph and replayed. */
+dgc_status dgc_rk_step_batched(const void *host_desc, const void *dev_desc, void *stream);
+
 /* Library build identification (static string). */
 const char *dgc_version(void);
 

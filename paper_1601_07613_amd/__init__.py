@@ -219,3 +219,93 @@ class DeviceMesh:
         _lib.check(_L.dgc_rk_step(C.byref(self.dm), U.data_ptr(), float(dt), VARIANTS[variant],
                                   PRECISIONS[precision], ws.data_ptr(), ws.numel(), _stream_ptr(stream)),
                    "dgc_rk_step")
+
+
+def rk_workspace_layout(n: int, precision: str = "f64"):
+    """Byte offsets (U1, U2, rhs, shadow) and size of the RK-stage workspace of ``n`` values."""
+    off = (C.c_size_t * 4)()
+    tot = C.c_size_t()
+    _lib.check(_L.dgc_rk_workspace_layout(n, PRECISIONS[precision], off, C.byref(tot)), "dgc_rk_workspace_layout")
+    return [int(x) for x in off], int(tot.value)
+
+
+class Batch:
+    """Many meshes of one element type and order advanced together.
+
+    ``members`` is a list of ``(DeviceMesh, U, ws, dt)``: the f64 state, the
+    RK workspace (``DeviceMesh.workspace("rk", ..., precision)``) and the time
+    step of each mesh.  The descriptor is built by the library on the host and
+    copied to the device once; every batched call launches a fixed number of
+    kernels whatever the number of meshes.
+    """
+
+    def __init__(self, members, precision: str = "f64", device="cuda"):
+        import torch
+
+        self.members = list(members)
+        self.precision = precision
+        n = len(self.members)
+        self._dms = (_lib.DMesh * n)(*[m[0].dm for m in self.members])
+        self._U = (C.c_void_p * n)(*[m[1].data_ptr() for m in self.members])
+        self._ws = (C.c_void_p * n)(*[m[2].data_ptr() for m in self.members])
+        self._dt = (C.c_double * n)(*[float(m[3]) for m in self.members])
+        need = C.c_size_t()
+        _lib.check(_L.dgc_batch_describe(n, self._dms, self._U, self._ws, self._dt, PRECISIONS[precision], None, 0,
+                                         C.byref(need)), "dgc_batch_describe")
+        self.host = np.zeros(need.value, dtype=np.uint8)
+        _lib.check(_L.dgc_batch_describe(n, self._dms, self._U, self._ws, self._dt, PRECISIONS[precision],
+                                         _ptr(self.host), self.host.nbytes, None), "dgc_batch_describe")
+        self.dev = torch.from_numpy(self.host).to(device)
+
+    def set_dt(self, dts) -> None:
+        """Change the time steps in place (same descriptor size; safe between graph replays)."""
+        for i, v in enumerate(dts):
+            self._dt[i] = float(v)
+        n = len(self.members)
+        _lib.check(_L.dgc_batch_describe(n, self._dms, self._U, self._ws, self._dt, PRECISIONS[self.precision],
+                                         _ptr(self.host), self.host.nbytes, None), "dgc_batch_describe")
+        self.dev.copy_(torch_from(self.host), non_blocking=False)
+
+    def surface(self, stage: int = 0, stream=None):
+        _lib.check(_L.dgc_surface_rhs_batched(_ptr(self.host), self.dev.data_ptr(), stage, _stream_ptr(stream)),
+                   "dgc_surface_rhs_batched")
+
+    def volume(self, stage: int = 0, stream=None):
+        _lib.check(_L.dgc_volume_rhs_batched(_ptr(self.host), self.dev.data_ptr(), stage, _stream_ptr(stream)),
+                   "dgc_volume_rhs_batched")
+
+    def rk_step(self, stream=None):
+        _lib.check(_L.dgc_rk_step_batched(_ptr(self.host), self.dev.data_ptr(), _stream_ptr(stream)),
+                   "dgc_rk_step_batched")
+
+    def stage_rhs(self, i: int):
+        """View of member ``i``'s stage right-hand side inside its workspace."""
+        D, U, ws, _ = self.members[i]
+        n = D.K * D.n_var * D.n_p
+        off, _ = rk_workspace_layout(n, self.precision)
+        import torch
+
+        dt = torch.float64 if self.precision == "f64" else torch.float32
+        elt = 8 if self.precision == "f64" else 4
+        return ws[off[2]:off[2] + n * elt].view(dt).view(D.K, D.n_var, D.n_p)
+
+    def capture(self, steps: int = 1):
+        """Capture ``steps`` batched RK3 steps in a graph; returns the graph (replay with ``.replay()``)."""
+        import torch
+
+        # load the kernels before capturing: stage-0 volume + surface only
+        # write the stage right-hand side (workspace), never the state
+        self.volume(0)
+        self.surface(0)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for _ in range(steps):
+                self.rk_step()
+        return g
+
+
+def torch_from(a: np.ndarray):
+    import torch
+
+    return torch.from_numpy(a)

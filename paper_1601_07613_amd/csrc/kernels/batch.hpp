@@ -1,0 +1,101 @@
+// Batched launches: many meshes of one element type and order per launch.
+//
+// Every work-group reads its mesh from the descriptor's block map (one
+// uniform load), then does exactly the per-face / per-element / per-DOF work
+// of the single-mesh kernels on that mesh's arrays.  Meshes are disjoint, so
+// one launch per color stays race-free (Algorithm 1 applied to the union of
+// the meshes), and a mesh's results do not depend on the other members of
+// the batch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "../batch_desc.hpp"
+#include "surface.hpp"
+#include "volume.hpp"
+
+namespace dgc_dev {
+
+using dgc_batch::Entry;
+using dgc_batch::Header;
+
+__device__ __forceinline__ const Header *bh(const char *desc) { return reinterpret_cast<const Header *>(desc); }
+
+__device__ __forceinline__ const Entry *bentry(const char *desc, int32_t m) {
+    return reinterpret_cast<const Entry *>(desc + bh(desc)->off_entries) + m;
+}
+
+// stage input of the face and volume work: the state (stage 0), U1, U2; the
+// f32 form always reads the f32 shadow of the current stage state
+template <class T>
+__device__ __forceinline__ const T *stage_input(const Entry *e, const dgc_batch::RkWs &w, int stage);
+template <>
+__device__ __forceinline__ const double *stage_input<double>(const Entry *e, const dgc_batch::RkWs &w, int stage) {
+    return stage == 0 ? e->U : (stage == 1 ? w.U1 : w.U2);
+}
+template <>
+__device__ __forceinline__ const float *stage_input<float>(const Entry *, const dgc_batch::RkWs &w, int) {
+    return w.shadow;
+}
+
+template <int DIM, int NP, int Q, class T>
+__global__ __launch_bounds__(256) void batch_surface_kernel(const char *__restrict__ desc, int color, int stage) {
+    constexpr int TEAM = DIM + 2 <= 4 ? 4 : 8;
+    const Header *h = bh(desc);
+    extern __shared__ unsigned char smem_raw[];
+    T *s_tr = reinterpret_cast<T *>(smem_raw);
+    T *s_pr = s_tr + h->n_codes * Q * NP;
+    stage_tables<T>(s_tr, s_pr, h->tables + h->off_trace, h->tables + h->off_proj, h->n_codes * Q * NP);
+    const int32_t m = reinterpret_cast<const int32_t *>(desc + h->off_map_face[color])[blockIdx.x];
+    const Entry *e = bentry(desc, m);
+    const int64_t local = (int64_t)blockIdx.x - e->blk_face[color];
+    const int64_t k = e->color_off[color] + (local * blockDim.x + threadIdx.x) / TEAM;
+    if (k >= e->color_off[color + 1]) return;
+    const dgc_batch::RkWs w = dgc_batch::rk_ws(e->ws, (size_t)e->n_dof, sizeof(T) == 4);
+    team_face<DIM, NP, Q, kColored, T, true>(k, threadIdx.x % TEAM, e->n_face, e->n_elem, e->face_lr, e->face_code,
+                                             e->face_geo, s_tr, s_pr, h->n_codes, stage_input<T>(e, w, stage),
+                                             static_cast<T *>(w.rhs), nullptr);
+}
+
+template <int DIM, int NP, int QV, class T>
+__global__ __launch_bounds__(256) void batch_volume_kernel(const char *__restrict__ desc, int stage) {
+    const Header *h = bh(desc);
+    const int32_t m = reinterpret_cast<const int32_t *>(desc + h->off_map_elem)[blockIdx.x];
+    const Entry *e = bentry(desc, m);
+    const int64_t k = ((int64_t)blockIdx.x - e->blk_elem) * blockDim.x + threadIdx.x;
+    if (k >= e->n_elem) return;
+    const dgc_batch::RkWs w = dgc_batch::rk_ws(e->ws, (size_t)e->n_dof, sizeof(T) == 4);
+    volume_elem<DIM, NP, QV, T>(k, e->n_elem, e->elem_geo, h->tables + h->off_vb, h->tables + h->off_vd,
+                                stage_input<T>(e, w, stage), static_cast<T *>(w.rhs));
+}
+
+// SSP-RK3 stage combination of every mesh, out = a x + b (y + dt r) with the
+// mesh's own dt; the f32 form also refreshes the f32 shadow (stages 0, 1).
+template <class T>
+__global__ __launch_bounds__(256) void batch_combine_kernel(const char *__restrict__ desc, int stage) {
+    const Header *h = bh(desc);
+    const int32_t m = reinterpret_cast<const int32_t *>(desc + h->off_map_dof)[blockIdx.x];
+    const Entry *e = bentry(desc, m);
+    const int64_t i = ((int64_t)blockIdx.x - e->blk_dof) * blockDim.x + threadIdx.x;
+    if (i >= e->n_dof) return;
+    const dgc_batch::RkWs w = dgc_batch::rk_ws(e->ws, (size_t)e->n_dof, sizeof(T) == 4);
+    const double a = stage == 0 ? 0.0 : (stage == 1 ? 0.75 : 1.0 / 3.0);
+    const double b = stage == 0 ? 1.0 : (stage == 1 ? 0.25 : 2.0 / 3.0);
+    const double *y = stage == 0 ? e->U : (stage == 1 ? w.U1 : w.U2);
+    double *out = stage == 0 ? w.U1 : (stage == 1 ? w.U2 : e->U);
+    const double v = a * e->U[i] + b * (y[i] + e->dt * (double)static_cast<const T *>(w.rhs)[i]);
+    out[i] = v;
+    if (sizeof(T) == 4 && stage < 2) w.shadow[i] = (float)v;
+}
+
+__global__ __launch_bounds__(256) void batch_to_f32_kernel(const char *__restrict__ desc) {
+    const Header *h = bh(desc);
+    const int32_t m = reinterpret_cast<const int32_t *>(desc + h->off_map_dof)[blockIdx.x];
+    const Entry *e = bentry(desc, m);
+    const int64_t i = ((int64_t)blockIdx.x - e->blk_dof) * blockDim.x + threadIdx.x;
+    if (i >= e->n_dof) return;
+    const dgc_batch::RkWs w = dgc_batch::rk_ws(e->ws, (size_t)e->n_dof, 1);
+    w.shadow[i] = (float)e->U[i];
+}
+
+}  // namespace dgc_dev

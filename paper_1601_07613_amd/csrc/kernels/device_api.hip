@@ -4,7 +4,12 @@
 
 #include <string>
 
+#include <cmath>
+#include <cstring>
+
+#include "../batch_desc.hpp"
 #include "../host/internal.hpp"
+#include "batch.hpp"
 #include "surface.hpp"
 #include "volume.hpp"
 
@@ -54,6 +59,8 @@ dgc_status check_colors(const dgc_dmesh *dm) {
 template <int DIM, int NP, int Q, int QV, class T>
 struct Impl {
     static constexpr int REC = (DIM + 2) * NP;
+    static constexpr int kDim = DIM, kNp = NP, kQ = Q, kQv = QV;
+    using Real = T;
 
     static dgc_status volume(const dgc_dmesh *dm, const dgc_table_info &ti, const T *U, T *rhs, hipStream_t st) {
         hipLaunchKernelGGL((dgc_dev::volume_kernel<DIM, NP, QV, T>), dim3(grid_for(dm->n_elem)), dim3(kBlock), 0, st,
@@ -115,17 +122,21 @@ struct Impl {
 };
 
 template <class T, class F>
-dgc_status dispatch(const dgc_dmesh *dm, F &&f) {
-    if (dm->elem_type == DGC_TRI) {
-        switch (dm->p) {
+dgc_status dispatch(const dgc_dmesh *dm, int elem_type, int p, F &&f) {
+    if (dm) {
+        elem_type = dm->elem_type;
+        p = dm->p;
+    }
+    if (elem_type == DGC_TRI) {
+        switch (p) {
             case 0: return f(Impl<2, 1, 1, 1, T>{});
             case 1: return f(Impl<2, 3, 2, 4, T>{});
             case 2: return f(Impl<2, 6, 3, 9, T>{});
             case 3: return f(Impl<2, 10, 4, 16, T>{});
             default: break;
         }
-    } else if (dm->elem_type == DGC_TET) {
-        switch (dm->p) {
+    } else if (elem_type == DGC_TET) {
+        switch (p) {
             case 0: return f(Impl<3, 1, 3, 1, T>{});
             case 1: return f(Impl<3, 4, 3, 8, T>{});
             default: break;
@@ -147,11 +158,11 @@ dgc_status dgc_volume_rhs(const dgc_dmesh *dm, const void *U, void *rhs, int32_t
     if (!U || !rhs) return fail(DGC_E_ARG, "dgc_volume_rhs: null U or rhs");
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (precision == DGC_F64)
-        return dispatch<double>(dm, [&](auto impl) {
+        return dispatch<double>(dm, 0, 0, [&](auto impl) {
             return decltype(impl)::volume(dm, ti, static_cast<const double *>(U), static_cast<double *>(rhs), st);
         });
     if (precision == DGC_F32)
-        return dispatch<float>(dm, [&](auto impl) {
+        return dispatch<float>(dm, 0, 0, [&](auto impl) {
             return decltype(impl)::volume(dm, ti, static_cast<const float *>(U), static_cast<float *>(rhs), st);
         });
     return fail(DGC_E_ARG, "unknown precision");
@@ -165,12 +176,12 @@ dgc_status dgc_surface_rhs(const dgc_dmesh *dm, const void *U, void *rhs, int32_
     if (!U || !rhs) return fail(DGC_E_ARG, "dgc_surface_rhs: null U or rhs");
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (precision == DGC_F64)
-        return dispatch<double>(dm, [&](auto impl) {
+        return dispatch<double>(dm, 0, 0, [&](auto impl) {
             return decltype(impl)::surface(dm, ti, static_cast<const double *>(U), static_cast<double *>(rhs), variant,
                                            ws, ws_bytes, st);
         });
     if (precision == DGC_F32)
-        return dispatch<float>(dm, [&](auto impl) {
+        return dispatch<float>(dm, 0, 0, [&](auto impl) {
             return decltype(impl)::surface(dm, ti, static_cast<const float *>(U), static_cast<float *>(rhs), variant, ws,
                                            ws_bytes, st);
         });
@@ -193,10 +204,9 @@ dgc_status dgc_workspace_bytes(const dgc_dmesh *dm, int32_t what, int32_t varian
     }
     if (what == DGC_WS_RK_STEP) {
         const size_t n = (size_t)dm->n_elem * dm->n_var * dm->n_p;
-        size_t b = 2 * n * 8 + n * elt;  // U1, U2 (f64) + rhs
-        if (precision == DGC_F32) b += n * 4;  // f32 shadow of the stage state
-        b = (b + 255) & ~(size_t)255;
-        *bytes = b + surf;
+        size_t off[4], total;
+        dgc_batch::rk_ws_offsets(n, precision == DGC_F32, off, &total);  // U1, U2, rhs, f32 shadow
+        *bytes = total + surf;
         return DGC_OK;
     }
     return fail(DGC_E_ARG, "unknown workspace kind");
@@ -214,15 +224,13 @@ dgc_status dgc_rk_step(const dgc_dmesh *dm, double *U, double dt, int32_t varian
     hipStream_t st = static_cast<hipStream_t>(stream);
     const size_t n = (size_t)dm->n_elem * dm->n_var * dm->n_p;
     char *w = static_cast<char *>(ws);
-    double *U1 = reinterpret_cast<double *>(w);
-    double *U2 = U1 + n;
-    const size_t elt = precision == DGC_F64 ? 8 : 4;
-    void *rhs = U2 + n;
-    float *shadow = precision == DGC_F32 ? reinterpret_cast<float *>(static_cast<char *>(rhs) + n * elt) : nullptr;
-    size_t base = 2 * n * 8 + n * elt + (shadow ? n * 4 : 0);
-    base = (base + 255) & ~(size_t)255;
-    void *sws = w + base;
-    size_t sws_bytes = ws_bytes - base;
+    const dgc_batch::RkWs lay = dgc_batch::rk_ws(w, n, precision == DGC_F32);
+    double *U1 = lay.U1;
+    double *U2 = lay.U2;
+    void *rhs = lay.rhs;
+    float *shadow = lay.shadow;
+    void *sws = w + lay.bytes;
+    size_t sws_bytes = ws_bytes - lay.bytes;
 
     const double a[3] = {0.0, 0.75, 1.0 / 3.0};
     const double b[3] = {1.0, 0.25, 2.0 / 3.0};
@@ -247,6 +255,217 @@ dgc_status dgc_rk_step(const dgc_dmesh *dm, double *U, double dt, int32_t varian
                                stage_out[stg]);
         }
         if ((s = hip_check("rk combine launch")) != DGC_OK) return s;
+    }
+    return DGC_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------
+// Batched forms
+// ------------------------------------------------------------------------
+
+namespace {
+
+template <class F>
+dgc_status dispatch_type(int elem_type, int p, int precision, F &&f) {
+    if (precision == DGC_F64) return dispatch<double>(nullptr, elem_type, p, f);
+    return dispatch<float>(nullptr, elem_type, p, f);
+}
+
+dgc_status read_header(const void *host_desc, dgc_batch::Header *h) {
+    if (!host_desc) return fail(DGC_E_ARG, "null batch descriptor");
+    std::memcpy(h, host_desc, sizeof(*h));
+    if (h->magic != dgc_batch::kMagic || h->n_mesh <= 0) return fail(DGC_E_ARG, "not a batch descriptor");
+    return DGC_OK;
+}
+
+template <int DIM, int NP, int Q, int QV, class T>
+struct BatchImpl {
+    static dgc_status surface(const dgc_batch::Header &h, const char *dev, int stage, hipStream_t st) {
+        const size_t lds = 2 * (size_t)h.n_codes * Q * NP * sizeof(T);
+        for (int c = 0; c < h.n_colors; ++c) {
+            if (h.nblk_face[c] == 0) continue;
+            hipLaunchKernelGGL((dgc_dev::batch_surface_kernel<DIM, NP, Q, T>), dim3(h.nblk_face[c]), dim3(h.block), lds,
+                               st, dev, c, stage);
+            if (dgc_status s = hip_check("batched surface launch"); s != DGC_OK) return s;
+        }
+        return DGC_OK;
+    }
+    static dgc_status volume(const dgc_batch::Header &h, const char *dev, int stage, hipStream_t st) {
+        hipLaunchKernelGGL((dgc_dev::batch_volume_kernel<DIM, NP, QV, T>), dim3(h.nblk_elem), dim3(kBlock), 0, st, dev,
+                           stage);
+        return hip_check("batched volume launch");
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+dgc_status dgc_rk_workspace_layout(int64_t n, int32_t precision, size_t off[4], size_t *total) {
+    if (n < 0 || !off || !total || (precision != DGC_F64 && precision != DGC_F32))
+        return fail(DGC_E_ARG, "dgc_rk_workspace_layout: bad argument");
+    dgc_batch::rk_ws_offsets((size_t)n, precision == DGC_F32, off, total);
+    if (precision != DGC_F32) off[3] = 0;
+    return DGC_OK;
+}
+
+dgc_status dgc_batch_describe(int32_t n_mesh, const dgc_dmesh *meshes, double *const *U, void *const *ws,
+                              const double *dt, int32_t precision, void *host_desc, size_t bytes, size_t *needed) {
+    if (n_mesh <= 0 || !meshes || !U || !ws || !dt) return fail(DGC_E_ARG, "dgc_batch_describe: bad argument");
+    if (precision != DGC_F64 && precision != DGC_F32) return fail(DGC_E_ARG, "dgc_batch_describe: unknown precision");
+    dgc_table_info ti{};
+    for (int32_t i = 0; i < n_mesh; ++i) {
+        dgc_table_info t;
+        if (dgc_status s = check_dm(&meshes[i], &t); s != DGC_OK) return s;
+        if (dgc_status s = check_colors(&meshes[i]); s != DGC_OK) return s;
+        if (i == 0) ti = t;
+        if (meshes[i].elem_type != meshes[0].elem_type || meshes[i].p != meshes[0].p)
+            return fail(DGC_E_ARG, "dgc_batch_describe: meshes of one batch share element type and order");
+        if (!U[i] || !ws[i]) return fail(DGC_E_ARG, "dgc_batch_describe: null state or workspace");
+        if (!std::isfinite(dt[i])) return fail(DGC_E_ARG, "dgc_batch_describe: non-finite dt");
+    }
+    const int team = ti.dim + 2 <= 4 ? 4 : 8;
+    const int fpb = kBlock / team;
+    int nc = 0;
+    for (int32_t i = 0; i < n_mesh; ++i) nc = meshes[i].n_colors > nc ? meshes[i].n_colors : nc;
+    // work-group counts
+    std::vector<int64_t> nb_face(nc, 0);
+    int64_t nb_elem = 0, nb_dof = 0;
+    for (int32_t i = 0; i < n_mesh; ++i) {
+        const dgc_dmesh &d = meshes[i];
+        for (int c = 0; c < nc; ++c) {
+            const int64_t nf = c < d.n_colors ? d.color_off[c + 1] - d.color_off[c] : 0;
+            nb_face[c] += (nf + fpb - 1) / fpb;
+        }
+        nb_elem += (d.n_elem + kBlock - 1) / kBlock;
+        nb_dof += (d.n_elem * d.n_var * d.n_p + kBlock - 1) / kBlock;
+    }
+    for (int c = 0; c < nc; ++c)
+        if (nb_face[c] > INT32_MAX) return fail(DGC_E_ARG, "dgc_batch_describe: batch too large");
+    if (nb_elem > INT32_MAX || nb_dof > INT32_MAX) return fail(DGC_E_ARG, "dgc_batch_describe: batch too large");
+    dgc_batch::Header h{};
+    h.magic = dgc_batch::kMagic;
+    h.n_mesh = n_mesh;
+    h.n_colors = nc;
+    h.elem_type = meshes[0].elem_type;
+    h.p = meshes[0].p;
+    h.n_p = ti.n_p;
+    h.n_var = ti.dim + 2;
+    h.n_qf = ti.n_qf;
+    h.n_qv = ti.n_qv;
+    h.n_codes = ti.n_codes;
+    h.precision = precision;
+    h.block = kBlock;
+    h.faces_per_block = fpb;
+    h.tables = meshes[0].tables;
+    h.off_trace = ti.off_trace;
+    h.off_proj = ti.off_proj;
+    h.off_vb = ti.off_vb;
+    h.off_vd = ti.off_vd;
+    int64_t off = dgc_batch::kHeaderBytes;
+    h.off_entries = off;
+    off += (int64_t)sizeof(dgc_batch::Entry) * n_mesh;
+    for (int c = 0; c < nc; ++c) {
+        h.off_map_face[c] = off;
+        h.nblk_face[c] = (int32_t)nb_face[c];
+        off += 4 * nb_face[c];
+    }
+    h.off_map_elem = off;
+    h.nblk_elem = (int32_t)nb_elem;
+    off += 4 * nb_elem;
+    h.off_map_dof = off;
+    h.nblk_dof = (int32_t)nb_dof;
+    off += 4 * nb_dof;
+    h.total_bytes = off;
+    if (needed) *needed = (size_t)off;
+    if (!host_desc) return DGC_OK;
+    if (bytes < (size_t)off) return fail(DGC_E_ARG, "dgc_batch_describe: destination too small");
+    char *out = static_cast<char *>(host_desc);
+    std::memset(out, 0, (size_t)off);
+    std::memcpy(out, &h, sizeof(h));
+    dgc_batch::Entry *ent = reinterpret_cast<dgc_batch::Entry *>(out + h.off_entries);
+    std::vector<int64_t> cur(nc, 0);
+    int64_t ce = 0, cd = 0;
+    for (int32_t i = 0; i < n_mesh; ++i) {
+        const dgc_dmesh &d = meshes[i];
+        dgc_batch::Entry &e = ent[i];
+        e.face_lr = d.face_lr;
+        e.face_code = d.face_code;
+        e.face_geo = d.face_geo;
+        e.elem_geo = d.elem_geo;
+        e.U = U[i];
+        e.ws = static_cast<char *>(ws[i]);
+        e.dt = dt[i];
+        e.n_face = d.n_face;
+        e.n_elem = d.n_elem;
+        e.n_dof = d.n_elem * d.n_var * d.n_p;
+        for (int c = 0; c <= nc; ++c) e.color_off[c] = c <= d.n_colors ? d.color_off[c] : d.n_face;
+        for (int c = 0; c < nc; ++c) {
+            const int64_t nf = e.color_off[c + 1] - e.color_off[c];
+            const int64_t nb = (nf + fpb - 1) / fpb;
+            e.blk_face[c] = (int32_t)cur[c];
+            int32_t *map = reinterpret_cast<int32_t *>(out + h.off_map_face[c]);
+            for (int64_t b = 0; b < nb; ++b) map[cur[c] + b] = i;
+            cur[c] += nb;
+        }
+        const int64_t ne = (d.n_elem + kBlock - 1) / kBlock, nd = (e.n_dof + kBlock - 1) / kBlock;
+        e.blk_elem = (int32_t)ce;
+        e.blk_dof = (int32_t)cd;
+        int32_t *me = reinterpret_cast<int32_t *>(out + h.off_map_elem);
+        int32_t *md = reinterpret_cast<int32_t *>(out + h.off_map_dof);
+        for (int64_t b = 0; b < ne; ++b) me[ce + b] = i;
+        for (int64_t b = 0; b < nd; ++b) md[cd + b] = i;
+        ce += ne;
+        cd += nd;
+    }
+    return DGC_OK;
+}
+
+dgc_status dgc_surface_rhs_batched(const void *host_desc, const void *dev_desc, int32_t stage, void *stream) {
+    dgc_batch::Header h;
+    if (dgc_status s = read_header(host_desc, &h); s != DGC_OK) return s;
+    if (!dev_desc || stage < 0 || stage > 2) return fail(DGC_E_ARG, "dgc_surface_rhs_batched: bad argument");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const char *dev = static_cast<const char *>(dev_desc);
+    return dispatch_type(h.elem_type, h.p, h.precision, [&](auto impl) {
+        using I = decltype(impl);
+        return BatchImpl<I::kDim, I::kNp, I::kQ, I::kQv, typename I::Real>::surface(h, dev, stage, st);
+    });
+}
+
+dgc_status dgc_volume_rhs_batched(const void *host_desc, const void *dev_desc, int32_t stage, void *stream) {
+    dgc_batch::Header h;
+    if (dgc_status s = read_header(host_desc, &h); s != DGC_OK) return s;
+    if (!dev_desc || stage < 0 || stage > 2) return fail(DGC_E_ARG, "dgc_volume_rhs_batched: bad argument");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const char *dev = static_cast<const char *>(dev_desc);
+    return dispatch_type(h.elem_type, h.p, h.precision, [&](auto impl) {
+        using I = decltype(impl);
+        return BatchImpl<I::kDim, I::kNp, I::kQ, I::kQv, typename I::Real>::volume(h, dev, stage, st);
+    });
+}
+
+dgc_status dgc_rk_step_batched(const void *host_desc, const void *dev_desc, void *stream) {
+    dgc_batch::Header h;
+    if (dgc_status s = read_header(host_desc, &h); s != DGC_OK) return s;
+    if (!dev_desc) return fail(DGC_E_ARG, "dgc_rk_step_batched: null device descriptor");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const char *dev = static_cast<const char *>(dev_desc);
+    const bool f32 = h.precision == DGC_F32;
+    if (f32) {
+        hipLaunchKernelGGL(dgc_dev::batch_to_f32_kernel, dim3(h.nblk_dof), dim3(kBlock), 0, st, dev);
+        if (dgc_status s = hip_check("batched f32 shadow launch"); s != DGC_OK) return s;
+    }
+    for (int stage = 0; stage < 3; ++stage) {
+        if (dgc_status s = dgc_volume_rhs_batched(host_desc, dev_desc, stage, stream); s != DGC_OK) return s;
+        if (dgc_status s = dgc_surface_rhs_batched(host_desc, dev_desc, stage, stream); s != DGC_OK) return s;
+        if (f32)
+            hipLaunchKernelGGL(dgc_dev::batch_combine_kernel<float>, dim3(h.nblk_dof), dim3(kBlock), 0, st, dev, stage);
+        else
+            hipLaunchKernelGGL(dgc_dev::batch_combine_kernel<double>, dim3(h.nblk_dof), dim3(kBlock), 0, st, dev, stage);
+        if (dgc_status s = hip_check("batched combine launch"); s != DGC_OK) return s;
     }
     return DGC_OK;
 }

@@ -191,7 +191,7 @@ __device__ __forceinline__ float team_bcast(float v, int k) {
     return __int_as_float(team_bcast_i<TEAM>(__float_as_int(v), k));
 }
 
-// Team form of the face kernel: TEAM lanes per face (4 for M = 4, 8 for
+// Team form of the face work: TEAM lanes per face (4 for M = 4, 8 for
 // M = 5); lane r < M owns conserved variable r.  Each lane reads and
 // updates the NP modes of its variable, so one load instruction of a team
 // touches one contiguous stretch of the element record instead of one
@@ -200,28 +200,14 @@ __device__ __forceinline__ float team_bcast(float v, int k) {
 // projects component r.  Same arithmetic and accumulation modes as
 // surface_kernel.
 template <int DIM, int NP, int Q, int MODE, class T, bool PREFETCH>
-__global__ __launch_bounds__(256) void surface_team_kernel(
-    int64_t f_begin, int64_t f_end, int64_t n_face, int64_t n_elem,
+__device__ __forceinline__ void team_face(
+    int64_t k, int r, int64_t n_face, int64_t n_elem,
     const int32_t *__restrict__ face_lr, const uint8_t *__restrict__ face_code,
-    const double *__restrict__ face_geo, const double *__restrict__ tab_trace,
-    const double *__restrict__ tab_proj, int n_codes,
-    const T *__restrict__ U, T *__restrict__ rhs, T *__restrict__ buf, int remap) {
+    const double *__restrict__ face_geo, const T *__restrict__ s_tr, const T *__restrict__ s_pr, int n_codes,
+    const T *__restrict__ U, T *__restrict__ rhs, T *__restrict__ buf) {
     constexpr int M = DIM + 2;
     constexpr int REC = M * NP;
     constexpr int TEAM = M <= 4 ? 4 : 8;
-    extern __shared__ unsigned char smem_raw[];
-    T *s_tr = reinterpret_cast<T *>(smem_raw);
-    T *s_pr = s_tr + n_codes * Q * NP;
-    const int ntab = n_codes * Q * NP;
-    for (int i = threadIdx.x; i < ntab; i += blockDim.x) {
-        s_tr[i] = T(tab_trace[i]);
-        s_pr[i] = T(tab_proj[i]);
-    }
-    __syncthreads();
-
-    const int r = threadIdx.x % TEAM;
-    const int64_t k = f_begin + ((int64_t)logical_block(remap) * blockDim.x + threadIdx.x) / TEAM;
-    if (k >= f_end) return;  // whole teams leave together
     const int32_t L = face_lr[k];
     const int32_t R = face_lr[n_face + k];
     const int cL = face_code[k];
@@ -331,6 +317,36 @@ __global__ __launch_bounds__(256) void surface_team_kernel(
             else dst[j] = a;
         }
     }
+}
+
+// Basis tables of every face code, copied once per work-group into LDS.
+template <class T>
+__device__ __forceinline__ void stage_tables(T *s_tr, T *s_pr, const double *__restrict__ tab_trace,
+                                             const double *__restrict__ tab_proj, int ntab) {
+    for (int i = threadIdx.x; i < ntab; i += blockDim.x) {
+        s_tr[i] = T(tab_trace[i]);
+        s_pr[i] = T(tab_proj[i]);
+    }
+    __syncthreads();
+}
+
+template <int DIM, int NP, int Q, int MODE, class T, bool PREFETCH>
+__global__ __launch_bounds__(256) void surface_team_kernel(
+    int64_t f_begin, int64_t f_end, int64_t n_face, int64_t n_elem,
+    const int32_t *__restrict__ face_lr, const uint8_t *__restrict__ face_code,
+    const double *__restrict__ face_geo, const double *__restrict__ tab_trace,
+    const double *__restrict__ tab_proj, int n_codes,
+    const T *__restrict__ U, T *__restrict__ rhs, T *__restrict__ buf, int remap) {
+    constexpr int TEAM = DIM + 2 <= 4 ? 4 : 8;
+    extern __shared__ unsigned char smem_raw[];
+    T *s_tr = reinterpret_cast<T *>(smem_raw);
+    T *s_pr = s_tr + n_codes * Q * NP;
+    stage_tables<T>(s_tr, s_pr, tab_trace, tab_proj, n_codes * Q * NP);
+    const int r = threadIdx.x % TEAM;
+    const int64_t k = f_begin + ((int64_t)logical_block(remap) * blockDim.x + threadIdx.x) / TEAM;
+    if (k >= f_end) return;  // whole teams leave together
+    team_face<DIM, NP, Q, MODE, T, PREFETCH>(k, r, n_face, n_elem, face_lr, face_code, face_geo, s_tr, s_pr, n_codes,
+                                             U, rhs, buf);
 }
 
 // Second pass of the buffered variant: rhs[k] += sum of element k's slots.

@@ -15,13 +15,11 @@
 namespace dgc_dev {
 
 template <int DIM, int NP, int QV, class T>
-__global__ __launch_bounds__(256) void volume_kernel(int64_t n_elem, const double *__restrict__ elem_geo,
-                                                     const double *__restrict__ vb, const double *__restrict__ vd,
-                                                     const T *__restrict__ U, T *__restrict__ rhs) {
+__device__ __forceinline__ void volume_elem(int64_t k, int64_t n_elem, const double *__restrict__ elem_geo,
+                                            const double *__restrict__ vb, const double *__restrict__ vd,
+                                            const T *__restrict__ U, T *__restrict__ rhs) {
     constexpr int M = DIM + 2;
     constexpr int REC = M * NP;
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n_elem) return;
     T Ji[DIM * DIM];
 #pragma unroll
     for (int a = 0; a < DIM * DIM; ++a) Ji[a] = T(elem_geo[a * n_elem + k]);
@@ -68,6 +66,15 @@ __global__ __launch_bounds__(256) void volume_kernel(int64_t n_elem, const doubl
     T *r = rhs + (size_t)k * REC;
 #pragma unroll
     for (int i = 0; i < REC; ++i) r[i] = acc[i] * T(sq);
+}
+
+template <int DIM, int NP, int QV, class T>
+__global__ __launch_bounds__(256) void volume_kernel(int64_t n_elem, const double *__restrict__ elem_geo,
+                                                     const double *__restrict__ vb, const double *__restrict__ vd,
+                                                     const T *__restrict__ U, T *__restrict__ rhs) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_elem) return;
+    volume_elem<DIM, NP, QV, T>(k, n_elem, elem_geo, vb, vd, U, rhs);
 }
 
 // out = a * x + b * (y + dt * r), f64 accumulation of the stage state
