@@ -165,6 +165,27 @@ def extra_workloads(dgc, synth, torch, steps, warmup, log):
     out["c3_amr_level3_p2"] = {"n_elem": info["n_elem"], "n_face": info["n_face"], "n_colors": info["n_colors"],
                                "refine_s": refine_s, "f64": r}
     log("c3: %s" % out["c3_amr_level3_p2"])
+    del DA, A
+
+    # c4: serving -- 256 solves, Poisson arrivals at 50/s, 100 SSP-RK3 steps each
+    from synth.requests import request_stream
+    from paper_1601_07613_amd.serve import GPUExecutor, Request, Server
+
+    def reqs(saturated=False):
+        rs = request_stream(256, rate=50.0, seed=5, steps=100)
+        return [Request(rid=r["rid"], arrival=0.0 if saturated else r["arrival"], p=r["p"], steps=r["steps"],
+                        spec=r) for r in rs]
+
+    serving = {}
+    for name, prec, mode, budget, sat in (("batched_f32_budget512MB", "f32", "batched", 512 << 20, False),
+                                          ("batched_f32_full", "f32", "batched", 200 << 30, False),
+                                          ("plain_f64_sequential", "f64", "sequential", 200 << 30, False),
+                                          ("batched_f32_saturated", "f32", "batched", 200 << 30, True),
+                                          ("plain_f64_saturated", "f64", "sequential", 200 << 30, True)):
+        st = Server(GPUExecutor(precision=prec), budget_bytes=budget, mode=mode, prep_workers=8).run(reqs(sat))
+        serving[name] = st.summary()
+        log("c4 %s: %s" % (name, serving[name]))
+    out["c4_serving_256"] = serving
     return out
 
 

@@ -1,0 +1,283 @@
+"""Serving loop: continuous batching of independent DG solves on one GPU.
+
+Requests arrive over time (each: a mesh, an order p, an initial state and a
+number of SSP-RK3 steps).  A host worker pool builds, colors and lays out
+each request's mesh while the GPU works.  A prepared request is admitted when
+its device footprint fits in the HBM budget (first come, first served; a
+request that can never fit is rejected).  Admitted requests of the same order
+p form one group; every iteration advances every group by one batched SSP-RK3
+step (one graph replay per group, re-captured only when the group's
+membership changes), so requests join and leave between steps and their work
+overlaps on the device.  Finished requests free their memory for the next
+admission.  A request whose result is not finite fails alone.
+
+``mode="sequential"`` is the plain baseline: one request at a time, each
+advanced by the single-mesh f64 step without batching or graphs.
+"""
+
+from __future__ import annotations
+
+import concurrent.futures as cf
+import math
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float
+    p: int
+    steps: int
+    spec: dict
+    footprint: int = 0
+    t_ready: float = math.nan
+    t_admit: float = math.nan
+    t_done: float = math.nan
+    steps_done: int = 0
+    status: str = "waiting"   # waiting, preparing, ready, active, done, failed, rejected
+    dofs: int = 0
+    host: object = None       # prepared host data (executor-specific)
+    dev: object = None        # device data (executor-specific)
+    result: object = None
+
+
+class WallClock:
+    def __init__(self):
+        self.t0 = time.perf_counter()
+
+    def now(self) -> float:
+        return time.perf_counter() - self.t0
+
+    def wait_until(self, t: float) -> None:
+        d = t - self.now()
+        if d > 0:
+            time.sleep(min(d, 0.002))
+
+
+@dataclass
+class ServeStats:
+    latencies: dict = field(default_factory=dict)
+    completed: int = 0
+    failed: int = 0
+    rejected: int = 0
+    makespan: float = 0.0
+    dof_steps: float = 0.0
+    max_used: int = 0
+    recaptures: int = 0
+    iterations: int = 0
+
+    def summary(self) -> dict:
+        lat = np.array(list(self.latencies.values())) if self.latencies else np.zeros(1)
+        return {
+            "completed": self.completed, "failed": self.failed, "rejected": self.rejected,
+            "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+            "mean_s": float(lat.mean()), "makespan_s": self.makespan,
+            "requests_per_s": self.completed / self.makespan if self.makespan > 0 else 0.0,
+            "dof_steps_per_s": self.dof_steps / self.makespan if self.makespan > 0 else 0.0,
+            "max_used_bytes": self.max_used, "graph_captures": self.recaptures, "iterations": self.iterations,
+        }
+
+
+class Server:
+    def __init__(self, executor, budget_bytes: int, mode: str = "batched", clock=None, prep_workers: int = 4):
+        if mode not in ("batched", "sequential"):
+            raise ValueError(mode)
+        self.ex = executor
+        self.budget = int(budget_bytes)
+        self.mode = mode
+        self.clock = clock or WallClock()
+        self.prep_workers = prep_workers
+
+    def run(self, requests) -> ServeStats:
+        reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
+        st = ServeStats()
+        pending = list(reqs)
+        preparing = {}
+        ready = []            # FIFO by arrival
+        active = {}           # p -> list of requests
+        dirty = set()
+        used = 0
+        clock = self.clock
+        pool = cf.ThreadPoolExecutor(max_workers=self.prep_workers) if self.prep_workers > 0 else None
+        try:
+            while pending or preparing or ready or any(active.values()):
+                now = clock.now()
+                # arrivals start their host preparation
+                while pending and pending[0].arrival <= now:
+                    r = pending.pop(0)
+                    r.status = "preparing"
+                    if pool is None:
+                        preparing[r.rid] = (r, _done_future(self.ex.prepare, r))
+                    else:
+                        preparing[r.rid] = (r, pool.submit(self.ex.prepare, r))
+                # finished preparations queue for admission, in arrival order
+                fin = [rid for rid, (r, f) in preparing.items() if f.done()]
+                for rid in sorted(fin, key=lambda i: (preparing[i][0].arrival, i)):
+                    r, f = preparing.pop(rid)
+                    try:
+                        f.result()
+                        r.status = "ready"
+                        r.t_ready = clock.now()
+                        ready.append(r)
+                    except Exception:  # noqa: BLE001 - a bad request fails alone
+                        r.status = "failed"
+                        st.failed += 1
+                ready.sort(key=lambda r: (r.arrival, r.rid))
+                # admission by footprint (head of line waits; never-fitting requests are rejected)
+                n_active = sum(len(v) for v in active.values())
+                while ready:
+                    r = ready[0]
+                    if r.footprint > self.budget:
+                        ready.pop(0)
+                        r.status = "rejected"
+                        st.rejected += 1
+                        self.ex.release(r)
+                        continue
+                    if used + r.footprint > self.budget or (self.mode == "sequential" and n_active >= 1):
+                        break
+                    ready.pop(0)
+                    self.ex.admit(r)
+                    r.status = "active"
+                    r.t_admit = clock.now()
+                    used += r.footprint
+                    st.max_used = max(st.max_used, used)
+                    active.setdefault(r.p, []).append(r)
+                    dirty.add(r.p)
+                    n_active += 1
+                if not any(active.values()):
+                    nxt = [pending[0].arrival] if pending else []
+                    clock.wait_until(min(nxt) if nxt else clock.now() + 0.0005)
+                    continue
+                # one SSP-RK3 step of every active group
+                for p in sorted(active):
+                    group = active[p]
+                    if not group:
+                        continue
+                    if self.mode == "batched":
+                        if p in dirty:
+                            self.ex.rebuild(p, group)
+                            st.recaptures += 1
+                        self.ex.step_group(p, group)
+                    else:
+                        for r in group:
+                            self.ex.step_single(r)
+                dirty.clear()
+                self.ex.sync()
+                st.iterations += 1
+                now = clock.now()
+                for p in sorted(active):
+                    keep = []
+                    for r in active[p]:
+                        r.steps_done += 1
+                        if r.steps_done < r.steps:
+                            keep.append(r)
+                            continue
+                        ok = self.ex.finish(r)
+                        used -= r.footprint
+                        r.t_done = now
+                        if ok:
+                            r.status = "done"
+                            st.completed += 1
+                            st.latencies[r.rid] = r.t_done - r.arrival
+                            st.dof_steps += r.dofs * r.steps
+                        else:
+                            r.status = "failed"
+                            st.failed += 1
+                        dirty.add(p)
+                    active[p] = keep
+            st.makespan = clock.now() - (reqs[0].arrival if reqs else 0.0)
+        finally:
+            if pool is not None:
+                pool.shutdown(wait=True)
+        return st
+
+
+def _done_future(fn, *a):
+    f = cf.Future()
+    try:
+        f.set_result(fn(*a))
+    except Exception as e:  # noqa: BLE001
+        f.set_exception(e)
+    return f
+
+
+class GPUExecutor:
+    """Runs requests on the GPU through libdgc (batched groups or single solves)."""
+
+    def __init__(self, precision: str = "f32", cfl: float = 0.1, seed: int = 0):
+        import torch
+
+        import paper_1601_07613_amd as dgc
+
+        self.dgc = dgc
+        self.torch = torch
+        self.precision = precision
+        self.cfl = cfl
+        self.seed = seed
+        self.batches = {}
+        self.graphs = {}
+
+    # host work (worker threads): mesh, coloring, layout, initial DOFs, dt
+    def prepare(self, r: Request) -> None:
+        import synth.requests as sreq
+
+        m, U0 = sreq.request_input(r.spec)
+        M = self.dgc.Mesh.build(m["elem_vert"], m["elem_xyz"])
+        M.color(seed=self.seed)
+        xyz = m["elem_xyz"]
+        area = 0.5 * np.abs((xyz[:, 1, 0] - xyz[:, 0, 0]) * (xyz[:, 2, 1] - xyz[:, 0, 1])
+                            - (xyz[:, 2, 0] - xyz[:, 0, 0]) * (xyz[:, 1, 1] - xyz[:, 0, 1]))
+        per = sum(np.linalg.norm(xyz[:, (k + 1) % 3] - xyz[:, k], axis=1) for k in range(3))
+        mean = U0[:, :, 0] / np.sqrt(area)[:, None]
+        rho = mean[:, 0]
+        vel = mean[:, 1:3] / rho[:, None]
+        pres = 0.4 * (mean[:, 3] - 0.5 * rho * (vel ** 2).sum(axis=1))
+        smax = float((np.linalg.norm(vel, axis=1) + np.sqrt(1.4 * pres / rho)).max())
+        dt = self.cfl * float((4.0 * area / per).min()) / smax
+        K = U0.shape[0]
+        n_p = U0.shape[2]
+        E = 3 * K // 2
+        # state U (f64) + workspace: U1, U2 (f64), stage rhs (f64 / f32), f32 shadow
+        ws_elt = 16 + (4 if self.precision == "f32" else 8) + (4 if self.precision == "f32" else 0)
+        # + face arrays (ids, codes, geometry) + element arrays (geometry, slots) + tables
+        r.footprint = int(K * 4 * n_p * (8 + ws_elt) + E * (8 + 2 + 40) + K * (5 * 8 + 12) + 64 * 1024)
+        r.dofs = K * 4 * n_p
+        r.host = (M, U0, dt)
+
+    def admit(self, r: Request) -> None:
+        torch = self.torch
+        M, U0, dt = r.host
+        D = self.dgc.DeviceMesh(M, r.p)
+        U = torch.from_numpy(D.to_layout(U0)).cuda()
+        ws = D.workspace("rk", "colored", self.precision if self.precision else "f64")
+        r.dev = (D, U, ws, dt)
+
+    def release(self, r: Request) -> None:
+        r.host = None
+        r.dev = None
+
+    def rebuild(self, p, group) -> None:
+        B = self.dgc.Batch([r.dev for r in group], precision=self.precision)
+        self.batches[p] = B
+        self.graphs[p] = B.capture()
+
+    def step_group(self, p, group) -> None:
+        self.graphs[p].replay()
+
+    def step_single(self, r: Request) -> None:
+        D, U, ws, dt = r.dev
+        D.rk_step(U, dt, precision="f64", ws=ws)
+
+    def sync(self) -> None:
+        self.torch.cuda.synchronize()
+
+    def finish(self, r: Request) -> bool:
+        D, U, ws, dt = r.dev
+        res = D.from_layout(U.cpu().numpy())
+        r.result = res
+        r.dev = None
+        r.host = None
+        return bool(np.isfinite(res).all())
