@@ -109,10 +109,14 @@ def extra_workloads(dgc, synth, torch, steps, warmup, log):
     U[:, 3, 0] = 0.25
     rhs = torch.zeros_like(U)
     ws = D.workspace("rk", "colored")
+    B = dgc.Batch([(D, U, ws, 1e-9)])
+    g = B.capture(steps=10)
     out["c0_periodic512_p1"] = {
         "surface_pass_us": time_call(lambda: D.surface_rhs(U, rhs), reps=200, warmup=20) * 1e3,
         "rk3_step_us": time_call(lambda: D.rk_step(U, 1e-9, ws=ws), reps=100, warmup=10) * 1e3,
+        "rk3_step_graph_us": time_call(g.replay, reps=20, warmup=3) * 1e3 / 10,
     }
+    del g, B
     log("c0: %s" % out["c0_periodic512_p1"])
 
     # c2: 64^3 x 6 periodic Kuhn tetrahedra, p = 1, f64 and f32
@@ -123,6 +127,11 @@ def extra_workloads(dgc, synth, torch, steps, warmup, log):
     info = DT.info
     r64 = surf_stats(DT, info["n_elem"], info["n_face"], info["n_boundary"], 8, "f64")
     r32 = surf_stats(DT, info["n_elem"], info["n_face"], info["n_boundary"], 4, "f32")
+    DT.set_launch("thread")
+    r64t = surf_stats(DT, info["n_elem"], info["n_face"], info["n_boundary"], 8, "f64")
+    DT.set_launch("team_prefetch")
+    r64v = surf_stats(DT, info["n_elem"], info["n_face"], info["n_boundary"], 8, "f64")
+    DT.set_launch("default")
     # f32 form error: 10 SSP-RK3 steps of the density wave from the same state
     meas = synth.element_measure(t["elem_xyz"])
     st = synth.density_wave_states(synth.element_centroid(t["elem_xyz"]))
@@ -142,7 +151,7 @@ def extra_workloads(dgc, synth, torch, steps, warmup, log):
     rk32 = time_call(lambda: DT.rk_step(Ub, dt, precision="f32", ws=wb), reps=5, warmup=1)
     out["c2_kuhn64_tets_p1"] = {
         "n_elem": info["n_elem"], "n_face": info["n_face"], "n_colors": info["n_colors"],
-        "color_ms": cs["color_ms"], "f64": r64, "f32": r32,
+        "color_ms": cs["color_ms"], "f64": r64, "f32": r32, "f64_thread_form": r64t, "f64_variable_team_form": r64v,
         "rk3_step_us": {"f64": rk64 * 1e3, "f32_form": rk32 * 1e3},
         "f32_form_rel_L2_after_10_steps": [float(x) for x in diff.cpu()],
     }
@@ -307,6 +316,25 @@ def main(argv=None):
                                                         args.warmup, stream)[0] * 1e3
             del D2, Ug2, rhs2
         M.set_colors(colors, layout=args.layout)
+        # Table 7 shape: standard greedy (more colors) vs the paper's coloring,
+        # each with no renumbering / renumbering / renumbering + reordering
+        ablation = {}
+        G = dgc.Mesh.build(m["elem_vert"], m["elem_xyz"])
+        gst = G.color(algorithm="greedy")
+        gcol = G.export("color")
+        for cname, Mx, col in (("greedy_%dcolors" % gst["n_colors"], G, gcol), ("paper_3colors", M, colors)):
+            for lay in ("none", "renumber", "paper"):
+                Mx.set_colors(col, layout=lay)
+                Dx = dgc.DeviceMesh(Mx, p)
+                Dx.set_launch(best["form"], best["block"], best["xcd_remap"])
+                Ux = torch.from_numpy(Dx.to_layout(U)).cuda()
+                rx = torch.zeros_like(Ux)
+                ablation["%s_%s" % (cname, lay)] = time_call(lambda: Dx.surface_rhs(Ux, rx, "colored"),
+                                                             reps=args.steps, warmup=args.warmup) * 1e3
+                del Dx, Ux, rx
+        extra["table7_ablation_us"] = ablation
+        M.set_colors(colors, layout=args.layout)
+        del G
         # the f32 form of the same pass (f32 records, f64 geometry)
         U32 = Ug.float()
         r32 = torch.zeros_like(U32)
@@ -322,7 +350,7 @@ def main(argv=None):
         extra["copy_1GiB_GBs"] = 2 * n * 8 / (cms * 1e-3) / 1e9
         del a, b
         for k2, v in extra.items():
-            log("%s: %.2f" % (k2, v))
+            log("%s: %s" % (k2, v))
 
     workloads = None
     if args.only == "all":

@@ -251,8 +251,12 @@ typedef struct {
  * per conserved variable) so that loads of one element record are
  * contiguous across lanes; DGC_FORM_TEAM_PREFETCH is the same with the
  * right-hand-side reads of the colored update issued before the flux
- * evaluation (the default); DGC_FORM_THREAD gives each face one work-item. */
-enum { DGC_FORM_DEFAULT = 0, DGC_FORM_TEAM = 1, DGC_FORM_THREAD = 2, DGC_FORM_TEAM_PREFETCH = 3 };
+ * evaluation (the default, except for tetrahedra at p = 1); DGC_FORM_THREAD
+ * gives each face one work-item; DGC_FORM_MODE_TEAM (tetrahedra, p = 1, the
+ * default there) gives each face 4 lanes, one per mode, and sums the traces
+ * across them. */
+enum { DGC_FORM_DEFAULT = 0, DGC_FORM_TEAM = 1, DGC_FORM_THREAD = 2, DGC_FORM_TEAM_PREFETCH = 3,
+       DGC_FORM_MODE_TEAM = 4 };
 
 /* Volume term of Eq. (2): rhs = int F(U) . grad v (overwrites rhs).
  * U, rhs: device [n_elem][n_var][n_p] (f64, or f32 for DGC_F32). */
@@ -286,6 +290,25 @@ enum { DGC_WS_SURFACE = 0, DGC_WS_RK_STEP = 1 };
  * dgc_rk_step (DGC_WS_RK_STEP) with the given variant and precision. */
 dgc_status dgc_workspace_bytes(const dgc_dmesh *dm, int32_t what, int32_t variant, int32_t precision,
                                size_t *bytes);
+
+/* Move element records between the caller's element order and the layout
+ * order (Section 5) on the device.  src, dst: device [n_rec][rec_bytes]
+ * (distinct buffers); perm: device int32 [n_rec], perm[i] = layout id of
+ * element i (the DGC_ARR_ELEM_NEW array).  to_layout != 0: dst[perm[i]] =
+ * src[i]; otherwise dst[i] = src[perm[i]].  rec_bytes must be a multiple of
+ * 4.  Errors: DGC_E_ARG, DGC_E_HIP. */
+dgc_status dgc_permute_records(const void *src, void *dst, const int32_t *perm, int64_t n_rec, int64_t rec_bytes,
+                               int32_t to_layout, void *stream);
+
+/* The closed-form child coloring of a 4-way split (Section 3.2), computed in
+ * parallel on the device.  parent_colors: device int8 [n][3], the colors
+ * (0..5) of the three edges of each split element; child_colors: device int8
+ * [n][9]: for parent edge k, the colors of its first and second child
+ * (entries 2k, 2k+1: c and (c + 3) mod 6; "first" is the half at the edge's
+ * recorded start vertex), then the colors of the interior edges parallel to
+ * parent edges 0, 1, 2 (entries 6..8).  dgc_mesh_refine applies the same map
+ * on the host.  Errors: DGC_E_ARG, DGC_E_HIP. */
+dgc_status dgc_child_colors(const int8_t *parent_colors, int64_t n, int8_t *child_colors, void *stream);
 
 /* Layout of the dgc_rk_step workspace for n = n_elem * n_var * n_p values:
  * byte offsets of the stage states U1, U2 (f64), the stage right-hand side

@@ -163,7 +163,7 @@ class DeviceMesh:
         dm.xcd_remap = 0
         self.dm = dm
 
-    FORMS = {"default": 0, "team": 1, "thread": 2, "team_prefetch": 3}
+    FORMS = {"default": 0, "team": 1, "thread": 2, "team_prefetch": 3, "mode_team": 4}
 
     def set_launch(self, form: str = "default", block: int = 0, xcd_remap: bool = False) -> None:
         """Choose the face-kernel form (team of lanes per face, or one work-item
@@ -181,6 +181,33 @@ class DeviceMesh:
 
     def from_layout(self, Ul: np.ndarray) -> np.ndarray:
         return Ul[self.elem_new]
+
+    def _perm_dev(self):
+        import torch
+
+        if getattr(self, "_perm", None) is None:
+            self._perm = torch.from_numpy(self.elem_new.astype(np.int32)).to(self.face_lr.device)
+        return self._perm
+
+    def to_layout_device(self, U, stream=None):
+        """Device gather of element records (caller's order) into the layout order."""
+        import torch
+
+        out = torch.empty_like(U)
+        rb = U[0].numel() * U.element_size()
+        _lib.check(_L.dgc_permute_records(U.data_ptr(), out.data_ptr(), self._perm_dev().data_ptr(), U.shape[0], rb, 1,
+                                          _stream_ptr(stream)), "dgc_permute_records")
+        return out
+
+    def from_layout_device(self, Ul, stream=None):
+        """Device gather of element records from the layout order back to the caller's order."""
+        import torch
+
+        out = torch.empty_like(Ul)
+        rb = Ul[0].numel() * Ul.element_size()
+        _lib.check(_L.dgc_permute_records(Ul.data_ptr(), out.data_ptr(), self._perm_dev().data_ptr(), Ul.shape[0], rb,
+                                          0, _stream_ptr(stream)), "dgc_permute_records")
+        return out
 
     def alloc(self, precision: str = "f64", zero: bool = True):
         import torch
@@ -219,6 +246,17 @@ class DeviceMesh:
         _lib.check(_L.dgc_rk_step(C.byref(self.dm), U.data_ptr(), float(dt), VARIANTS[variant],
                                   PRECISIONS[precision], ws.data_ptr(), ws.numel(), _stream_ptr(stream)),
                    "dgc_rk_step")
+
+
+def child_colors(parent_colors, stream=None):
+    """Child-edge colors of split elements computed on the device: parent
+    colors ``[n, 3]`` (int8 tensor on the GPU) -> ``[n, 9]``."""
+    import torch
+
+    out = torch.empty((parent_colors.shape[0], 9), dtype=torch.int8, device=parent_colors.device)
+    _lib.check(_L.dgc_child_colors(parent_colors.data_ptr(), parent_colors.shape[0], out.data_ptr(),
+                                   _stream_ptr(stream)), "dgc_child_colors")
+    return out
 
 
 def rk_workspace_layout(n: int, precision: str = "f64"):

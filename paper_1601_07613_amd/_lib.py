@@ -91,6 +91,9 @@ _SIGS = {
                               C.c_size_t, C.c_void_p]),
     "dgc_workspace_bytes": (C.c_int, [C.POINTER(DMesh), C.c_int32, C.c_int32, C.c_int32,
                                       C.POINTER(C.c_size_t)]),
+    "dgc_permute_records": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_int32,
+                                      C.c_void_p]),
+    "dgc_child_colors": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
     "dgc_rk_workspace_layout": (C.c_int, [C.c_int64, C.c_int32, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
     "dgc_batch_describe": (C.c_int, [C.c_int32, C.POINTER(DMesh), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                      C.POINTER(C.c_double), C.c_int32, C.c_void_p, C.c_size_t,

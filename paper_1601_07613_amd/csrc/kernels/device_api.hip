@@ -10,6 +10,7 @@
 #include "../batch_desc.hpp"
 #include "../host/internal.hpp"
 #include "batch.hpp"
+#include "layout_dev.hpp"
 #include "surface.hpp"
 #include "volume.hpp"
 
@@ -40,7 +41,7 @@ dgc_status check_dm(const dgc_dmesh *dm, dgc_table_info *ti) {
         return fail(DGC_E_ARG, "dgc_dmesh: bad element / face count");
     if (!dm->face_lr || !dm->face_code || !dm->face_geo || !dm->elem_geo || !dm->tables)
         return fail(DGC_E_ARG, "dgc_dmesh: null device array");
-    if (dm->surf_form < DGC_FORM_DEFAULT || dm->surf_form > DGC_FORM_TEAM_PREFETCH)
+    if (dm->surf_form < DGC_FORM_DEFAULT || dm->surf_form > DGC_FORM_MODE_TEAM)
         return fail(DGC_E_ARG, "dgc_dmesh: unknown surf_form");
     if (dm->block_size != 0 && dm->block_size != 64 && dm->block_size != 128 && dm->block_size != 256)
         return fail(DGC_E_ARG, "dgc_dmesh: block_size must be 0, 64, 128 or 256");
@@ -74,6 +75,17 @@ struct Impl {
         if (f1 <= f0) return DGC_OK;
         const size_t lds = 2 * (size_t)ti.n_codes * Q * NP * sizeof(T);
         const int block = dm->block_size ? dm->block_size : kBlock;
+        if constexpr (NP == 4 && DIM == 3) {
+            // tetrahedra at p = 1: the mode team (4 lanes, lane = mode) unless another form is asked for
+            if (dm->surf_form == DGC_FORM_DEFAULT || dm->surf_form == DGC_FORM_MODE_TEAM) {
+                hipLaunchKernelGGL((dgc_dev::surface_mode_team_kernel<DIM, NP, Q, MODE, T>),
+                                   dim3(grid_for((f1 - f0) * 4, block)), dim3(block), lds, st, f0, f1, dm->n_face,
+                                   dm->n_elem, dm->face_lr, dm->face_code, dm->face_geo, dm->tables + ti.off_trace,
+                                   dm->tables + ti.off_proj, ti.n_codes, U, rhs, buf, dm->xcd_remap);
+                return hip_check("surface kernel launch");
+            }
+        }
+        if (dm->surf_form == DGC_FORM_MODE_TEAM) return fail(DGC_E_UNSUPPORTED, "mode teams need N_p = 4 in 3D");
         if (dm->surf_form == DGC_FORM_THREAD) {
             hipLaunchKernelGGL((dgc_dev::surface_kernel<DIM, NP, Q, MODE, T>), dim3(grid_for(f1 - f0, block)),
                                dim3(block), lds, st, f0, f1, dm->n_face, dm->n_elem, dm->face_lr, dm->face_code,
@@ -302,6 +314,26 @@ struct BatchImpl {
 }  // namespace
 
 extern "C" {
+
+dgc_status dgc_permute_records(const void *src, void *dst, const int32_t *perm, int64_t n_rec, int64_t rec_bytes,
+                               int32_t to_layout, void *stream) {
+    if (!src || !dst || !perm || n_rec < 0 || rec_bytes <= 0 || rec_bytes % 4 != 0 || src == dst)
+        return fail(DGC_E_ARG, "dgc_permute_records: bad argument");
+    if (n_rec == 0) return DGC_OK;
+    const int64_t words = rec_bytes / 4;
+    hipLaunchKernelGGL(dgc_dev::permute_records_kernel, dim3(grid_for(n_rec * words)), dim3(kBlock), 0,
+                       static_cast<hipStream_t>(stream), static_cast<const uint32_t *>(src), static_cast<uint32_t *>(dst),
+                       perm, n_rec, words, to_layout ? 1 : 0);
+    return hip_check("permute kernel launch");
+}
+
+dgc_status dgc_child_colors(const int8_t *parent_colors, int64_t n, int8_t *child_colors, void *stream) {
+    if (!parent_colors || !child_colors || n < 0) return fail(DGC_E_ARG, "dgc_child_colors: bad argument");
+    if (n == 0) return DGC_OK;
+    hipLaunchKernelGGL(dgc_dev::child_colors_kernel, dim3(grid_for(n)), dim3(kBlock), 0,
+                       static_cast<hipStream_t>(stream), parent_colors, n, child_colors);
+    return hip_check("child color kernel launch");
+}
 
 dgc_status dgc_rk_workspace_layout(int64_t n, int32_t precision, size_t off[4], size_t *total) {
     if (n < 0 || !off || !total || (precision != DGC_F64 && precision != DGC_F32))

@@ -319,6 +319,123 @@ __device__ __forceinline__ void team_face(
     }
 }
 
+// Sum over the 4 lanes of a quad (butterfly with DPP quad permutations);
+// every lane of the quad gets the same, order-independent result
+// ((v0 + v1) + (v2 + v3)).
+__device__ __forceinline__ int quad_xor1_i(int v) { return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false); }
+__device__ __forceinline__ int quad_xor2_i(int v) { return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false); }
+
+__device__ __forceinline__ double quad_xor1(double v) {
+    return __hiloint2double(quad_xor1_i(__double2hiint(v)), quad_xor1_i(__double2loint(v)));
+}
+__device__ __forceinline__ double quad_xor2(double v) {
+    return __hiloint2double(quad_xor2_i(__double2hiint(v)), quad_xor2_i(__double2loint(v)));
+}
+__device__ __forceinline__ float quad_xor1(float v) { return __int_as_float(quad_xor1_i(__float_as_int(v))); }
+__device__ __forceinline__ float quad_xor2(float v) { return __int_as_float(quad_xor2_i(__float_as_int(v))); }
+
+template <class T>
+__device__ __forceinline__ T quad_sum(T v) {
+    v = v + quad_xor1(v);
+    return v + quad_xor2(v);
+}
+
+// Mode-team form of the face work for N_p = 4 (tetrahedra, p = 1): a team
+// of 4 lanes per face, lane j owns mode j of every conserved variable.  Each
+// lane forms its mode's share of all traces, the shares are summed across
+// the quad with DPP, every lane evaluates the flux of the full state and lane
+// j projects onto mode j.  Loads and stores of one record are 4 consecutive
+// values per instruction, and no lane idles (the variable-per-lane team
+// would need 8 lanes for M = 5).
+template <int DIM, int NP, int Q, int MODE, class T, bool PREFETCH>
+__device__ __forceinline__ void mode_team_face(
+    int64_t k, int j, int64_t n_face, int64_t n_elem,
+    const int32_t *__restrict__ face_lr, const uint8_t *__restrict__ face_code,
+    const double *__restrict__ face_geo, const T *__restrict__ s_tr, const T *__restrict__ s_pr, int n_codes,
+    const T *__restrict__ U, T *__restrict__ rhs, T *__restrict__ buf) {
+    static_assert(NP == 4, "mode teams need exactly four modes");
+    constexpr int M = DIM + 2;
+    constexpr int REC = M * NP;
+    const int32_t L = face_lr[k];
+    const int32_t R = face_lr[n_face + k];
+    const int cL = face_code[k];
+    const int cR = face_code[n_face + k];
+    if (L < 0 || L >= n_elem || R >= n_elem || cL >= n_codes || cR >= n_codes) return;
+    T n[DIM];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) n[d] = T(face_geo[d * n_face + k]);
+    const double len = face_geo[DIM * n_face + k];
+    const double isL = face_geo[(DIM + 1) * n_face + k];
+    const double isR = face_geo[(DIM + 2) * n_face + k];
+
+    T pre_L[M], pre_R[M];
+    if (PREFETCH && MODE == kColored) {
+#pragma unroll
+        for (int m = 0; m < M; ++m) pre_L[m] = rhs[(size_t)L * REC + m * NP + j];
+        if (R >= 0) {
+#pragma unroll
+            for (int m = 0; m < M; ++m) pre_R[m] = rhs[(size_t)R * REC + m * NP + j];
+        }
+    }
+    T uL[Q][M], uR[Q][M];
+    {
+        T c[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) c[m] = U[(size_t)L * REC + m * NP + j];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const T t = s_tr[(cL * Q + q) * NP + j];
+#pragma unroll
+            for (int m = 0; m < M; ++m) uL[q][m] = quad_sum(t * c[m]) * T(isL);
+        }
+    }
+    if (R >= 0) {
+        T c[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) c[m] = U[(size_t)R * REC + m * NP + j];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const T t = s_tr[(cR * Q + q) * NP + j];
+#pragma unroll
+            for (int m = 0; m < M; ++m) uR[q][m] = quad_sum(t * c[m]) * T(isR);
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) wall_ghost<DIM, T>(uL[q], n, uR[q]);
+    }
+    T F[Q][M];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) rusanov<DIM, T>(uL[q], uR[q], n, F[q]);
+    {
+        const T sL = T(len * isL);
+        T *dst = MODE == kGather ? buf + (size_t)(2 * k) * REC : rhs + (size_t)L * REC;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            T a = 0;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) a += s_pr[(cL * Q + q) * NP + j] * F[q][m];
+            a *= sL;
+            if (MODE == kColored) dst[m * NP + j] = (PREFETCH ? pre_L[m] : dst[m * NP + j]) - a;
+            else if (MODE == kAtomic) atomic_add<T>(dst + m * NP + j, -a);
+            else dst[m * NP + j] = -a;
+        }
+    }
+    if (R >= 0) {
+        const T sR = T(len * isR);
+        T *dst = MODE == kGather ? buf + (size_t)(2 * k + 1) * REC : rhs + (size_t)R * REC;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            T a = 0;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) a += s_pr[(cR * Q + q) * NP + j] * F[q][m];
+            a *= sR;
+            if (MODE == kColored) dst[m * NP + j] = (PREFETCH ? pre_R[m] : dst[m * NP + j]) + a;
+            else if (MODE == kAtomic) atomic_add<T>(dst + m * NP + j, a);
+            else dst[m * NP + j] = a;
+        }
+    }
+}
+
 // Basis tables of every face code, copied once per work-group into LDS.
 template <class T>
 __device__ __forceinline__ void stage_tables(T *s_tr, T *s_pr, const double *__restrict__ tab_trace,
@@ -347,6 +464,23 @@ __global__ __launch_bounds__(256) void surface_team_kernel(
     if (k >= f_end) return;  // whole teams leave together
     team_face<DIM, NP, Q, MODE, T, PREFETCH>(k, r, n_face, n_elem, face_lr, face_code, face_geo, s_tr, s_pr, n_codes,
                                              U, rhs, buf);
+}
+
+template <int DIM, int NP, int Q, int MODE, class T>
+__global__ __launch_bounds__(256) void surface_mode_team_kernel(
+    int64_t f_begin, int64_t f_end, int64_t n_face, int64_t n_elem,
+    const int32_t *__restrict__ face_lr, const uint8_t *__restrict__ face_code,
+    const double *__restrict__ face_geo, const double *__restrict__ tab_trace,
+    const double *__restrict__ tab_proj, int n_codes,
+    const T *__restrict__ U, T *__restrict__ rhs, T *__restrict__ buf, int remap) {
+    extern __shared__ unsigned char smem_raw[];
+    T *s_tr = reinterpret_cast<T *>(smem_raw);
+    T *s_pr = s_tr + n_codes * Q * NP;
+    stage_tables<T>(s_tr, s_pr, tab_trace, tab_proj, n_codes * Q * NP);
+    const int64_t k = f_begin + ((int64_t)logical_block(remap) * blockDim.x + threadIdx.x) / 4;
+    if (k >= f_end) return;  // whole quads leave together
+    mode_team_face<DIM, NP, Q, MODE, T, true>(k, threadIdx.x % 4, n_face, n_elem, face_lr, face_code, face_geo,
+                                              s_tr, s_pr, n_codes, U, rhs, buf);
 }
 
 // Second pass of the buffered variant: rhs[k] += sum of element k's slots.

@@ -105,10 +105,12 @@ def test_surface_delaunay_walls_ragged(variant, form, block, xcd):
     _check(got, dg.surface_rhs(c.d, c.U), dg.surface_abs(c.d, c.U), "surface delaunay " + variant)
 
 
-@pytest.mark.parametrize("form", ["team", "thread"])
+@pytest.mark.parametrize("form", ["default", "team", "thread", "mode_team"])
 @pytest.mark.parametrize("p", [0, 1])
 @pytest.mark.parametrize("variant", ["colored", "atomic", "gather"])
 def test_surface_tets(p, variant, form):
+    if form == "mode_team" and p != 1:
+        pytest.skip("mode teams need N_p = 4 (tetrahedra, p = 1)")
     c = Case("tets", 6, 3, p)
     c.D.set_launch(form)
     assert c.stats["n_colors"] == 4
@@ -281,7 +283,7 @@ TOL32 = 2e-6
 
 
 @pytest.mark.parametrize("kind,size,p", [("periodic", 16, 2), ("delaunay", 6000, 2), ("tets", 5, 1)])
-@pytest.mark.parametrize("variant", ["colored", "atomic"])
+@pytest.mark.parametrize("variant", ["colored", "atomic", "gather"])
 def test_surface_and_volume_f32(kind, size, p, variant):
     """f32 storage and arithmetic (geometry stored in f64) against the f64
     oracle evaluated on the same f32-rounded DOFs."""
@@ -292,7 +294,8 @@ def test_surface_and_volume_f32(kind, size, p, variant):
     U = U32.astype(np.float64)
     Ug = torch.from_numpy(c.D.to_layout(U32)).cuda()
     rhs = torch.zeros_like(Ug)
-    c.D.surface_rhs(Ug, rhs, variant=variant, precision="f32")
+    ws = c.D.workspace("surface", variant, "f32") if variant == "gather" else None
+    c.D.surface_rhs(Ug, rhs, variant=variant, precision="f32", ws=ws)
     vol = torch.zeros_like(Ug)
     c.D.volume_rhs(Ug, vol, precision="f32")
     torch.cuda.synchronize()
@@ -398,3 +401,56 @@ def test_rk3_refined_vortex_20_steps():
     torch.cuda.synchronize()
     got = D.from_layout(Ug.cpu().numpy())
     assert np.abs(got - U).max() / np.abs(U).max() <= TOL
+
+
+def test_device_layout_permutation_round_trip():
+    import torch
+
+    c = Case("delaunay", 5000, 13, 2)
+    Uo = torch.from_numpy(c.U).cuda()
+    Ul = c.D.to_layout_device(Uo)
+    torch.cuda.synchronize()
+    assert torch.equal(Ul.cpu(), torch.from_numpy(c.D.to_layout(c.U)))
+    back = c.D.from_layout_device(Ul)
+    torch.cuda.synchronize()
+    assert torch.equal(back, Uo)
+
+
+def test_device_child_color_map_matches_refinement():
+    """The GPU closed-form map gives the colors the refinement assigns: halves
+    c / (c+3) mod 6 of every split edge, interior edges = parallel parent edge."""
+    import torch
+
+    from oracle import refine as R
+
+    dgc = _dgc()
+    rng = np.random.default_rng(3)
+    par = rng.integers(0, 6, size=(1000, 3)).astype(np.int8)
+    out = dgc.child_colors(torch.from_numpy(par).cuda()).cpu().numpy()
+    for i in range(len(par)):
+        for k in range(3):
+            assert tuple(out[i, 2 * k:2 * k + 2]) == R.child_colors(int(par[i, k]))
+            assert out[i, 6 + k] == par[i, k]
+    # on a refined mesh: every split parent's three edges and its center child
+    from oracle.coloring import color_faces
+
+    m = synth.periodic_tri(12, jitter=0.0, seed=4)
+    O = build_mesh(m["elem_vert"], m["elem_xyz"])
+    col, _ = color_faces(O, seed=0)
+    st = R.from_base(O, col)
+    flags = synth.refine_flags(np.array([lf.xyz for lf in st.leaves]), np.zeros(O.K), 0, radius=0.3)
+    st, _ = R.refine(st, flags)
+    parents, expect = [], []
+    for i in range(0, len(st.leaves) - 3):
+        lf = st.leaves[i]
+        if lf.level == 1 and i + 3 < len(st.leaves) and st.leaves[i + 3].level == 1:
+            c0, c1, c2, ce = st.leaves[i:i + 4]
+            if c0.edges[0].parent is None or ce.edges[0] is not c2.edges[0]:
+                continue
+            E = [c0.edges[0].parent, c1.edges[1].parent, c2.edges[2].parent]
+            parents.append([e.color for e in E])
+            expect.append([x for e in E for x in (e.children[0].color, e.children[1].color)]
+                          + [ce.edges[k].color for k in range(3)])
+    assert len(parents) > 10
+    got = dgc.child_colors(torch.from_numpy(np.array(parents, dtype=np.int8)).cuda()).cpu().numpy()
+    assert np.array_equal(got, np.array(expect, dtype=np.int8))
