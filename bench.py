@@ -27,19 +27,30 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-PROFILE = os.path.join(ROOT, "profiles", "surface_colored_team_prefetch_delaunay996k_p2_f64.md")
+PROFILES = {
+    "delaunay": os.path.join(ROOT, "profiles", "surface_colored_team_prefetch_delaunay996k_p2_f64.md"),
+    "tets": os.path.join(ROOT, "profiles", "surface_colored_mode_team_kuhn64_tets_p1_f64.md"),
+}
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1601_07613_amd", "csrc", "kernels", f)
                   for f in ("surface.hpp", "euler_dev.hpp")]
 
 
-def profiled_traffic():
+def profiled_traffic(args, launch):
     """HBM bytes per launch measured by rocprofv3 counters for the committed
-    kernel, or None when the kernel source changed since the profile."""
+    kernel on the default configuration of this workload, or None when the
+    kernel source changed since the profile (or the configuration differs)."""
     import hashlib
     import re
 
+    same_launch = (launch.get("form") in ("default", "team_prefetch" if args.workload == "delaunay" else "default")
+                   and launch.get("block") in (0, 256) and not launch.get("xcd_remap"))
+    default = (same_launch and args.seed == 2 and args.layout == "paper" and
+               ((args.workload == "delaunay" and args.points == 500_000 and args.p == 2) or
+                (args.workload == "tets" and args.tet_n == 64 and args.p == 1)))
+    if not default:
+        return None
     try:
-        text = open(PROFILE).read()
+        text = open(PROFILES[args.workload]).read()
     except OSError:
         return None
     h = hashlib.sha256(b"".join(open(f, "rb").read() for f in KERNEL_SOURCES)).hexdigest()[:16]
@@ -203,8 +214,11 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", choices=["delaunay", "tets"], default="delaunay",
+                    help="delaunay: ~1M triangles, p=2 (the headline); tets: 64^3 x 6 Kuhn tetrahedra, p=1")
     ap.add_argument("--points", type=int, default=500_000)
-    ap.add_argument("--p", type=int, default=2)
+    ap.add_argument("--tet-n", type=int, default=64)
+    ap.add_argument("--p", type=int, default=None)
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--only", choices=["all", "colored"], default="all",
                     help="'colored' times the colored pass only (for profiling)")
@@ -246,7 +260,13 @@ def main(argv=None):
     from paper_1601_07613_amd.tune import autotune, time_call
 
     t = time.perf_counter()
-    m = synth.poisson_delaunay(args.points, seed=args.seed)
+    if args.workload == "delaunay":
+        m = synth.poisson_delaunay(args.points, seed=args.seed)
+        p = 2 if args.p is None else args.p
+    else:
+        m = synth.kuhn_tets(args.tet_n, seed=3)
+        p = 1 if args.p is None else args.p
+    args.p = p
     gen_s = time.perf_counter() - t
     log("mesh generated: K=%d in %.1fs" % (len(m["elem_vert"]), gen_s))
     t = time.perf_counter()
@@ -255,8 +275,8 @@ def main(argv=None):
     cst = M.color(seed=0, layout=args.layout)
     colors = M.export("color")
     meas = synth.element_measure(m["elem_xyz"])
-    st = synth.shock_tube_states(synth.element_centroid(m["elem_xyz"]))
-    p = args.p
+    cen = synth.element_centroid(m["elem_xyz"])
+    st = synth.shock_tube_states(cen) if args.workload == "delaunay" else synth.density_wave_states(cen)
     stream = torch.cuda.current_stream()
     log("host preprocessing: build %.2fs, color %.0f ms, layout %.0f ms" % (build_s, cst["color_ms"], cst["layout_ms"]))
 
@@ -353,7 +373,7 @@ def main(argv=None):
             log("%s: %s" % (k2, v))
 
     workloads = None
-    if args.only == "all":
+    if args.only == "all" and args.workload == "delaunay":
         workloads = extra_workloads(dgc, synth, torch, args.steps, args.warmup, log)
 
     cpu = None
@@ -389,16 +409,18 @@ def main(argv=None):
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": "Delaunay triangulation of %d seeded Poisson-disc points in the unit square (%d triangles, "
-                        "%d edges, %d wall edges), 2D Euler p=%d (N_p=%d, M=4), shock tube, colored surface pass, "
-                        "%s layout" % (m["n_vert"], K, E, nb, args.p, D.n_p, args.layout),
+            "workload": ("Delaunay triangulation of %d seeded Poisson-disc points in the unit square (%d triangles, "
+                         "%d edges, %d wall edges), 2D Euler p=%d (N_p=%d, M=4), shock tube, colored surface pass, "
+                         "%s layout" % (m["n_vert"], K, E, nb, args.p, D.n_p, args.layout))
+            if args.workload == "delaunay" else
+            ("periodic %d^3 cubes x 6 Kuhn tetrahedra (%d tets, %d faces), 3D Euler p=%d (N_p=%d, M=5), density "
+             "wave, colored surface pass, %s layout" % (args.tet_n, K, E, args.p, D.n_p, args.layout)),
             "n_elem": K, "n_face": E, "p": args.p, "n_colors": info["n_colors"], "variant": "colored",
             "layout": args.layout, "launch": best,
         },
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": (profiled_traffic() if (args.p == 2 and args.points == 500_000 and args.seed == 2
-                                                        and args.layout == "paper") else None),
+                     "traffic": profiled_traffic(args, best),
                      "algorithmic_bytes_per_launch": ab // info["n_colors"],
                      "launches_per_pass": info["n_colors"],
                      "kernel": "surface_team_kernel (colored), one launch per color"},
