@@ -209,6 +209,35 @@ def extra_workloads(dgc, synth, torch, steps, warmup, log):
     return out
 
 
+def oracle_pool(m, U, p, log):
+    """The oracle's surface term over a pool of host processes, in a child
+    interpreter that never touches the GPU; ``None`` if it fails."""
+    import subprocess
+    import tempfile
+
+    workers = max(1, min(16, os.cpu_count() or 1))
+    with tempfile.TemporaryDirectory() as tmp:
+        path = os.path.join(tmp, "input.npz")
+        np.savez(path, elem_vert=m["elem_vert"], elem_xyz=m["elem_xyz"], U=U, p=p)
+        try:
+            r = subprocess.run([sys.executable, "-m", "oracle.pool_timing", path, str(workers), "2"], cwd=ROOT,
+                               capture_output=True, text=True, timeout=300)
+        except subprocess.TimeoutExpired:
+            log("cpu oracle pool: timed out")
+            return None
+    if r.returncode != 0:
+        log("cpu oracle pool failed: %s" % r.stderr[-500:])
+        return None
+    res = json.loads(r.stdout.strip().splitlines()[-1])
+    dof = U.size
+    log("cpu oracle pool: %.2f s per surface term on %d processes" % (res["seconds"], res["workers"]))
+    return {"value": dof / res["seconds"], "unit": "DOF-updates/s", "cores": res["workers"], "kind": "oracle",
+            "sample": "the same surface term split into %d element chunks over %d host processes (faces on chunk "
+                      "borders evaluated by both sides), %d repetitions" % (4 * res["workers"], res["workers"],
+                                                                             res["reps"]),
+            "matches_single_process": res["matches_single_process"]}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -228,6 +257,8 @@ def main(argv=None):
     ap.add_argument("--xcd-remap", action="store_true")
     ap.add_argument("--layout", choices=["paper", "paper_sfc", "renumber", "none"], default="paper")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-pool", action="store_true",
+                    help="skip the oracle timed over a pool of host processes")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (HBM counter calibration)")
     args = ap.parse_args(argv)
@@ -394,6 +425,8 @@ def main(argv=None):
                "sample": "the full surface term of this workload (%d elements, %d faces), %d repetitions, "
                          "numpy float64, single process" % (K, E, reps)}
         log("cpu oracle: %.2f s per surface term" % cpu_s)
+        if not args.no_cpu_pool:
+            cpu["pool"] = oracle_pool(m, U, args.p, log)
 
     out = {
         "metric": "surface-integral DOF-updates/s",
@@ -423,7 +456,8 @@ def main(argv=None):
                      "traffic": profiled_traffic(args, best),
                      "algorithmic_bytes_per_launch": ab // info["n_colors"],
                      "launches_per_pass": info["n_colors"],
-                     "kernel": "surface_team_kernel (colored), one launch per color"},
+                     "kernel": ("surface_mode_team_kernel" if args.workload == "tets" and best.get("form") in
+                                ("default", "mode_team") else "surface_team_kernel") + " (colored), one launch per color"},
         "cpu_baseline": cpu,
         "host_preprocess": {"generate_s": gen_s, "build_s": build_s, "color_ms": cst["color_ms"],
                             "layout_ms": cst["layout_ms"], "conflicts_after_greedy": cst["conflicts_after_greedy"]},

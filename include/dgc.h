@@ -199,8 +199,11 @@ const char *dgc_last_error(void);
 /* Basis and quadrature tables for an element type and order (Eq. 2 with an
  * orthonormal basis; the quadrature is not given by the paper: Gauss-Legendre
  * with p+1 points on edges, the symmetric 3-point rule on tetrahedron faces
- * (p = 1), collapsed Gauss-Jacobi rules with p+1 points per direction in the
- * volume).  Layout of the f64 array (offsets in doubles, from info):
+ * up to p = 1 and the collapsed Gauss-Jacobi triangle rule with (p+1)^2
+ * points from p = 2, collapsed Gauss-Jacobi rules with p+1 points per
+ * direction in the volume).  Orders: triangles p <= 5, tetrahedra p <= 2;
+ * DGC_E_UNSUPPORTED beyond.  Layout of the f64 array (offsets in doubles,
+ * from info):
  *   trace [n_codes][n_qf][n_p]  phi_j at face point q seen through code c
  *   proj  [n_codes][n_qf][n_p]  w_q * trace (face weights sum to 1)
  *   vb    [n_qv][n_p]           phi_j at volume point q
@@ -208,7 +211,10 @@ const char *dgc_last_error(void);
  * Code c = f * n_orient + o addresses local face f seen with orientation o:
  * o = 0 the face's own point order, 2D: 1 reversed, 2 / 3 reversed points on
  * the first / second half of the edge (hanging edge seen from the coarse
- * side); 3D: the o-th permutation (lexicographic) of the three points. */
+ * side); 3D: the o-th permutation pi (lexicographic) of the face's three
+ * vertices, vertex u of the left element's face order being vertex pi[u] of
+ * this side's face; face point q is placed by its barycentric weights in the
+ * left element's order, so both sides evaluate the same physical point. */
 typedef struct {
     int32_t elem_type, p, dim, n_p, n_qf, n_qv, n_codes, n_orient;
     int64_t off_trace, off_proj, off_vb, off_vd, total; /* in doubles */

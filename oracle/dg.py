@@ -53,10 +53,11 @@ class Discretization:
             self.face_bary = np.stack([1.0 - s, s], axis=1)
             self.face_w = w
         else:
-            if p > 1:
-                raise NotImplementedError("tetrahedral face rule only for p <= 1")
             self.vol_pts, self.vol_w = quadrature.tet_volume_rule(p + 1)
-            self.face_bary, self.face_w = quadrature.tet_face_rule_p1()
+            if p <= 1:
+                self.face_bary, self.face_w = quadrature.tet_face_rule_p1()
+            else:
+                self.face_bary, self.face_w = quadrature.tri_face_rule_bary(p + 1)
         self.vol_B = basis.eval_basis(self.dim, p, self.vol_pts)          # [Qv, Np]
         self.vol_D = basis.eval_grad(self.dim, p, self.vol_pts)           # [Qv, dim, Np]
         self.phi0 = float(basis.eval_basis(self.dim, 0, self.vol_pts[:1])[0, 0])

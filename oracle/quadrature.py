@@ -9,9 +9,14 @@ rules are the readings chosen for this project:
   each, exact for total degree ``2 n - 1``;
 * tetrahedron volume: collapsed product Gauss-Legendre x Gauss-Jacobi (1, 0)
   x Gauss-Jacobi (2, 0), ``n`` points each;
-* tetrahedron faces at ``p = 1``: the symmetric three-point rule with
+* tetrahedron faces at ``p <= 1``: the symmetric three-point rule with
   barycentric points ``(2/3, 1/6, 1/6)`` and permutations, weight 1/3 each
-  (exact for degree 2; weights sum to 1).
+  (exact for degree 2; weights sum to 1);
+* tetrahedron faces at ``p >= 2``: the collapsed triangle rule above with
+  ``n = p + 1`` points per direction, written in barycentric coordinates of
+  the face's vertices (exact for degree ``2 p + 1``; weights sum to 1).  The
+  rule is not symmetric, so each side of a face places its points through the
+  face's vertex order as seen from the left element.
 
 Pins: monomial exactness against ``a! b! / (a + b + 2)!`` (unit triangle),
 ``a! b! c! / (a + b + c + 3)!`` (unit tetrahedron) and ``1 / (k + 1)`` on
@@ -82,3 +87,11 @@ def tet_face_rule_p1():
     for q in range(3):
         bary[q, q] = 2.0 / 3.0
     return bary, np.full(3, 1.0 / 3.0)
+
+
+def tri_face_rule_bary(n: int):
+    """Collapsed rule of :func:`tri_volume_rule` as barycentric points ``[n*n, 3]``
+    ``(1 - xi - eta, xi, eta)`` on a face triangle, weights ``[n*n]`` summing to 1."""
+    pts, w = tri_volume_rule(n)
+    bary = np.stack([1.0 - pts[:, 0] - pts[:, 1], pts[:, 0], pts[:, 1]], axis=1)
+    return bary, 2.0 * w

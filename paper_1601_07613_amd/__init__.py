@@ -37,6 +37,9 @@ class Mesh:
 
     def __init__(self, handle: C.c_void_p):
         self._h = handle
+        # held by the instance: module globals may already be cleared when
+        # the interpreter finalises the last meshes
+        self._free = _L.dgc_mesh_free
 
     @classmethod
     def build(cls, elem_vert, elem_xyz) -> "Mesh":
@@ -49,8 +52,9 @@ class Mesh:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            _L.dgc_mesh_free(h)
+        free = getattr(self, "_free", None)
+        if h is not None and h.value and free is not None:
+            free(h)
             self._h = None
 
     def color(self, seed: int = 0, max_swaps: int = -1, algorithm: str = "paper", layout: str = "paper") -> dict:

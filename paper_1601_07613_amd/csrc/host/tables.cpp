@@ -157,7 +157,7 @@ const int kPerm3[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1},
 dgc_status build_tables(int32_t elem_type, int p, dgc_table_info *info, std::vector<double> *out) {
     if (elem_type != DGC_TRI && elem_type != DGC_TET) return fail(DGC_E_ARG, "unknown element type");
     const int dim = elem_type == DGC_TRI ? 2 : 3;
-    if (p < 0 || (dim == 2 && p > 5) || (dim == 3 && p > 1))
+    if (p < 0 || (dim == 2 && p > 5) || (dim == 3 && p > 2))
         return fail(DGC_E_UNSUPPORTED, "order p=" + std::to_string(p) + " is not supported for this element");
     dgc_table_info ti{};
     ti.elem_type = elem_type;
@@ -166,7 +166,7 @@ dgc_status build_tables(int32_t elem_type, int p, dgc_table_info *info, std::vec
     ti.n_p = nmodes(dim, p);
     const int n = p + 1;
     ti.n_qv = dim == 2 ? n * n : n * n * n;
-    ti.n_qf = dim == 2 ? p + 1 : 3;
+    ti.n_qf = dim == 2 ? p + 1 : (p <= 1 ? 3 : n * n);
     ti.n_orient = dim == 2 ? 4 : 6;
     const int nfaces = dim == 2 ? 3 : 4;
     ti.n_codes = nfaces * ti.n_orient;
@@ -181,16 +181,35 @@ dgc_status build_tables(int32_t elem_type, int p, dgc_table_info *info, std::vec
     out->assign(ti.total, 0.0);
     double *T = out->data();
 
-    // face rule
-    std::vector<double> fs, fw;
+    // face rule.  Edges: Gauss-Legendre on [0, 1].  Tetrahedron faces, as
+    // barycentric weights fb[q][u] of the face's vertices in the left
+    // element's order: the symmetric 3-point rule (2/3, 1/6, 1/6) up to
+    // p = 1, else the collapsed Gauss-Jacobi product with n points per
+    // direction (exact for degree 2n - 1), weights summing to 1.
+    std::vector<double> fs, fw, fb;
     if (dim == 2) {
         gauss_jacobi(qf, 0.0, 0.0, fs, fw);
         for (int q = 0; q < qf; ++q) {
             fs[q] = 0.5 * (fs[q] + 1.0);
             fw[q] *= 0.5;
         }
-    } else {
+    } else if (p <= 1) {
         fw.assign(3, 1.0 / 3.0);
+        fb.assign(9, 1.0 / 6.0);
+        for (int q = 0; q < 3; ++q) fb[q * 3 + q] = 2.0 / 3.0;
+    } else {
+        std::vector<double> xa, wa, xb, wb;
+        gauss_jacobi(n, 0.0, 0.0, xa, wa);
+        gauss_jacobi(n, 1.0, 0.0, xb, wb);
+        for (int i = 0; i < n; ++i)
+            for (int k = 0; k < n; ++k) {
+                double r = 0.5 * (1.0 + xa[i]) * (1.0 - xb[k]) - 1.0, s = xb[k];
+                double x = 0.5 * (1.0 + r), y = 0.5 * (1.0 + s);
+                fb.push_back(1.0 - x - y);
+                fb.push_back(x);
+                fb.push_back(y);
+                fw.push_back(wa[i] * wb[k] / 4.0);
+            }
     }
     std::vector<double> phi(np), grad(dim * np);
     for (int f = 0; f < nfaces; ++f) {
@@ -210,11 +229,10 @@ dgc_status build_tables(int32_t elem_type, int p, dgc_table_info *info, std::vec
                     xi[0] = A[0] + t * (B[0] - A[0]);
                     xi[1] = A[1] + t * (B[1] - A[1]);
                 } else {
-                    int cq = kPerm3[o][q];  // canonical point of this face seen by point q
-                    for (int v = 0; v < 3; ++v) {
-                        double bw = v == cq ? 2.0 / 3.0 : 1.0 / 6.0;
-                        const double *V = kRefTet[kTetFace[f][v]];
-                        for (int e = 0; e < 3; ++e) xi[e] += bw * V[e];
+                    // the left element's face vertex u is this side's face vertex kPerm3[o][u]
+                    for (int u = 0; u < 3; ++u) {
+                        const double *V = kRefTet[kTetFace[f][kPerm3[o][u]]];
+                        for (int e = 0; e < 3; ++e) xi[e] += fb[q * 3 + u] * V[e];
                     }
                 }
                 dubiner(dim, p, xi, phi.data(), nullptr);

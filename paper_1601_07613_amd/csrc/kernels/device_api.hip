@@ -145,12 +145,15 @@ dgc_status dispatch(const dgc_dmesh *dm, int elem_type, int p, F &&f) {
             case 1: return f(Impl<2, 3, 2, 4, T>{});
             case 2: return f(Impl<2, 6, 3, 9, T>{});
             case 3: return f(Impl<2, 10, 4, 16, T>{});
+            case 4: return f(Impl<2, 15, 5, 25, T>{});
+            case 5: return f(Impl<2, 21, 6, 36, T>{});
             default: break;
         }
     } else if (elem_type == DGC_TET) {
         switch (p) {
             case 0: return f(Impl<3, 1, 3, 1, T>{});
             case 1: return f(Impl<3, 4, 3, 8, T>{});
+            case 2: return f(Impl<3, 10, 9, 27, T>{});
             default: break;
         }
     }

@@ -34,8 +34,17 @@ def _states(m, K):
     return synth.shock_tube_states(cen)
 
 
+def _eps(kind, p):
+    """Noise level of the higher modes that keeps every trace state physical
+    (orthonormal modes grow towards the vertices with the order)."""
+    if kind == "tets":
+        return 0.02 if p <= 1 else 0.005
+    return 0.02 if p <= 3 else 0.004
+
+
 class Case:
-    def __init__(self, kind, size, seed, p, cseed=0, eps=0.02):
+    def __init__(self, kind, size, seed, p, cseed=0, eps=None):
+        eps = _eps(kind, p) if eps is None else eps
         import torch
 
         dgc = _dgc()
@@ -84,7 +93,7 @@ def _volume_abs(d, U):
 
 
 @pytest.mark.parametrize("form", ["team", "team_prefetch", "thread"])
-@pytest.mark.parametrize("p", [0, 1, 2, 3])
+@pytest.mark.parametrize("p", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("variant", ["colored", "atomic", "gather"])
 def test_surface_periodic_triangles(p, variant, form):
     c = Case("periodic", 16, 1, p)
@@ -106,7 +115,7 @@ def test_surface_delaunay_walls_ragged(variant, form, block, xcd):
 
 
 @pytest.mark.parametrize("form", ["default", "team", "thread", "mode_team"])
-@pytest.mark.parametrize("p", [0, 1])
+@pytest.mark.parametrize("p", [0, 1, 2])
 @pytest.mark.parametrize("variant", ["colored", "atomic", "gather"])
 def test_surface_tets(p, variant, form):
     if form == "mode_team" and p != 1:
@@ -119,8 +128,9 @@ def test_surface_tets(p, variant, form):
 
 
 @pytest.mark.parametrize("kind,size,p", [("periodic", 16, 0), ("periodic", 16, 1), ("periodic", 16, 2),
-                                         ("periodic", 16, 3), ("delaunay", 6000, 2), ("tets", 5, 0),
-                                         ("tets", 5, 1)])
+                                         ("periodic", 16, 3), ("periodic", 16, 4), ("periodic", 16, 5),
+                                         ("delaunay", 6000, 2), ("tets", 5, 0),
+                                         ("tets", 5, 1), ("tets", 5, 2)])
 def test_volume(kind, size, p):
     import torch
 
@@ -282,14 +292,18 @@ def test_full_size_sampled(full_c1):
 TOL32 = 2e-6
 
 
-@pytest.mark.parametrize("kind,size,p", [("periodic", 16, 2), ("delaunay", 6000, 2), ("tets", 5, 1)])
+@pytest.mark.parametrize("kind,size,p", [("periodic", 16, 2), ("periodic", 16, 5), ("delaunay", 6000, 2),
+                                         ("tets", 5, 1), ("tets", 5, 2)])
 @pytest.mark.parametrize("variant", ["colored", "atomic", "gather"])
 def test_surface_and_volume_f32(kind, size, p, variant):
     """f32 storage and arithmetic (geometry stored in f64) against the f64
-    oracle evaluated on the same f32-rounded DOFs."""
+    oracle evaluated on the same f32-rounded DOFs.  The worst-case rounding
+    error of the trace and projection sums grows linearly with their length
+    N_p + Q, so the bar set at p = 2 (N_p + Q = 9) is scaled by that length."""
     import torch
 
     c = Case(kind, size, 12, p)
+    tol = TOL32 * max(1.0, (c.D.n_p + c.D.tinfo["n_qf"]) / 9.0)
     U32 = c.U.astype(np.float32)
     U = U32.astype(np.float64)
     Ug = torch.from_numpy(c.D.to_layout(U32)).cuda()
@@ -299,7 +313,7 @@ def test_surface_and_volume_f32(kind, size, p, variant):
     vol = torch.zeros_like(Ug)
     c.D.volume_rhs(Ug, vol, precision="f32")
     torch.cuda.synchronize()
-    _check32 = lambda got, ref, scale, what: _check_tol(got, ref, scale, what, TOL32)
+    _check32 = lambda got, ref, scale, what: _check_tol(got, ref, scale, what, tol)
     _check32(c.D.from_layout(rhs.cpu().numpy()).astype(np.float64), dg.surface_rhs(c.d, U),
              dg.surface_abs(c.d, U), "f32 surface")
     _check32(c.D.from_layout(vol.cpu().numpy()).astype(np.float64), dg.volume_rhs(c.d, U),

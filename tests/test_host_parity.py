@@ -127,7 +127,8 @@ def test_mesh_errors():
     assert e.value.name == "DGC_E_MESH"
 
 
-@pytest.mark.parametrize("et,dim,p", [(0, 2, 0), (0, 2, 1), (0, 2, 2), (0, 2, 3), (2, 3, 0), (2, 3, 1)])
+@pytest.mark.parametrize("et,dim,p", [(0, 2, 0), (0, 2, 1), (0, 2, 2), (0, 2, 3), (0, 2, 4), (0, 2, 5), (2, 3, 0),
+                                      (2, 3, 1), (2, 3, 2)])
 def test_tables_match_oracle_basis(et, dim, p):
     info, T = dgc.tables(et, p)
     npm, qf, qv = info["n_p"], info["n_qf"], info["n_qv"]
@@ -149,15 +150,18 @@ def test_tables_match_oracle_basis(et, dim, p):
                 assert np.abs(pr[f * 4 + o] - fw[:, None] * ref).max() < 1e-13
     else:
         x, w = oquad.tet_volume_rule(p + 1)
-        bary, fw = oquad.tet_face_rule_p1()
+        bary, fw = oquad.tet_face_rule_p1() if p <= 1 else oquad.tri_face_rule_bary(p + 1)
+        assert qf == len(fw)
         faces = [(1, 2, 3), (0, 2, 3), (0, 1, 3), (0, 1, 2)]
         perms = [(0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)]
         V = obasis.REF_VERTS[3]
         for f, fv in enumerate(faces):
             for o, pm in enumerate(perms):
-                pts = np.array([bary[pm[q]] @ V[list(fv)] for q in range(3)])
+                # the left element's face vertex u is vertex pm[u] of this side's face
+                pts = bary @ V[[fv[pm[u]] for u in range(3)]]
                 ref = obasis.eval_basis(3, p, pts)
                 assert np.abs(tr[f * 6 + o] - ref).max() < 1e-13
+                assert np.abs(pr[f * 6 + o] - fw[:, None] * ref).max() < 1e-13
     assert np.abs(vb - obasis.eval_basis(dim, p, x)).max() < 1e-13
     G = obasis.eval_grad(dim, p, x)
     for d in range(dim):

@@ -7,7 +7,7 @@ import pytest
 from oracle import basis, quadrature as Q
 
 
-@pytest.mark.parametrize("p", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("p", [0, 1, 2, 3, 4, 5])
 def test_triangle_orthonormal(p):
     x, w = Q.tri_volume_rule(p + 2)
     B = basis.eval_basis(2, p, x)
@@ -25,7 +25,7 @@ def test_tet_orthonormal(p):
     assert np.abs(G - np.eye(B.shape[1])).max() < 1e-13
 
 
-@pytest.mark.parametrize("dim,p", [(2, 1), (2, 2), (2, 3), (3, 1), (3, 2)])
+@pytest.mark.parametrize("dim,p", [(2, 1), (2, 2), (2, 3), (2, 4), (2, 5), (3, 1), (3, 2)])
 def test_span_is_polynomials_of_degree_p(dim, p):
     rng = np.random.default_rng(5)
     pts = rng.random((200, dim))

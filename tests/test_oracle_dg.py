@@ -14,7 +14,7 @@ def _tri(n=8, seed=1):
     return build_mesh(m["elem_vert"], m["elem_xyz"])
 
 
-@pytest.mark.parametrize("p", [0, 1, 2, 3])
+@pytest.mark.parametrize("p", [0, 1, 2, 3, 4, 5])
 def test_free_stream_triangles(p):
     M = _tri(6)
     d = dg.Discretization(M, p)
@@ -23,7 +23,7 @@ def test_free_stream_triangles(p):
     assert np.abs(dg.rhs(d, U)).max() < 1e-13 * scale
 
 
-@pytest.mark.parametrize("p", [0, 1])
+@pytest.mark.parametrize("p", [0, 1, 2])
 def test_free_stream_tets(p):
     t = synth.kuhn_tets(3)
     M = build_mesh(t["elem_vert"], t["elem_xyz"])
@@ -115,3 +115,29 @@ def test_convergence_isentropic_vortex_p1():
     rates, errs = _rates(1, [8, 16, 32], 0.05, lambda X: synth.isentropic_vortex(X, 0.0, radius=R),
                          lambda X: synth.isentropic_vortex(X, 0.05, radius=R))
     assert rates[-1] >= 1.8, (rates, errs)
+
+
+@pytest.mark.parametrize("kind,p", [("tri", 1), ("tri", 3), ("tet", 1), ("tet", 2)])
+def test_face_points_coincide_from_both_sides(kind, p):
+    # every face quadrature point, mapped through the left and through the right
+    # element's affine map, lands on the same physical point (up to a whole
+    # period on the torus): a wrong vertex order on either side fails this
+    if kind == "tri":
+        m = synth.periodic_tri(5, seed=4)
+    else:
+        m = synth.kuhn_tets(4, seed=4)
+    M = build_mesh(m["elem_vert"], m["elem_xyz"])
+    d = dg.Discretization(M, p)
+    inter = np.nonzero(M.face_elem[:, 1] >= 0)[0]
+    xyz = M.elem_xyz
+    phys = []
+    for side in (0, 1):
+        e = M.face_elem[inter, side]
+        ref = np.einsum("qv,fvd->fqd", d.face_bary, M.face_ref[inter, side])
+        J = np.stack([xyz[e, k + 1] - xyz[e, 0] for k in range(M.dim)], axis=2)   # columns = edge vectors
+        phys.append(xyz[e, 0][:, None, :] + np.einsum("fde,fqe->fqd", J, ref))
+    diff = phys[0] - phys[1]
+    assert np.abs(diff - np.round(diff)).max() < 1e-13
+    # and the rule is not degenerate: distinct points on every face
+    if d.face_bary.shape[0] > 1:
+        assert np.abs(np.diff(phys[0], axis=1)).max(axis=2).min() > 1e-6

@@ -48,3 +48,22 @@ def test_tet_face_rule_degree_two():
                 exact = 2.0 * math.factorial(a) * math.factorial(b) * math.factorial(c) / math.factorial(a + b + c + 2)
                 got = (w * bary[:, 0] ** a * bary[:, 1] ** b * bary[:, 2] ** c).sum()
                 assert abs(got - exact) < 1e-15
+
+
+@pytest.mark.parametrize("n", [3, 4])
+def test_tet_face_rule_collapsed_barycentric(n):
+    # the p >= 2 face rule: every barycentric monomial of degree <= 2n - 1 is
+    # averaged exactly (closed form 2 a! b! c! / (a + b + c + 2)!), and the
+    # same rule is exact when the face's vertices are listed in any order
+    bary, w = Q.tri_face_rule_bary(n)
+    assert bary.shape == (n * n, 3) and abs(w.sum() - 1.0) < 1e-15
+    assert np.abs(bary.sum(axis=1) - 1.0).max() < 1e-15 and bary.min() > 0
+    for perm in ([0, 1, 2], [2, 0, 1], [1, 0, 2]):
+        B = bary[:, perm]
+        for a in range(2 * n):
+            for b in range(2 * n - a):
+                for c in range(2 * n - a - b):
+                    exact = 2.0 * math.factorial(a) * math.factorial(b) * math.factorial(c) / math.factorial(
+                        a + b + c + 2)
+                    got = (w * B[:, 0] ** a * B[:, 1] ** b * B[:, 2] ** c).sum()
+                    assert abs(got - exact) < 1e-14
