@@ -187,6 +187,42 @@ def extra_workloads(dgc, synth, torch, steps, warmup, log):
     log("c3: %s" % out["c3_amr_level3_p2"])
     del DA, A
 
+    # c3 dynamic: the same base, a feature moving across the torus; every 10
+    # SSP-RK3 steps coarsen behind it and refine one level (up to 3) around it,
+    # moving the solution on the device; 60 steps, p = 2
+    from paper_1601_07613_amd.amr import AdaptiveRun
+
+    A = dgc.Mesh.build(m["elem_vert"], m["elem_xyz"])
+    A.color(seed=0)
+    DA = dgc.DeviceMesh(A, 2)
+    cen = synth.element_centroid(m["elem_xyz"])
+    U0 = synth.perturbed_dofs(synth.element_measure(m["elem_xyz"]), synth.isentropic_vortex(cen, 0.0), DA.n_p,
+                              eps=0.0)
+    dt_dyn = 0.1 * (1.0 / 128 / 8) / 3.0
+
+    def crit(xyz, lev, tt):
+        return synth.adapt_flags(xyz, lev, (0.5 + 100.0 * tt, 0.5 + 60.0 * tt), 0.15, 0.2, max_level=3)
+
+    run = AdaptiveRun(A, 2, torch.from_numpy(DA.to_layout(U0)).cuda(), dt_dyn, crit, every=10)
+    t0 = time.perf_counter()
+    run.run(60)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_us = time_call(lambda: run.D.rk_step(run.U, dt_dyn, ws=run.ws), reps=5, warmup=1) * 1e3
+    log_ = run.log
+    out["c3_dynamic_p2"] = {
+        "adapt_cycles": len(log_), "steps": 60, "wall_s": wall,
+        "n_elem_range": [min(r["n_elem"] for r in log_), max(r["n_elem"] for r in log_)],
+        "merged_total": sum(r["merged"] for r in log_), "refined_total": sum(r["refined"] for r in log_),
+        "max_colors": max(r["n_colors"] for r in log_),
+        "host_adapt_ms_mean": sum(r["host_ms"] for r in log_) / len(log_),
+        "device_transfer_us_mean": sum(r["transfer_us"] for r in log_) / len(log_),
+        "rk3_step_us_final_mesh": step_us,
+        "finite": bool(torch.isfinite(run.U).all()),
+    }
+    log("c3 dynamic: %s" % out["c3_dynamic_p2"])
+    del run, DA, A
+
     # c4: serving -- 256 solves, Poisson arrivals at 50/s, 100 SSP-RK3 steps each
     from synth.requests import request_stream
     from paper_1601_07613_amd.serve import GPUExecutor, Request, Server

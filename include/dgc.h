@@ -159,6 +159,24 @@ dgc_status dgc_set_colors(dgc_mesh *m, const int8_t *colors, uint32_t layout_fla
 dgc_status dgc_mesh_refine(const dgc_mesh *parent, const uint8_t *flags, dgc_mesh **out,
                            int64_t *n_closure);
 
+/* Undo 4-way splits (the coarsening of Section 3.2).  Four leaves merge
+ * back into the element they were split from when they are its children
+ * 0..3, all four are flagged and none of their edges is split (so no
+ * neighbour ends up two levels finer); the merged element takes the place
+ * of its first child.  Its edges are the parent edges, whose colors were
+ * kept, so coarsening restores the parent coloring without any search; a
+ * parent edge whose halves no leaf references any more is unsplit.
+ *   fine      a colored mesh (a conforming base has nothing to merge and
+ *             comes back with the same leaves, renumbered as a refined mesh
+ *             would be).
+ *   flags     host uint8 [n_elem]: nonzero = this leaf may merge.
+ *   n_merged  out (may be NULL): number of merged families.
+ * The result is colored and laid out (DGC_LAYOUT_PAPER); the origin of every
+ * leaf is exported as DGC_ARR_ADAPT_* / DGC_ARR_DEV_ADAPT_*, as after
+ * dgc_mesh_refine.  Errors: DGC_E_ARG, DGC_E_NOT_COLORED, DGC_E_UNSUPPORTED
+ * (tetrahedra). */
+dgc_status dgc_mesh_coarsen(const dgc_mesh *fine, const uint8_t *flags, dgc_mesh **out, int64_t *n_merged);
+
 dgc_status dgc_mesh_info(const dgc_mesh *m, dgc_mesh_info_t *info);
 
 /* Arrays that dgc_mesh_export can copy out (host memory, caller-owned). */
@@ -181,10 +199,19 @@ enum {
     DGC_ARR_DEV_FACE_GEO = 22,  /* f64 [dim+3][E]: n_0..n_{dim-1}, |f|, 1/sqrt(detJ_L), 1/sqrt(detJ_R) (0 at walls) */
     DGC_ARR_DEV_ELEM_GEO = 23,  /* f64 [dim*dim+1][K]: (J^-1)_{de} row-major, then sqrt(det J) */
     DGC_ARR_DEV_ELEM_SLOTS = 24,/* int32 [max_slots][K]: 2*face+side of each element's faces, -1 padded */
+    DGC_ARR_DEV_ADAPT_KIND = 25,/* int8 [K] (layout order): origin of each leaf, as DGC_ARR_ADAPT_KIND */
+    DGC_ARR_DEV_ADAPT_SRC = 26, /* int32 [4][K] (layout order): its source leaves as layout ids of the
+                                   previous mesh, -1 padded */
     /* refinement bookkeeping */
     DGC_ARR_ELEM_LEVEL = 30,    /* int8 [K]: refinement level of each leaf (original ids) */
     DGC_ARR_ELEM_XYZ = 31,      /* f64 [K][nv][dim]: element vertex coordinates (original ids) */
-    DGC_ARR_ELEM_VERT = 32      /* int32 [K][nv]: element vertex ids (original ids) */
+    DGC_ARR_ELEM_VERT = 32,     /* int32 [K][nv]: element vertex ids (original ids) */
+    /* meshes made by dgc_mesh_refine / dgc_mesh_coarsen: where each leaf came from */
+    DGC_ARR_ADAPT_KIND = 33,    /* int8 [K]: 0 the same leaf, 1 + k child k of a leaf (k = 0..2 corner
+                                   children at v0, v1, v2, k = 3 the center child), 5 the parent of
+                                   four leaves (children 0..3) */
+    DGC_ARR_ADAPT_SRC = 34      /* int32 [K][4]: those leaves (original ids of the previous mesh),
+                                   -1 padded */
 };
 
 /* Copy array `which` into dst (bytes available).  *needed (if not NULL)
@@ -208,6 +235,11 @@ const char *dgc_last_error(void);
  *   proj  [n_codes][n_qf][n_p]  w_q * trace (face weights sum to 1)
  *   vb    [n_qv][n_p]           phi_j at volume point q
  *   vd    [dim][n_qv][n_p]      w_q * d phi_j / d xi_d at volume point q
+ *   prolong [4][n_p][n_p]       triangles only (empty for tetrahedra): L2
+ *                               projection of a parent's modes onto child k
+ *                               (corner children at v0, v1, v2, then the
+ *                               center child; Section 3.2 split), see
+ *                               dgc_adapt_transfer
  * Code c = f * n_orient + o addresses local face f seen with orientation o:
  * o = 0 the face's own point order, 2D: 1 reversed, 2 / 3 reversed points on
  * the first / second half of the edge (hanging edge seen from the coarse
@@ -217,7 +249,7 @@ const char *dgc_last_error(void);
  * left element's order, so both sides evaluate the same physical point. */
 typedef struct {
     int32_t elem_type, p, dim, n_p, n_qf, n_qv, n_codes, n_orient;
-    int64_t off_trace, off_proj, off_vb, off_vd, total; /* in doubles */
+    int64_t off_trace, off_proj, off_vb, off_vd, off_prolong, total; /* in doubles */
 } dgc_table_info;
 
 dgc_status dgc_tables(int32_t elem_type, int32_t p, dgc_table_info *info, double *dst, size_t bytes,
@@ -315,6 +347,24 @@ dgc_status dgc_permute_records(const void *src, void *dst, const int32_t *perm, 
  * parent edges 0, 1, 2 (entries 6..8).  dgc_mesh_refine applies the same map
  * on the host.  Errors: DGC_E_ARG, DGC_E_HIP. */
 dgc_status dgc_child_colors(const int8_t *parent_colors, int64_t n, int8_t *child_colors, void *stream);
+
+/* Move a solution onto a mesh made by dgc_mesh_refine / dgc_mesh_coarsen
+ * (refinement under a running solution, Section 3.2), on the device.  Every
+ * new leaf gets the L2 projection of the previous solution: an unchanged leaf
+ * copies its modes, child k of a split leaf gets P_k c (P_k from the tables'
+ * prolong block), a merged parent gets sum_k P_k^T c_k over its four
+ * children (exact inverse of the split: sum_k P_k^T P_k = I).
+ *   dm      device view of the NEW mesh (triangles, p <= 5).
+ *   U_old   device f64 [n_old][n_var][n_p] in the previous mesh's layout order.
+ *   U_new   device f64 [dm->n_elem][n_var][n_p] in the new layout order;
+ *           must not alias U_old.
+ *   kind    device int8 [n_elem]  (DGC_ARR_DEV_ADAPT_KIND of the new mesh)
+ *   src     device int32 [4][n_elem] (DGC_ARR_DEV_ADAPT_SRC of the new mesh)
+ * A record whose source id falls outside [0, n_old) or whose kind is unknown
+ * is filled with NaN.  Errors: DGC_E_ARG, DGC_E_UNSUPPORTED (tetrahedra),
+ * DGC_E_HIP. */
+dgc_status dgc_adapt_transfer(const dgc_dmesh *dm, const double *U_old, int64_t n_old, double *U_new,
+                              const int8_t *kind, const int32_t *src, void *stream);
 
 /* Layout of the dgc_rk_step workspace for n = n_elem * n_var * n_p values:
  * byte offsets of the stage states U1, U2 (f64), the stage right-hand side

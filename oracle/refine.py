@@ -69,21 +69,29 @@ class Edge:
 
 
 class Leaf:
-    __slots__ = ("verts", "xyz", "level", "edges")
+    __slots__ = ("verts", "xyz", "level", "edges", "parent", "child")
 
-    def __init__(self, verts, xyz, level, edges):
+    def __init__(self, verts, xyz, level, edges, parent=None, child=-1):
         self.verts = verts      # 3 vertex ids, counter-clockwise
         self.xyz = xyz          # [3, 2] own coordinates
         self.level = level
         self.edges = edges      # 3 Edge nodes; local edge k joins verts[k], verts[k+1]
+        self.parent = parent    # the Leaf this one was split from (None on the base mesh)
+        self.child = child      # 0..3: corner children at v0, v1, v2, then the center child
 
 
 class RefineState:
-    """Leaves of a (possibly nonconforming) triangle mesh with its edge tree."""
+    """Leaves of a (possibly nonconforming) triangle mesh with its edge tree.
 
-    def __init__(self, leaves, n_vert):
+    ``origin[i]`` says where leaf ``i`` came from in the previous state:
+    ``(0, [j])`` the same leaf ``j``; ``(1 + k, [j])`` child ``k`` of leaf
+    ``j``; ``(5, [j0, j1, j2, j3])`` the parent of the four leaves ``j0..j3``
+    (children 0..3).  The base state has ``origin = None``."""
+
+    def __init__(self, leaves, n_vert, origin=None):
         self.leaves = leaves
         self.n_vert = n_vert
+        self.origin = origin
 
 
 def from_base(mesh, color) -> RefineState:
@@ -157,6 +165,7 @@ def refine(state: RefineState, flags):
     split = closure(state, flags)
     n_flag = sum(1 for f in flags if f)
     new_leaves = []
+    origin = []
     for i, lf in enumerate(state.leaves):
         if i not in split:
             continue
@@ -165,7 +174,9 @@ def refine(state: RefineState, flags):
     for i, lf in enumerate(state.leaves):
         if i not in split:
             new_leaves.append(lf)
+            origin.append((0, [i]))
             continue
+        origin.extend((1 + k, [i]) for k in range(4))
         v0, v1, v2 = lf.verts
         E0, E1, E2 = lf.edges
         m01, m12, m20 = E0.mid, E1.mid, E2.mid
@@ -179,13 +190,54 @@ def refine(state: RefineState, flags):
         I2 = Edge(m01, m12, E2.color)
         lvl = lf.level + 1
         new_leaves.append(Leaf([v0, m01, m20], np.array([x[0], x01, x20]), lvl,
-                               [_half(E0, v0, m01), I1, _half(E2, m20, v0)]))
+                               [_half(E0, v0, m01), I1, _half(E2, m20, v0)], lf, 0))
         new_leaves.append(Leaf([m01, v1, m12], np.array([x01, x[1], x12]), lvl,
-                               [_half(E0, m01, v1), _half(E1, v1, m12), I2]))
+                               [_half(E0, m01, v1), _half(E1, v1, m12), I2], lf, 1))
         new_leaves.append(Leaf([m20, m12, v2], np.array([x20, x12, x[2]]), lvl,
-                               [I0, _half(E1, m12, v2), _half(E2, v2, m20)]))
-        new_leaves.append(Leaf([m12, m20, m01], np.array([x12, x20, x01]), lvl, [I0, I1, I2]))
-    return RefineState(new_leaves, state.n_vert), len(split) - n_flag
+                               [I0, _half(E1, m12, v2), _half(E2, v2, m20)], lf, 2))
+        new_leaves.append(Leaf([m12, m20, m01], np.array([x12, x20, x01]), lvl, [I0, I1, I2], lf, 3))
+    return RefineState(new_leaves, state.n_vert, origin), len(split) - n_flag
+
+
+def coarsen(state: RefineState, flags):
+    """One coarsening pass (the inverse of a split, Section 3.2); returns
+    ``(new_state, n_merged)``.
+
+    Four leaves merge back into their parent when they are the parent's four
+    children, all four are flagged and none of their edges is split (a split
+    edge means a neighbour two levels finer than the parent would be).  The
+    parent takes the place of its first child.  Its edges are the parent
+    edges, which kept their colors: coarsening restores the parent coloring.
+    A parent edge whose two halves no leaf references any more is unsplit
+    (its midpoint id is not reused)."""
+    leaves = state.leaves
+    K = len(leaves)
+    new_leaves = []
+    origin = []
+    merged = []
+    i = 0
+    while i < K:
+        lf = leaves[i]
+        par = lf.parent
+        if (par is not None and lf.child == 0 and i + 3 < K
+                and all(leaves[i + k].parent is par and leaves[i + k].child == k for k in range(4))
+                and all(flags[i + k] for k in range(4))
+                and all(e.children is None for k in range(4) for e in leaves[i + k].edges)):
+            new_leaves.append(par)
+            origin.append((5, [i, i + 1, i + 2, i + 3]))
+            merged.append(par)
+            i += 4
+            continue
+        new_leaves.append(lf)
+        origin.append((0, [i]))
+        i += 1
+    used = {id(e) for lf in new_leaves for e in lf.edges}
+    for par in merged:
+        for e in par.edges:
+            if e.children is not None and not any(id(ch) in used for ch in e.children):
+                e.children = None
+                e.mid = -1
+    return RefineState(new_leaves, state.n_vert, origin), len(merged)
 
 
 def to_mesh(state: RefineState):

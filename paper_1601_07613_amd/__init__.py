@@ -78,6 +78,15 @@ class Mesh:
         _lib.check(_L.dgc_mesh_refine(self._h, _ptr(f), C.byref(h), C.byref(ncl)), "dgc_mesh_refine")
         return Mesh(h), int(ncl.value)
 
+    def coarsen(self, flags) -> tuple["Mesh", int]:
+        """Merge flagged sibling quadruples back into their parent; returns
+        ``(mesh, number of merged families)``."""
+        f = np.ascontiguousarray(flags, dtype=np.uint8)
+        h = C.c_void_p()
+        n = C.c_int64()
+        _lib.check(_L.dgc_mesh_coarsen(self._h, _ptr(f), C.byref(h), C.byref(n)), "dgc_mesh_coarsen")
+        return Mesh(h), int(n.value)
+
     def info(self) -> dict:
         i = _lib.MeshInfo()
         _lib.check(_L.dgc_mesh_info(self._h, C.byref(i)), "dgc_mesh_info")
@@ -243,6 +252,32 @@ class DeviceMesh:
         wb = ws.numel() * ws.element_size() if ws is not None else 0
         _lib.check(_L.dgc_surface_rhs(C.byref(self.dm), U.data_ptr(), rhs.data_ptr(), VARIANTS[variant],
                                       PRECISIONS[precision], wp, wb, _stream_ptr(stream)), "dgc_surface_rhs")
+
+    def adapt_arrays(self):
+        """Device copies (made once) of this mesh's origin arrays: kind
+        ``[K]`` int8 and sources ``[4, K]`` int32, both in layout order."""
+        if getattr(self, "_adapt", None) is None:
+            dev = self.face_lr.device
+            import torch
+
+            self._adapt = (torch.from_numpy(self.mesh.export("dev_adapt_kind")).to(dev),
+                           torch.from_numpy(self.mesh.export("dev_adapt_src")).to(dev))
+        return self._adapt
+
+    def transfer_from(self, U_old, stream=None):
+        """Solution on this mesh (made by ``Mesh.refine`` / ``Mesh.coarsen``)
+        from ``U_old`` (f64 device tensor ``[K_old, M, N_p]``, layout order of
+        the mesh it was made from), by L2 projection on the device."""
+        import torch
+
+        if U_old.dtype != torch.float64 or not U_old.is_contiguous() or U_old.dim() != 3:
+            raise ValueError("U_old must be a contiguous float64 [K, M, N_p] tensor")
+        dev = U_old.device
+        kind, src = self.adapt_arrays()
+        U_new = torch.empty((self.K, self.n_var, self.n_p), dtype=torch.float64, device=dev)
+        _lib.check(_L.dgc_adapt_transfer(C.byref(self.dm), U_old.data_ptr(), U_old.shape[0], U_new.data_ptr(),
+                                         kind.data_ptr(), src.data_ptr(), _stream_ptr(stream)), "dgc_adapt_transfer")
+        return U_new
 
     def rk_step(self, U, dt: float, variant: str = "colored", precision: str = "f64", ws=None, stream=None):
         if ws is None:

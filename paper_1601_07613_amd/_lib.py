@@ -30,6 +30,8 @@ ARR = {
     "color_off": (12, "int64"), "dev_face_lr": (20, "int32"), "dev_face_code": (21, "uint8"),
     "dev_face_geo": (22, "float64"), "dev_elem_geo": (23, "float64"), "dev_elem_slots": (24, "int32"),
     "elem_level": (30, "int8"), "elem_xyz": (31, "float64"), "elem_vert": (32, "int32"),
+    "adapt_kind": (33, "int8"), "adapt_src": (34, "int32"), "dev_adapt_kind": (25, "int8"),
+    "dev_adapt_src": (26, "int32"),
 }
 
 
@@ -55,7 +57,7 @@ class TableInfo(C.Structure):
         ("elem_type", C.c_int32), ("p", C.c_int32), ("dim", C.c_int32), ("n_p", C.c_int32),
         ("n_qf", C.c_int32), ("n_qv", C.c_int32), ("n_codes", C.c_int32), ("n_orient", C.c_int32),
         ("off_trace", C.c_int64), ("off_proj", C.c_int64), ("off_vb", C.c_int64), ("off_vd", C.c_int64),
-        ("total", C.c_int64),
+        ("off_prolong", C.c_int64), ("total", C.c_int64),
     ]
 
 
@@ -77,6 +79,9 @@ _SIGS = {
     "dgc_color_edges": (C.c_int, [C.c_void_p, C.c_uint64, C.c_int64, C.c_uint32, C.POINTER(ColorStats)]),
     "dgc_set_colors": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32]),
     "dgc_mesh_refine": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_int64)]),
+    "dgc_mesh_coarsen": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_int64)]),
+    "dgc_adapt_transfer": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_void_p]),
     "dgc_mesh_info": (C.c_int, [C.c_void_p, C.POINTER(MeshInfo)]),
     "dgc_mesh_export": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t, C.POINTER(C.c_size_t)]),
     "dgc_mesh_free": (None, [C.c_void_p]),

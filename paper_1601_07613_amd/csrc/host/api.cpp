@@ -73,7 +73,7 @@ void dgc_mesh_free(dgc_mesh *m) { delete m; }
 dgc_status dgc_color_edges(dgc_mesh *h, uint64_t seed, int64_t max_swaps, uint32_t flags, dgc_color_stats *stats) {
     if (!h) return fail(DGC_E_ARG, "dgc_color_edges: null mesh");
     dgc::Mesh &m = h->m;
-    if (m.max_level > 0) return fail(DGC_E_UNSUPPORTED, "refined meshes are colored by dgc_mesh_refine");
+    if (m.has_tree()) return fail(DGC_E_UNSUPPORTED, "refined meshes are colored by dgc_mesh_refine");
     uint32_t alg = flags & 0x0Fu, lay = flags & 0xF0u;
     if (lay == 0) lay = DGC_LAYOUT_PAPER;
     if (alg == 0) alg = DGC_COLOR_PAPER;
@@ -194,6 +194,27 @@ dgc_status dgc_mesh_export(const dgc_mesh *h, int32_t which, void *dst, size_t b
             case DGC_ARR_ELEM_LEVEL: return copy_out(m.elem_level, dst, bytes, needed);
             case DGC_ARR_ELEM_XYZ: return copy_out(m.elem_xyz, dst, bytes, needed);
             case DGC_ARR_ELEM_VERT: return copy_out(m.elem_vert, dst, bytes, needed);
+            case DGC_ARR_ADAPT_KIND:
+            case DGC_ARR_ADAPT_SRC:
+            case DGC_ARR_DEV_ADAPT_KIND:
+            case DGC_ARR_DEV_ADAPT_SRC: {
+                if (m.adapt_kind.size() != (size_t)K)
+                    return fail(DGC_E_ARG, "dgc_mesh_export: mesh was not made by dgc_mesh_refine / dgc_mesh_coarsen");
+                if (which == DGC_ARR_ADAPT_KIND) return copy_out(m.adapt_kind, dst, bytes, needed);
+                if (which == DGC_ARR_ADAPT_SRC) return copy_out(m.adapt_src, dst, bytes, needed);
+                if (which == DGC_ARR_DEV_ADAPT_KIND) {
+                    std::vector<int8_t> v(K);
+                    for (int64_t i = 0; i < K; ++i) v[m.elem_new[i]] = m.adapt_kind[i];
+                    return copy_out(v, dst, bytes, needed);
+                }
+                std::vector<int32_t> v(4 * K, -1);
+                for (int64_t i = 0; i < K; ++i)
+                    for (int a = 0; a < 4; ++a) {
+                        const int32_t s = m.adapt_src[i * 4 + a];
+                        v[a * K + m.elem_new[i]] = s >= 0 ? m.prev_elem_new[s] : -1;
+                    }
+                return copy_out(v, dst, bytes, needed);
+            }
             case DGC_ARR_DEV_FACE_LR: {
                 std::vector<int32_t> v(2 * E);
                 for (int64_t k = 0; k < E; ++k) {

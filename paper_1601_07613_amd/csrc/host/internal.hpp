@@ -57,6 +57,26 @@ struct Mesh {
     std::vector<EdgeNode> nodes;
     std::vector<int32_t> leaf_edge;   // [K][3] node of each local edge
     int64_t n_vert = 0;               // vertex ids in use
+    bool has_tree() const { return !nodes.empty(); }
+
+    // leaf tree: the element each leaf was split from (its "family"), kept so
+    // that four siblings can merge back into it
+    struct Family {
+        int32_t verts[3];
+        double xyz[6];
+        int32_t edges[3];
+        int32_t parent;  // family of the split element itself (-1: a base element)
+        int8_t child;    // the split element's index in that family
+        int8_t level;
+    };
+    std::vector<Family> families;
+    std::vector<int32_t> leaf_family;  // [K], -1 for base elements
+    std::vector<int8_t> leaf_child;    // [K] 0..3 (corner at v0, v1, v2, center)
+
+    // provenance with respect to the mesh this one was adapted from
+    std::vector<int8_t> adapt_kind;     // [K] 0 same leaf, 1 + k child k, 5 parent of four
+    std::vector<int32_t> adapt_src;     // [K][4] original ids in the previous mesh, -1 padded
+    std::vector<int32_t> prev_elem_new; // layout ids of the previous mesh
 };
 
 // mesh_build.cpp

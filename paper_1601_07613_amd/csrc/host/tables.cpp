@@ -175,7 +175,8 @@ dgc_status build_tables(int32_t elem_type, int p, dgc_table_info *info, std::vec
     ti.off_proj = ti.off_trace + (int64_t)ti.n_codes * qf * np;
     ti.off_vb = ti.off_proj + (int64_t)ti.n_codes * qf * np;
     ti.off_vd = ti.off_vb + (int64_t)qv * np;
-    ti.total = ti.off_vd + (int64_t)dim * qv * np;
+    ti.off_prolong = ti.off_vd + (int64_t)dim * qv * np;
+    ti.total = ti.off_prolong + (dim == 2 ? 4 * (int64_t)np * np : 0);
     if (info) *info = ti;
     if (!out) return DGC_OK;
     out->assign(ti.total, 0.0);
@@ -275,6 +276,35 @@ dgc_status build_tables(int32_t elem_type, int p, dgc_table_info *info, std::vec
                     double xi[3] = {0.5 * (1.0 + r), 0.5 * (1.0 + s), 0.5 * (1.0 + t)};
                     put(xi, wa[i] * wb[j] * wc[k] / 64.0);
                 }
+    }
+
+    // prolongation onto the four children of the midpoint split:
+    // P_k[j][l] = 1/2 sum_q w_q phi_j(xi_q) phi_l(child_k(xi_q)), the factor
+    // 1/2 = sqrt(det J_child / det J_parent) of the physical basis; the
+    // product has degree 2p, within the volume rule's exactness 2p+1
+    if (dim == 2) {
+        // child vertices in the parent's reference coordinates, each child's own order
+        const double C[4][3][2] = {{{0, 0}, {0.5, 0}, {0, 0.5}},
+                                   {{0.5, 0}, {1, 0}, {0.5, 0.5}},
+                                   {{0, 0.5}, {0.5, 0.5}, {0, 1}},
+                                   {{0.5, 0.5}, {0, 0.5}, {0.5, 0}}};
+        std::vector<double> phic(np), phip(np);
+        for (int i = 0; i < n; ++i)
+            for (int k = 0; k < n; ++k) {
+                double r = 0.5 * (1.0 + xa[i]) * (1.0 - xb[k]) - 1.0, s = xb[k];
+                double xi[2] = {0.5 * (1.0 + r), 0.5 * (1.0 + s)};
+                const double w = wa[i] * wb[k] / 8.0;
+                dubiner(dim, p, xi, phic.data(), nullptr);
+                for (int c = 0; c < 4; ++c) {
+                    double xp[2];
+                    for (int d = 0; d < 2; ++d)
+                        xp[d] = C[c][0][d] + xi[0] * (C[c][1][d] - C[c][0][d]) + xi[1] * (C[c][2][d] - C[c][0][d]);
+                    dubiner(dim, p, xp, phip.data(), nullptr);
+                    double *Pk = T + ti.off_prolong + (int64_t)c * np * np;
+                    for (int j = 0; j < np; ++j)
+                        for (int l = 0; l < np; ++l) Pk[j * np + l] += 0.5 * w * phic[j] * phip[l];
+                }
+            }
     }
     return DGC_OK;
 }

@@ -38,9 +38,16 @@ __device__ __forceinline__ const float *stage_input<float>(const Entry *, const 
     return w.shadow;
 }
 
+// lanes per face: the mode team (lane = mode) for tetrahedra at p = 1, as the
+// single-mesh default; otherwise the variable team
+template <int DIM, int NP>
+constexpr int batch_team() {
+    return (DIM == 3 && NP == 4) ? 4 : (DIM + 2 <= 4 ? 4 : 8);
+}
+
 template <int DIM, int NP, int Q, class T>
 __global__ __launch_bounds__(256) void batch_surface_kernel(const char *__restrict__ desc, int color, int stage) {
-    constexpr int TEAM = DIM + 2 <= 4 ? 4 : 8;
+    constexpr int TEAM = batch_team<DIM, NP>();
     const Header *h = bh(desc);
     extern __shared__ unsigned char smem_raw[];
     T *s_tr = reinterpret_cast<T *>(smem_raw);
@@ -52,9 +59,14 @@ __global__ __launch_bounds__(256) void batch_surface_kernel(const char *__restri
     const int64_t k = e->color_off[color] + (local * blockDim.x + threadIdx.x) / TEAM;
     if (k >= e->color_off[color + 1]) return;
     const dgc_batch::RkWs w = dgc_batch::rk_ws(e->ws, (size_t)e->n_dof, sizeof(T) == 4);
-    team_face<DIM, NP, Q, kColored, T, true>(k, threadIdx.x % TEAM, e->n_face, e->n_elem, e->face_lr, e->face_code,
-                                             e->face_geo, s_tr, s_pr, h->n_codes, stage_input<T>(e, w, stage),
-                                             static_cast<T *>(w.rhs), nullptr);
+    if constexpr (DIM == 3 && NP == 4)
+        mode_team_face<DIM, NP, Q, kColored, T, true>(k, threadIdx.x % TEAM, e->n_face, e->n_elem, e->face_lr,
+                                                      e->face_code, e->face_geo, s_tr, s_pr, h->n_codes,
+                                                      stage_input<T>(e, w, stage), static_cast<T *>(w.rhs), nullptr);
+    else
+        team_face<DIM, NP, Q, kColored, T, true>(k, threadIdx.x % TEAM, e->n_face, e->n_elem, e->face_lr,
+                                                 e->face_code, e->face_geo, s_tr, s_pr, h->n_codes,
+                                                 stage_input<T>(e, w, stage), static_cast<T *>(w.rhs), nullptr);
 }
 
 template <int DIM, int NP, int QV, class T>

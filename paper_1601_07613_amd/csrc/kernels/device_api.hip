@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <type_traits>
 
 #include <cmath>
 #include <cstring>
@@ -338,6 +339,35 @@ dgc_status dgc_child_colors(const int8_t *parent_colors, int64_t n, int8_t *chil
     return hip_check("child color kernel launch");
 }
 
+dgc_status dgc_adapt_transfer(const dgc_dmesh *dm, const double *U_old, int64_t n_old, double *U_new,
+                              const int8_t *kind, const int32_t *src, void *stream) {
+    dgc_table_info ti;
+    dgc_status s = check_dm(dm, &ti);
+    if (s != DGC_OK) return s;
+    if (dm->elem_type != DGC_TRI) return fail(DGC_E_UNSUPPORTED, "dgc_adapt_transfer: triangles only");
+    if (!U_old || !U_new || !kind || !src || n_old <= 0 || n_old > ((int64_t)1 << 31) - 1)
+        return fail(DGC_E_ARG, "dgc_adapt_transfer: bad argument");
+    if (U_old == U_new) return fail(DGC_E_ARG, "dgc_adapt_transfer: U_old and U_new must be distinct");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const double *P = dm->tables + ti.off_prolong;
+    const int64_t n = dm->n_elem * dm->n_var;
+    auto go = [&](auto np_tag) {
+        constexpr int NP = decltype(np_tag)::value;
+        hipLaunchKernelGGL((dgc_dev::adapt_transfer_kernel<NP>), dim3(grid_for(n)), dim3(kBlock), 0, st, dm->n_elem,
+                           dm->n_var, n_old, kind, src, P, U_old, U_new);
+        return hip_check("adapt transfer kernel launch");
+    };
+    switch (dm->p) {
+        case 0: return go(std::integral_constant<int, 1>{});
+        case 1: return go(std::integral_constant<int, 3>{});
+        case 2: return go(std::integral_constant<int, 6>{});
+        case 3: return go(std::integral_constant<int, 10>{});
+        case 4: return go(std::integral_constant<int, 15>{});
+        case 5: return go(std::integral_constant<int, 21>{});
+        default: return fail(DGC_E_UNSUPPORTED, "dgc_adapt_transfer: no kernel for this order");
+    }
+}
+
 dgc_status dgc_rk_workspace_layout(int64_t n, int32_t precision, size_t off[4], size_t *total) {
     if (n < 0 || !off || !total || (precision != DGC_F64 && precision != DGC_F32))
         return fail(DGC_E_ARG, "dgc_rk_workspace_layout: bad argument");
@@ -361,7 +391,8 @@ dgc_status dgc_batch_describe(int32_t n_mesh, const dgc_dmesh *meshes, double *c
         if (!U[i] || !ws[i]) return fail(DGC_E_ARG, "dgc_batch_describe: null state or workspace");
         if (!std::isfinite(dt[i])) return fail(DGC_E_ARG, "dgc_batch_describe: non-finite dt");
     }
-    const int team = ti.dim + 2 <= 4 ? 4 : 8;
+    // lanes per face of batch_surface_kernel (batch_team<DIM, NP>)
+    const int team = (ti.dim == 3 && ti.n_p == 4) ? 4 : (ti.dim + 2 <= 4 ? 4 : 8);
     const int fpb = kBlock / team;
     int nc = 0;
     for (int32_t i = 0; i < n_mesh; ++i) nc = meshes[i].n_colors > nc ? meshes[i].n_colors : nc;

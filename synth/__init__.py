@@ -13,6 +13,7 @@ from .meshes import (  # noqa: F401
     kuhn_tets,
     element_measure,
     element_centroid,
+    adapt_flags,
     refine_flags,
 )
 from .fields import (  # noqa: F401

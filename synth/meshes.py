@@ -252,3 +252,17 @@ def refine_flags(elem_xyz: np.ndarray, levels: np.ndarray, level: int, center=(0
     c = np.asarray(elem_xyz, dtype=np.float64).mean(axis=1)
     d = np.hypot(c[:, 0] - center[0], c[:, 1] - center[1])
     return (np.asarray(levels) == level) & (d < radius)
+
+
+def adapt_flags(elem_xyz: np.ndarray, levels: np.ndarray, center, r_refine: float, r_coarsen: float,
+                max_level: int, period: float = 1.0):
+    """Criteria of the moving-feature workload on a periodic square: refine
+    leaves below ``max_level`` whose centroid lies within ``r_refine`` of
+    ``center`` (distance to the nearest periodic image), coarsen leaves above
+    level 0 farther than ``r_coarsen``.  Returns ``(refine, coarsen)`` flags."""
+    c = np.asarray(elem_xyz, dtype=np.float64).mean(axis=1)
+    d = c - np.asarray(center, dtype=np.float64)[None, :]
+    d -= period * np.round(d / period)
+    r = np.hypot(d[:, 0], d[:, 1])
+    lev = np.asarray(levels)
+    return (lev < max_level) & (r < r_refine), (lev > 0) & (r > r_coarsen)

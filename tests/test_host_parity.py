@@ -135,7 +135,14 @@ def test_tables_match_oracle_basis(et, dim, p):
     tr = T[info["off_trace"]:info["off_proj"]].reshape(info["n_codes"], qf, npm)
     pr = T[info["off_proj"]:info["off_vb"]].reshape(info["n_codes"], qf, npm)
     vb = T[info["off_vb"]:info["off_vd"]].reshape(qv, npm)
-    vd = T[info["off_vd"]:].reshape(dim, qv, npm)
+    vd = T[info["off_vd"]:info["off_prolong"]].reshape(dim, qv, npm)
+    if dim == 2:
+        from oracle import transfer as otransfer
+
+        Pk = T[info["off_prolong"]:info["total"]].reshape(4, npm, npm)
+        assert np.abs(Pk - otransfer.prolongation(p)).max() < 1e-13
+    else:
+        assert info["off_prolong"] == info["total"]
     if dim == 2:
         x, w = oquad.tri_volume_rule(p + 1)
         s, fw = oquad.gauss_legendre_01(p + 1)

@@ -91,3 +91,77 @@ def test_no_flags_gives_same_mesh():
     assert ncl == 0
     assert np.array_equal(M2.export("face_elem"), M.export("face_elem"))
     assert np.array_equal(M2.export("color"), M.export("color"))
+
+
+def _origin_arrays(origin):
+    kind = np.array([k for k, _ in origin], dtype=np.int64)
+    src = np.full((len(origin), 4), -1, dtype=np.int64)
+    for i, (_, s) in enumerate(origin):
+        src[i, :len(s)] = s
+    return kind, src
+
+
+def _check_origin(st, M, prev_new):
+    kind, src = _origin_arrays(st.origin)
+    assert np.array_equal(M.export("adapt_kind").astype(np.int64), kind)
+    assert np.array_equal(M.export("adapt_src").reshape(-1, 4), src)
+    # device form: rows in layout order, sources as layout ids of the previous mesh
+    new = M.export("elem_new")
+    dk = M.export("dev_adapt_kind").astype(np.int64)
+    ds = M.export("dev_adapt_src").reshape(4, -1)
+    assert np.array_equal(dk[new], kind)
+    want = np.where(src >= 0, prev_new[np.maximum(src, 0)], -1)
+    assert np.array_equal(ds[:, new].T, want)
+
+
+def test_moving_feature_refine_and_coarsen_bit_exact():
+    """Several adapt cycles around a moving center (coarsen, then refine one
+    level), native against the oracle: leaves, vertex ids, face table, colors,
+    layout and the origin of every leaf."""
+    m = synth.periodic_tri(16, jitter=0.0, seed=4)
+    O = build_mesh(m["elem_vert"], m["elem_xyz"])
+    col, _ = color_faces(O, seed=0)
+    st = R.from_base(O, col)
+    M = dgc.Mesh.build(m["elem_vert"], m["elem_xyz"])
+    M.color(seed=0)
+    merged_total = 0
+    for cyc in range(6):
+        center = (0.3 + 0.08 * cyc, 0.35 + 0.05 * cyc)
+        xyz = np.array([lf.xyz for lf in st.leaves])
+        lev = np.array([lf.level for lf in st.leaves])
+        _, coarse = synth.adapt_flags(xyz, lev, center, 0.12, 0.16, max_level=2)
+        prev_new = M.export("elem_new")
+        st, n = R.coarsen(st, coarse)
+        M, n_c = M.coarsen(coarse)
+        assert n_c == n
+        merged_total += n
+        _compare(st, M)
+        _check_origin(st, M, prev_new)
+        assert R.check_balance(st)
+        xyz = np.array([lf.xyz for lf in st.leaves])
+        lev = np.array([lf.level for lf in st.leaves])
+        fine, _ = synth.adapt_flags(xyz, lev, center, 0.12, 0.16, max_level=2)
+        prev_new = M.export("elem_new")
+        st, ncl = R.refine(st, fine)
+        M, ncl_c = M.refine(fine)
+        assert ncl_c == ncl
+        _compare(st, M)
+        _check_origin(st, M, prev_new)
+    assert merged_total > 0 and M.info()["max_level"] == 2
+
+
+def test_coarsen_all_the_way_back_to_the_base_coloring():
+    m = synth.periodic_tri(24, jitter=0.0, seed=4)
+    st, M = _run(m, 3, 0.15, 0)
+    O = build_mesh(m["elem_vert"], m["elem_xyz"])
+    col, _ = color_faces(O, seed=0)
+    base = R.to_mesh(R.from_base(O, col))
+    for _ in range(3):
+        K = M.info()["n_elem"]
+        st, n = R.coarsen(st, np.ones(K, dtype=bool))
+        M, n_c = M.coarsen(np.ones(K, dtype=np.uint8))
+        assert n_c == n > 0
+    _compare(st, M)
+    assert M.info()["max_level"] == 0 and M.info()["n_colors"] == 3
+    assert np.array_equal(M.export("color").astype(np.int64), base[1])
+    assert np.array_equal(M.export("face_elem").reshape(-1, 2), base[0].face_elem)

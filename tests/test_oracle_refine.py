@@ -116,3 +116,56 @@ def test_dg_free_stream_and_conservation_on_refined_mesh(p):
     r = dg.rhs(d, U)
     total = (r[:, :, 0] * np.sqrt(mesh.detJ)[:, None]).sum(axis=0)
     assert np.abs(total).max() < 1e-13 * np.abs(r).max() * mesh.K
+
+
+def test_worked_example_coarsens_back():
+    """Refining the worked example and merging the four children restores the
+    parent triangle with colors (DB, BA, AD) = (2, 1, 3) (1-based)."""
+    st, _ = R.refine(_single((2, 1, 3)), [True])
+    st2, n = R.coarsen(st, [True] * 4)
+    assert n == 1 and len(st2.leaves) == 1 and st2.origin == [(5, [0, 1, 2, 3])]
+    lf = st2.leaves[0]
+    assert lf.verts == [0, 1, 2] and lf.level == 0
+    assert [e.color + 1 for e in lf.edges] == [2, 1, 3]
+    assert all(e.children is None for e in lf.edges)
+
+
+def test_coarsening_restores_the_base_mesh():
+    """Coarsen every family of a three-level refinement, level by level: the
+    face table, orientation codes and colors of the conforming base come back."""
+    m = synth.periodic_tri(24, jitter=0.0, seed=4)
+    M = build_mesh(m["elem_vert"], m["elem_xyz"])
+    col, _ = color_faces(M, seed=0)
+    base = R.to_mesh(R.from_base(M, col))
+    st = _c3_like()
+    for _ in range(3):
+        st, n = R.coarsen(st, [True] * len(st.leaves))
+        assert n > 0 and R.check_balance(st)
+    got = R.to_mesh(st)
+    assert got[0].K == M.K and got[3].max() == 0
+    for a, b in zip(_mesh_arrays_from(got), _mesh_arrays_from(base)):
+        assert np.array_equal(a, b)
+
+
+def _mesh_arrays_from(t):
+    mesh, color, orient, levels = t
+    return mesh.face_elem, mesh.face_local, orient, color, mesh.elem_vert
+
+
+def test_coarsening_keeps_balance_and_valid_six_coloring():
+    """Random coarsening flags: only families whose children are all flagged
+    and unsplit merge; the result stays 2:1 balanced and validly colored."""
+    st = _c3_like(n=16, levels=3, radius=0.2)
+    rng = np.random.default_rng(3)
+    K0 = len(st.leaves)
+    st2, n = R.coarsen(st, rng.random(K0) < 0.8)
+    assert 0 < n and len(st2.leaves) == K0 - 3 * n
+    assert R.check_balance(st2)
+    mesh, color, orient, levels = R.to_mesh(st2)
+    check_coloring(mesh, color, 6)
+    assert abs(mesh.elem_measure.sum() - 1.0) < 1e-13
+    assert all(kind in (0, 5) for kind, _ in st2.origin)
+    # refining the merged parents again gives a balanced mesh
+    flags = [kind == 5 for kind, _ in st2.origin]
+    st3, ncl = R.refine(st2, flags)
+    assert R.check_balance(st3)
