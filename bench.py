@@ -384,6 +384,12 @@ def main(argv=None):
         extra["gather_us"] = timed(lambda: D.surface_rhs(Ug, rhs, "gather", ws=ws), args.steps, args.warmup,
                                    stream)[0] * 1e3
         extra["volume_us"] = timed(lambda: D.volume_rhs(Ug, rhs), args.steps, args.warmup, stream)[0] * 1e3
+        if D.dim == 2:
+            for vf in ("valu", "mfma", "team"):
+                D.set_volume_form(vf)
+                extra["volume_%s_us" % vf] = timed(lambda: D.volume_rhs(Ug, rhs), args.steps, args.warmup,
+                                                   stream)[0] * 1e3
+            D.set_volume_form("default")
         wsr = D.workspace("rk", "colored")
         Ur = Ug.clone()
         extra["rk3_step_us"] = timed(lambda: D.rk_step(Ur, 1e-7, ws=wsr), max(args.steps // 5, 3), 2, stream)[0] * 1e3

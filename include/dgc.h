@@ -282,8 +282,18 @@ typedef struct {
     int32_t block_size;        /* work-items per work-group of the face kernels: 64, 128 or 256 */
     int32_t xcd_remap;         /* 1: work-groups are dealt round-robin to the 8 XCDs, so give
                                   each XCD one contiguous range of faces (shared L2 lines) */
-    int32_t pad_;
+    int32_t vol_form;          /* DGC_VOL_* */
 } dgc_dmesh;
+
+/* Volume-kernel forms: DGC_VOL_VALU evaluates each element in one work-item
+ * with vector FMAs; DGC_VOL_TEAM gives each element a team of lanes (one
+ * per conserved variable, the element record read as one contiguous
+ * stretch) that exchange the point values; DGC_VOL_MFMA (triangles, f64,
+ * p <= 3; other cases fall back to DGC_VOL_VALU) runs the two basis
+ * contractions of four elements at a time on the matrix cores
+ * (v_mfma_f64_16x16x4f64) and the flux between them on the vector units.
+ * DGC_VOL_DEFAULT is the team form. */
+enum { DGC_VOL_DEFAULT = 0, DGC_VOL_VALU = 1, DGC_VOL_MFMA = 2, DGC_VOL_TEAM = 3 };
 
 /* Face-kernel forms: DGC_FORM_TEAM gives each face a team of lanes (one lane
  * per conserved variable) so that loads of one element record are

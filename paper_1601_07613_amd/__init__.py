@@ -174,9 +174,17 @@ class DeviceMesh:
         dm.surf_form = 0
         dm.block_size = 0
         dm.xcd_remap = 0
+        dm.vol_form = 0
         self.dm = dm
 
     FORMS = {"default": 0, "team": 1, "thread": 2, "team_prefetch": 3, "mode_team": 4}
+    VOL_FORMS = {"default": 0, "valu": 1, "mfma": 2, "team": 3}
+
+    def set_volume_form(self, form: str = "default") -> None:
+        """Volume-kernel form: one work-item per element ("valu"), a team of
+        lanes per element ("team", the default), or the two basis
+        contractions on the matrix cores ("mfma": triangles, f64, p <= 3)."""
+        self.dm.vol_form = self.VOL_FORMS[form]
 
     def set_launch(self, form: str = "default", block: int = 0, xcd_remap: bool = False) -> None:
         """Choose the face-kernel form (team of lanes per face, or one work-item

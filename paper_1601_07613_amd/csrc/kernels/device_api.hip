@@ -14,6 +14,8 @@
 #include "layout_dev.hpp"
 #include "surface.hpp"
 #include "volume.hpp"
+#include "volume_mfma.hpp"
+#include "volume_team.hpp"
 
 using dgc::fail;
 
@@ -44,6 +46,8 @@ dgc_status check_dm(const dgc_dmesh *dm, dgc_table_info *ti) {
         return fail(DGC_E_ARG, "dgc_dmesh: null device array");
     if (dm->surf_form < DGC_FORM_DEFAULT || dm->surf_form > DGC_FORM_MODE_TEAM)
         return fail(DGC_E_ARG, "dgc_dmesh: unknown surf_form");
+    if (dm->vol_form < DGC_VOL_DEFAULT || dm->vol_form > DGC_VOL_TEAM)
+        return fail(DGC_E_ARG, "dgc_dmesh: unknown vol_form");
     if (dm->block_size != 0 && dm->block_size != 64 && dm->block_size != 128 && dm->block_size != 256)
         return fail(DGC_E_ARG, "dgc_dmesh: block_size must be 0, 64, 128 or 256");
     return DGC_OK;
@@ -65,6 +69,22 @@ struct Impl {
     using Real = T;
 
     static dgc_status volume(const dgc_dmesh *dm, const dgc_table_info &ti, const T *U, T *rhs, hipStream_t st) {
+        if constexpr (DIM == 2 && std::is_same_v<T, double> && NP <= 16 && QV <= 16) {
+            if (dm->vol_form == DGC_VOL_MFMA) {
+                const int64_t groups = (dm->n_elem + 15) / 16;
+                const unsigned grid = (unsigned)(groups < 4096 ? groups : 4096);
+                hipLaunchKernelGGL((dgc_dev::volume_mfma_kernel<NP, QV>), dim3(grid), dim3(256), 0, st, dm->n_elem,
+                                   dm->elem_geo, dm->tables + ti.off_vb, dm->tables + ti.off_vd, U, rhs);
+                return hip_check("volume kernel launch");
+            }
+        }
+        if (dm->vol_form == DGC_VOL_DEFAULT || dm->vol_form == DGC_VOL_TEAM) {
+            constexpr int TEAM = DIM + 2 <= 4 ? 4 : 8;
+            hipLaunchKernelGGL((dgc_dev::volume_team_kernel<DIM, NP, QV, T>), dim3(grid_for(dm->n_elem * TEAM)),
+                               dim3(kBlock), 0, st, dm->n_elem, dm->elem_geo, dm->tables + ti.off_vb,
+                               dm->tables + ti.off_vd, U, rhs);
+            return hip_check("volume kernel launch");
+        }
         hipLaunchKernelGGL((dgc_dev::volume_kernel<DIM, NP, QV, T>), dim3(grid_for(dm->n_elem)), dim3(kBlock), 0, st,
                            dm->n_elem, dm->elem_geo, dm->tables + ti.off_vb, dm->tables + ti.off_vd, U, rhs);
         return hip_check("volume kernel launch");

@@ -1,0 +1,85 @@
+// Volume term of Eq. (2), team form: TEAM lanes per element (4 for M = 4,
+// 8 for M = 5), lane r < M owning conserved variable r.
+//
+// Lane r reads the N_p modes of its variable (the team reads the element
+// record as one contiguous stretch), forms its variable's value at every
+// volume point, and the team exchanges the values (DPP quad broadcasts, or
+// ds_bpermute for 8-lane teams) so that every lane holds the full state.
+// Every lane evaluates the flux of the full state and keeps its own
+// component; the contravariant flux and the projection onto the modes are
+// then lane-local, and lane r writes its variable's N_p modes of the result.
+// Same arithmetic as volume_elem, in the same order.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "euler_dev.hpp"
+#include "surface.hpp"
+
+namespace dgc_dev {
+
+template <int DIM, int NP, int QV, class T>
+__global__ __launch_bounds__(256) void volume_team_kernel(int64_t n_elem, const double *__restrict__ elem_geo,
+                                                          const double *__restrict__ vb,
+                                                          const double *__restrict__ vd,
+                                                          const T *__restrict__ U, T *__restrict__ rhs) {
+    constexpr int M = DIM + 2;
+    constexpr int REC = M * NP;
+    constexpr int TEAM = M <= 4 ? 4 : 8;
+    const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / TEAM;
+    const int r = threadIdx.x % TEAM;
+    if (k >= n_elem) return;  // whole teams leave together
+    const bool own = r < M;
+    T Ji[DIM * DIM];
+#pragma unroll
+    for (int a = 0; a < DIM * DIM; ++a) Ji[a] = T(elem_geo[a * n_elem + k]);
+    const double sq = elem_geo[DIM * DIM * n_elem + k];
+    const T isq = T(1.0 / sq);
+    T c[NP];
+    const T *u = U + (size_t)k * REC + r * NP;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) c[j] = own ? u[j] : T(0);
+    T acc[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) acc[j] = 0;
+#pragma unroll
+    for (int q = 0; q < QV; ++q) {
+        T t = 0;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) t += T(vb[q * NP + j]) * c[j];
+        T uq[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) uq[m] = team_bcast<TEAM>(t * isq, m);
+        T Fx[M * DIM];
+        phys_flux<DIM, T>(uq, Fx);
+        T Fm[DIM];
+#pragma unroll
+        for (int e = 0; e < DIM; ++e) {
+            T f = Fx[e];
+#pragma unroll
+            for (int m = 1; m < M; ++m) f = r == m ? Fx[m * DIM + e] : f;
+            Fm[e] = f;
+        }
+        T G[DIM];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+            T g = 0;
+#pragma unroll
+            for (int e = 0; e < DIM; ++e) g += Ji[d * DIM + e] * Fm[e];
+            G[d] = g;
+        }
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            T a = 0;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) a += T(vd[(d * QV + q) * NP + j]) * G[d];
+            acc[j] += a;
+        }
+    }
+    if (!own) return;
+    T *o = rhs + (size_t)k * REC + r * NP;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) o[j] = acc[j] * T(sq);
+}
+
+}  // namespace dgc_dev

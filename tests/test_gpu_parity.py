@@ -131,14 +131,40 @@ def test_surface_tets(p, variant, form):
                                          ("periodic", 16, 3), ("periodic", 16, 4), ("periodic", 16, 5),
                                          ("delaunay", 6000, 2), ("tets", 5, 0),
                                          ("tets", 5, 1), ("tets", 5, 2)])
-def test_volume(kind, size, p):
+@pytest.mark.parametrize("form", ["default", "valu"])
+def test_volume(kind, size, p, form):
     import torch
 
     c = Case(kind, size, 4, p)
+    c.D.set_volume_form(form)
     rhs = torch.full_like(c.Ug, 7.0)  # overwritten by the kernel
     c.D.volume_rhs(c.Ug, rhs)
     torch.cuda.synchronize()
     _check(c.to_host(rhs), dg.volume_rhs(c.d, c.U), _volume_abs(c.d, c.U), "volume %s p=%d" % (kind, p))
+
+
+@pytest.mark.parametrize("kind,size,p", [("periodic", 16, 0), ("periodic", 16, 1), ("periodic", 16, 2),
+                                         ("periodic", 16, 3), ("delaunay", 6000, 2), ("delaunay", 6001, 1)])
+def test_volume_forms(kind, size, p):
+    """The MFMA form (four elements per 16 x 16 x 4 f64 product chain), the
+    one-work-item form and the team form against the oracle and each other;
+    ragged element counts exercise the masked rows of the last group."""
+    import torch
+
+    c = Case(kind, size, 14, p)
+    ref = dg.volume_rhs(c.d, c.U)
+    out = {}
+    for form in ("mfma", "valu", "team"):
+        c.D.set_volume_form(form)
+        rhs = torch.full_like(c.Ug, 7.0)
+        c.D.volume_rhs(c.Ug, rhs)
+        torch.cuda.synchronize()
+        out[form] = c.to_host(rhs)
+        _check(out[form], ref, _volume_abs(c.d, c.U), "volume %s %s p=%d" % (form, kind, p))
+    c.D.set_volume_form("default")
+    scale = np.abs(ref).max()
+    assert np.abs(out["mfma"] - out["valu"]).max() <= 1e-13 * max(scale, 1e-300)
+    assert np.abs(out["team"] - out["valu"]).max() <= 1e-13 * max(scale, 1e-300)
 
 
 @pytest.mark.parametrize("layout", ["paper_sfc", "renumber", "none"])
