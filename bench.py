@@ -393,6 +393,10 @@ def main(argv=None):
         wsr = D.workspace("rk", "colored")
         Ur = Ug.clone()
         extra["rk3_step_us"] = timed(lambda: D.rk_step(Ur, 1e-7, ws=wsr), max(args.steps // 5, 3), 2, stream)[0] * 1e3
+        D.set_rk_form("separate")
+        extra["rk3_step_separate_combine_us"] = timed(lambda: D.rk_step(Ur, 1e-7, ws=wsr), max(args.steps // 5, 3), 2,
+                                                      stream)[0] * 1e3
+        D.set_rk_form("default")
         D.set_launch("thread", 256)
         extra["colored_thread_form_us"] = timed(lambda: D.surface_rhs(Ug, rhs, "colored"), args.steps, args.warmup,
                                                 stream)[0] * 1e3

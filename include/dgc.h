@@ -283,7 +283,16 @@ typedef struct {
     int32_t xcd_remap;         /* 1: work-groups are dealt round-robin to the 8 XCDs, so give
                                   each XCD one contiguous range of faces (shared L2 lines) */
     int32_t vol_form;          /* DGC_VOL_* */
+    int32_t rk_form;           /* DGC_RK_* */
+    int32_t pad_;
 } dgc_dmesh;
+
+/* dgc_rk_step forms: DGC_RK_DEFAULT fuses each stage's combination into the
+ * face kernel of the last color when that is exact (f64, colored variant, a
+ * conforming mesh colored with as many colors as an element has faces, so
+ * every element has exactly one face of the last color, and a team face
+ * form); DGC_RK_SEPARATE always runs the combination as its own kernel. */
+enum { DGC_RK_DEFAULT = 0, DGC_RK_SEPARATE = 1 };
 
 /* Volume-kernel forms: DGC_VOL_VALU evaluates each element in one work-item
  * with vector FMAs; DGC_VOL_TEAM gives each element a team of lanes (one

@@ -175,10 +175,18 @@ class DeviceMesh:
         dm.block_size = 0
         dm.xcd_remap = 0
         dm.vol_form = 0
+        dm.rk_form = 0
         self.dm = dm
 
     FORMS = {"default": 0, "team": 1, "thread": 2, "team_prefetch": 3, "mode_team": 4}
     VOL_FORMS = {"default": 0, "valu": 1, "mfma": 2, "team": 3}
+
+    RK_FORMS = {"default": 0, "separate": 1}
+
+    def set_rk_form(self, form: str = "default") -> None:
+        """SSP-RK3 stages with the combination fused into the last color's
+        face kernel where exact ("default"), or as a separate kernel."""
+        self.dm.rk_form = self.RK_FORMS[form]
 
     def set_volume_form(self, form: str = "default") -> None:
         """Volume-kernel form: one work-item per element ("valu"), a team of

@@ -71,6 +71,7 @@ class DMesh(C.Structure):
         ("face_lr", C.c_void_p), ("face_code", C.c_void_p), ("face_geo", C.c_void_p),
         ("elem_geo", C.c_void_p), ("elem_slots", C.c_void_p), ("tables", C.c_void_p),
         ("surf_form", C.c_int32), ("block_size", C.c_int32), ("xcd_remap", C.c_int32), ("vol_form", C.c_int32),
+        ("rk_form", C.c_int32), ("pad_", C.c_int32),
     ]
 
 

@@ -128,6 +128,42 @@ struct Impl {
         return hip_check("surface kernel launch");
     }
 
+    // colored pass whose last color writes the stage combination (f64); *fused
+    // is false (and nothing is launched) when the last color is empty
+    static dgc_status surface_fused(const dgc_dmesh *dm, const dgc_table_info &ti, const T *U, T *rhs,
+                                    const dgc_dev::CombineArgs &cmb, bool *fused, hipStream_t st) {
+        *fused = false;
+        if constexpr (!std::is_same_v<T, double>) {
+            return fail(DGC_E_ARG, "fused stage combination is f64 only");
+        } else {
+            dgc_status s = check_colors(dm);
+            if (s != DGC_OK) return s;
+            const int nc = dm->n_colors;
+            const int64_t f0 = dm->color_off[nc - 1], f1 = dm->color_off[nc];
+            if (f1 <= f0) return DGC_OK;
+            for (int c = 0; c < nc - 1 && s == DGC_OK; ++c)
+                s = faces<dgc_dev::kColored>(dm, ti, dm->color_off[c], dm->color_off[c + 1], U, rhs, nullptr, st);
+            if (s != DGC_OK) return s;
+            const size_t lds = 2 * (size_t)ti.n_codes * Q * NP * sizeof(double);
+            const int block = dm->block_size ? dm->block_size : kBlock;
+            constexpr bool kMT = DIM == 3 && NP == 4;
+            if (kMT && dm->surf_form != DGC_FORM_TEAM_PREFETCH) {
+                hipLaunchKernelGGL((dgc_dev::surface_combine_kernel<DIM, NP, Q, kMT>),
+                                   dim3(grid_for((f1 - f0) * 4, block)), dim3(block), lds, st, f0, f1, dm->n_face,
+                                   dm->n_elem, dm->face_lr, dm->face_code, dm->face_geo, dm->tables + ti.off_trace,
+                                   dm->tables + ti.off_proj, ti.n_codes, U, rhs, cmb);
+            } else {
+                constexpr int TEAM = DIM + 2 <= 4 ? 4 : 8;
+                hipLaunchKernelGGL((dgc_dev::surface_combine_kernel<DIM, NP, Q, false>),
+                                   dim3(grid_for((f1 - f0) * TEAM, block)), dim3(block), lds, st, f0, f1, dm->n_face,
+                                   dm->n_elem, dm->face_lr, dm->face_code, dm->face_geo, dm->tables + ti.off_trace,
+                                   dm->tables + ti.off_proj, ti.n_codes, U, rhs, cmb);
+            }
+            *fused = true;
+            return hip_check("fused surface kernel launch");
+        }
+    }
+
     static dgc_status surface(const dgc_dmesh *dm, const dgc_table_info &ti, const T *U, T *rhs, int variant, void *ws,
                               size_t ws_bytes, hipStream_t st) {
         dgc_status s = DGC_OK;
@@ -277,9 +313,28 @@ dgc_status dgc_rk_step(const dgc_dmesh *dm, double *U, double dt, int32_t varian
         hipLaunchKernelGGL(dgc_dev::to_f32_kernel, dim3(grid_for((int64_t)n)), dim3(kBlock), 0, st, (int64_t)n, U, shadow);
         if ((s = hip_check("f32 shadow launch")) != DGC_OK) return s;
     }
+    // the stage combination rides on the last color's face kernel when every
+    // element has exactly one face of that color (see DGC_RK_DEFAULT)
+    const int faces_per_elem = dm->elem_type == DGC_TRI ? 3 : 4;
+    const bool fuse = !shadow && variant == DGC_SURF_COLORED && dm->rk_form == DGC_RK_DEFAULT &&
+                      dm->n_colors == faces_per_elem && dm->max_slots == faces_per_elem &&
+                      (dm->surf_form == DGC_FORM_DEFAULT || dm->surf_form == DGC_FORM_TEAM_PREFETCH ||
+                       dm->surf_form == DGC_FORM_MODE_TEAM);
+    if (dm->rk_form != DGC_RK_DEFAULT && dm->rk_form != DGC_RK_SEPARATE)
+        return fail(DGC_E_ARG, "dgc_dmesh: unknown rk_form");
     for (int stg = 0; stg < 3; ++stg) {
         const void *Uin = shadow ? static_cast<const void *>(shadow) : static_cast<const void *>(stage_in[stg]);
         if ((s = dgc_volume_rhs(dm, Uin, rhs, precision, stream)) != DGC_OK) return s;
+        if (fuse) {
+            const dgc_dev::CombineArgs cmb{stg == 0 ? nullptr : U, stage_out[stg], a[stg], b[stg], dt};
+            bool fused = false;
+            s = dispatch<double>(dm, 0, 0, [&](auto impl) {
+                return decltype(impl)::surface_fused(dm, ti, stage_in[stg], static_cast<double *>(rhs), cmb, &fused,
+                                                     st);
+            });
+            if (s != DGC_OK) return s;
+            if (fused) continue;
+        }
         if ((s = dgc_surface_rhs(dm, Uin, rhs, variant, precision, sws, sws_bytes, stream)) != DGC_OK) return s;
         if (shadow) {
             hipLaunchKernelGGL(dgc_dev::rk_combine_f32_kernel, dim3(grid_for((int64_t)n)), dim3(kBlock), 0, st,
@@ -414,6 +469,8 @@ dgc_status dgc_batch_describe(int32_t n_mesh, const dgc_dmesh *meshes, double *c
     // lanes per face of batch_surface_kernel (batch_team<DIM, NP>)
     const int team = (ti.dim == 3 && ti.n_p == 4) ? 4 : (ti.dim + 2 <= 4 ? 4 : 8);
     const int fpb = kBlock / team;
+    // lanes per element of batch_volume_kernel (volume_team_size<DIM>)
+    const int vteam = ti.dim + 2 <= 4 ? 4 : 8;
     int nc = 0;
     for (int32_t i = 0; i < n_mesh; ++i) nc = meshes[i].n_colors > nc ? meshes[i].n_colors : nc;
     // work-group counts
@@ -425,7 +482,7 @@ dgc_status dgc_batch_describe(int32_t n_mesh, const dgc_dmesh *meshes, double *c
             const int64_t nf = c < d.n_colors ? d.color_off[c + 1] - d.color_off[c] : 0;
             nb_face[c] += (nf + fpb - 1) / fpb;
         }
-        nb_elem += (d.n_elem + kBlock - 1) / kBlock;
+        nb_elem += (d.n_elem * vteam + kBlock - 1) / kBlock;
         nb_dof += (d.n_elem * d.n_var * d.n_p + kBlock - 1) / kBlock;
     }
     for (int c = 0; c < nc; ++c)
@@ -496,7 +553,7 @@ dgc_status dgc_batch_describe(int32_t n_mesh, const dgc_dmesh *meshes, double *c
             for (int64_t b = 0; b < nb; ++b) map[cur[c] + b] = i;
             cur[c] += nb;
         }
-        const int64_t ne = (d.n_elem + kBlock - 1) / kBlock, nd = (e.n_dof + kBlock - 1) / kBlock;
+        const int64_t ne = (d.n_elem * vteam + kBlock - 1) / kBlock, nd = (e.n_dof + kBlock - 1) / kBlock;
         e.blk_elem = (int32_t)ce;
         e.blk_dof = (int32_t)cd;
         int32_t *me = reinterpret_cast<int32_t *>(out + h.off_map_elem);

@@ -25,7 +25,26 @@
 
 namespace dgc_dev {
 
-enum { kColored = 0, kAtomic = 1, kGather = 2 };
+enum { kColored = 0, kAtomic = 1, kGather = 2, kCombine = 3 };
+
+// Last color of a colored pass with the SSP-RK3 stage combination fused in:
+// on a conforming mesh every element has exactly one face of every color, so
+// when its last-color face is done its right-hand side is complete and the
+// face's lanes write out = a x + b (y + dt r) instead of r (y = the stage
+// input the traces were read from, x = the stage-0 state, or y itself when
+// x is null).  f64 only.
+struct CombineArgs {
+    const double *x;
+    double *out;
+    double a, b, dt;
+};
+
+__device__ __forceinline__ void combine_store(const CombineArgs &cmb, size_t idx, double y, double r) {
+    const double x = cmb.x ? cmb.x[idx] : y;
+    cmb.out[idx] = cmb.a * x + cmb.b * (y + cmb.dt * r);
+}
+template <class T>
+__device__ __forceinline__ void combine_store(const CombineArgs &, size_t, T, T) {}
 
 template <class T>
 __device__ __forceinline__ void atomic_add(T *addr, T v) {
@@ -204,10 +223,11 @@ __device__ __forceinline__ void team_face(
     int64_t k, int r, int64_t n_face, int64_t n_elem,
     const int32_t *__restrict__ face_lr, const uint8_t *__restrict__ face_code,
     const double *__restrict__ face_geo, const T *__restrict__ s_tr, const T *__restrict__ s_pr, int n_codes,
-    const T *__restrict__ U, T *__restrict__ rhs, T *__restrict__ buf) {
+    const T *__restrict__ U, T *__restrict__ rhs, T *__restrict__ buf, const CombineArgs &cmb = CombineArgs{}) {
     constexpr int M = DIM + 2;
     constexpr int REC = M * NP;
     constexpr int TEAM = M <= 4 ? 4 : 8;
+    constexpr bool RMW = MODE == kColored || MODE == kCombine;
     const int32_t L = face_lr[k];
     const int32_t R = face_lr[n_face + k];
     const int cL = face_code[k];
@@ -224,7 +244,7 @@ __device__ __forceinline__ void team_face(
     // optionally issue the right-hand-side reads of a colored update up front,
     // so that they are in flight together with the DOF reads
     T pre_L[NP], pre_R[NP];
-    if (PREFETCH && MODE == kColored && own) {
+    if (PREFETCH && RMW && own) {
         const T *a = rhs + (size_t)L * REC + r * NP;
 #pragma unroll
         for (int j = 0; j < NP; ++j) pre_L[j] = a[j];
@@ -237,31 +257,30 @@ __device__ __forceinline__ void team_face(
 
     // my variable's traces on both sides
     T tL[Q], tR[Q];
+    T cL_[NP], cR_[NP];
     {
-        T c[NP];
         const T *uL = U + (size_t)L * REC + r * NP;
 #pragma unroll
-        for (int j = 0; j < NP; ++j) c[j] = own ? uL[j] : T(0);
+        for (int j = 0; j < NP; ++j) cL_[j] = own ? uL[j] : T(0);
         const T *tl = s_tr + cL * Q * NP;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             T a = 0;
 #pragma unroll
-            for (int j = 0; j < NP; ++j) a += tl[q * NP + j] * c[j];
+            for (int j = 0; j < NP; ++j) a += tl[q * NP + j] * cL_[j];
             tL[q] = a * T(isL);
         }
     }
     if (R >= 0) {
-        T c[NP];
         const T *uR = U + (size_t)R * REC + r * NP;
 #pragma unroll
-        for (int j = 0; j < NP; ++j) c[j] = own ? uR[j] : T(0);
+        for (int j = 0; j < NP; ++j) cR_[j] = own ? uR[j] : T(0);
         const T *tr = s_tr + cR * Q * NP;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             T a = 0;
 #pragma unroll
-            for (int j = 0; j < NP; ++j) a += tr[q * NP + j] * c[j];
+            for (int j = 0; j < NP; ++j) a += tr[q * NP + j] * cR_[j];
             tR[q] = a * T(isR);
         }
     }
@@ -298,6 +317,8 @@ __device__ __forceinline__ void team_face(
             for (int q = 0; q < Q; ++q) a += pl[q * NP + j] * Fm[q];
             a *= sL;
             if (MODE == kColored) dst[j] = (PREFETCH ? pre_L[j] : dst[j]) - a;
+            else if (MODE == kCombine)
+                combine_store(cmb, (size_t)L * REC + r * NP + j, cL_[j], (PREFETCH ? pre_L[j] : dst[j]) - a);
             else if (MODE == kAtomic) atomic_add<T>(dst + j, -a);
             else dst[j] = -a;
         }
@@ -313,6 +334,8 @@ __device__ __forceinline__ void team_face(
             for (int q = 0; q < Q; ++q) a += pr[q * NP + j] * Fm[q];
             a *= sR;
             if (MODE == kColored) dst[j] = (PREFETCH ? pre_R[j] : dst[j]) + a;
+            else if (MODE == kCombine)
+                combine_store(cmb, (size_t)R * REC + r * NP + j, cR_[j], (PREFETCH ? pre_R[j] : dst[j]) + a);
             else if (MODE == kAtomic) atomic_add<T>(dst + j, a);
             else dst[j] = a;
         }
@@ -352,10 +375,11 @@ __device__ __forceinline__ void mode_team_face(
     int64_t k, int j, int64_t n_face, int64_t n_elem,
     const int32_t *__restrict__ face_lr, const uint8_t *__restrict__ face_code,
     const double *__restrict__ face_geo, const T *__restrict__ s_tr, const T *__restrict__ s_pr, int n_codes,
-    const T *__restrict__ U, T *__restrict__ rhs, T *__restrict__ buf) {
+    const T *__restrict__ U, T *__restrict__ rhs, T *__restrict__ buf, const CombineArgs &cmb = CombineArgs{}) {
     static_assert(NP == 4, "mode teams need exactly four modes");
     constexpr int M = DIM + 2;
     constexpr int REC = M * NP;
+    constexpr bool RMW = MODE == kColored || MODE == kCombine;
     const int32_t L = face_lr[k];
     const int32_t R = face_lr[n_face + k];
     const int cL = face_code[k];
@@ -369,7 +393,7 @@ __device__ __forceinline__ void mode_team_face(
     const double isR = face_geo[(DIM + 2) * n_face + k];
 
     T pre_L[M], pre_R[M];
-    if (PREFETCH && MODE == kColored) {
+    if (PREFETCH && RMW) {
 #pragma unroll
         for (int m = 0; m < M; ++m) pre_L[m] = rhs[(size_t)L * REC + m * NP + j];
         if (R >= 0) {
@@ -378,26 +402,25 @@ __device__ __forceinline__ void mode_team_face(
         }
     }
     T uL[Q][M], uR[Q][M];
+    T cL_[M], cR_[M];
     {
-        T c[M];
 #pragma unroll
-        for (int m = 0; m < M; ++m) c[m] = U[(size_t)L * REC + m * NP + j];
+        for (int m = 0; m < M; ++m) cL_[m] = U[(size_t)L * REC + m * NP + j];
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const T t = s_tr[(cL * Q + q) * NP + j];
 #pragma unroll
-            for (int m = 0; m < M; ++m) uL[q][m] = quad_sum(t * c[m]) * T(isL);
+            for (int m = 0; m < M; ++m) uL[q][m] = quad_sum(t * cL_[m]) * T(isL);
         }
     }
     if (R >= 0) {
-        T c[M];
 #pragma unroll
-        for (int m = 0; m < M; ++m) c[m] = U[(size_t)R * REC + m * NP + j];
+        for (int m = 0; m < M; ++m) cR_[m] = U[(size_t)R * REC + m * NP + j];
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const T t = s_tr[(cR * Q + q) * NP + j];
 #pragma unroll
-            for (int m = 0; m < M; ++m) uR[q][m] = quad_sum(t * c[m]) * T(isR);
+            for (int m = 0; m < M; ++m) uR[q][m] = quad_sum(t * cR_[m]) * T(isR);
         }
     } else {
 #pragma unroll
@@ -416,6 +439,8 @@ __device__ __forceinline__ void mode_team_face(
             for (int q = 0; q < Q; ++q) a += s_pr[(cL * Q + q) * NP + j] * F[q][m];
             a *= sL;
             if (MODE == kColored) dst[m * NP + j] = (PREFETCH ? pre_L[m] : dst[m * NP + j]) - a;
+            else if (MODE == kCombine)
+                combine_store(cmb, (size_t)L * REC + m * NP + j, cL_[m], (PREFETCH ? pre_L[m] : dst[m * NP + j]) - a);
             else if (MODE == kAtomic) atomic_add<T>(dst + m * NP + j, -a);
             else dst[m * NP + j] = -a;
         }
@@ -430,6 +455,8 @@ __device__ __forceinline__ void mode_team_face(
             for (int q = 0; q < Q; ++q) a += s_pr[(cR * Q + q) * NP + j] * F[q][m];
             a *= sR;
             if (MODE == kColored) dst[m * NP + j] = (PREFETCH ? pre_R[m] : dst[m * NP + j]) + a;
+            else if (MODE == kCombine)
+                combine_store(cmb, (size_t)R * REC + m * NP + j, cR_[m], (PREFETCH ? pre_R[m] : dst[m * NP + j]) + a);
             else if (MODE == kAtomic) atomic_add<T>(dst + m * NP + j, a);
             else dst[m * NP + j] = a;
         }
@@ -481,6 +508,30 @@ __global__ __launch_bounds__(256) void surface_mode_team_kernel(
     if (k >= f_end) return;  // whole quads leave together
     mode_team_face<DIM, NP, Q, MODE, T, true>(k, threadIdx.x % 4, n_face, n_elem, face_lr, face_code, face_geo,
                                               s_tr, s_pr, n_codes, U, rhs, buf);
+}
+
+// Last color of an SSP-RK3 stage with the stage combination fused in (see
+// CombineArgs): the team form, or the mode team for tetrahedra at p = 1.
+template <int DIM, int NP, int Q, bool MT>
+__global__ __launch_bounds__(256) void surface_combine_kernel(
+    int64_t f_begin, int64_t f_end, int64_t n_face, int64_t n_elem,
+    const int32_t *__restrict__ face_lr, const uint8_t *__restrict__ face_code,
+    const double *__restrict__ face_geo, const double *__restrict__ tab_trace,
+    const double *__restrict__ tab_proj, int n_codes,
+    const double *__restrict__ U, double *__restrict__ rhs, CombineArgs cmb) {
+    constexpr int TEAM = MT ? 4 : (DIM + 2 <= 4 ? 4 : 8);
+    extern __shared__ unsigned char smem_raw[];
+    double *s_tr = reinterpret_cast<double *>(smem_raw);
+    double *s_pr = s_tr + n_codes * Q * NP;
+    stage_tables<double>(s_tr, s_pr, tab_trace, tab_proj, n_codes * Q * NP);
+    const int64_t k = f_begin + ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / TEAM;
+    if (k >= f_end) return;  // whole teams leave together
+    if constexpr (MT)
+        mode_team_face<DIM, NP, Q, kCombine, double, true>(k, threadIdx.x % 4, n_face, n_elem, face_lr, face_code,
+                                                            face_geo, s_tr, s_pr, n_codes, U, rhs, nullptr, cmb);
+    else
+        team_face<DIM, NP, Q, kCombine, double, true>(k, threadIdx.x % TEAM, n_face, n_elem, face_lr, face_code,
+                                                       face_geo, s_tr, s_pr, n_codes, U, rhs, nullptr, cmb);
 }
 
 // Second pass of the buffered variant: rhs[k] += sum of element k's slots.

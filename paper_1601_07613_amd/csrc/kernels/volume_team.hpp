@@ -18,17 +18,20 @@
 
 namespace dgc_dev {
 
+template <int DIM>
+constexpr int volume_team_size() {
+    return DIM + 2 <= 4 ? 4 : 8;
+}
+
+// element k, lane r of its team (all lanes of the team must call)
 template <int DIM, int NP, int QV, class T>
-__global__ __launch_bounds__(256) void volume_team_kernel(int64_t n_elem, const double *__restrict__ elem_geo,
-                                                          const double *__restrict__ vb,
-                                                          const double *__restrict__ vd,
-                                                          const T *__restrict__ U, T *__restrict__ rhs) {
+__device__ __forceinline__ void volume_team_elem(int64_t k, int r, int64_t n_elem,
+                                                 const double *__restrict__ elem_geo, const double *__restrict__ vb,
+                                                 const double *__restrict__ vd, const T *__restrict__ U,
+                                                 T *__restrict__ rhs) {
     constexpr int M = DIM + 2;
     constexpr int REC = M * NP;
-    constexpr int TEAM = M <= 4 ? 4 : 8;
-    const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / TEAM;
-    const int r = threadIdx.x % TEAM;
-    if (k >= n_elem) return;  // whole teams leave together
+    constexpr int TEAM = volume_team_size<DIM>();
     const bool own = r < M;
     T Ji[DIM * DIM];
 #pragma unroll
@@ -80,6 +83,17 @@ __global__ __launch_bounds__(256) void volume_team_kernel(int64_t n_elem, const 
     T *o = rhs + (size_t)k * REC + r * NP;
 #pragma unroll
     for (int j = 0; j < NP; ++j) o[j] = acc[j] * T(sq);
+}
+
+template <int DIM, int NP, int QV, class T>
+__global__ __launch_bounds__(256) void volume_team_kernel(int64_t n_elem, const double *__restrict__ elem_geo,
+                                                          const double *__restrict__ vb,
+                                                          const double *__restrict__ vd,
+                                                          const T *__restrict__ U, T *__restrict__ rhs) {
+    constexpr int TEAM = volume_team_size<DIM>();
+    const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / TEAM;
+    if (k >= n_elem) return;  // whole teams leave together
+    volume_team_elem<DIM, NP, QV, T>(k, threadIdx.x % TEAM, n_elem, elem_geo, vb, vd, U, rhs);
 }
 
 }  // namespace dgc_dev

@@ -270,6 +270,37 @@ def test_rk3_100_steps_vortex():
     assert err <= TOL, err
 
 
+@pytest.mark.parametrize("kind,size,p", [("delaunay", 6000, 2), ("periodic", 16, 1), ("periodic", 16, 3),
+                                         ("tets", 5, 1), ("tets", 4, 2)])
+def test_rk3_fused_combination_equals_separate(kind, size, p):
+    """The stage combination fused into the last color's face kernel gives the
+    separate-kernel step (same formula; only the compiler's contraction of
+    a x + b (y + dt r) may differ) over several steps, walls included."""
+    import torch
+
+    c = Case(kind, size, 21, p)
+    if kind != "tets":
+        # a smooth state: the shock tube has no limiter to survive several steps at p >= 1
+        st = synth.density_wave_states(synth.element_centroid(c.m["elem_xyz"]), vel=(0.5, 0.3))
+        c.Ug = torch.from_numpy(c.D.to_layout(synth.perturbed_dofs(c.O.elem_measure, st, c.d.n_p, eps=0.01,
+                                                                   seed=3))).cuda()
+    U0 = c.Ug.clone()
+    dt = 1e-4
+    out = {}
+    for form in ("default", "separate"):
+        c.D.set_rk_form(form)
+        U = U0.clone()
+        ws = c.D.workspace("rk", "colored")
+        for _ in range(5):
+            c.D.rk_step(U, dt, ws=ws)
+        torch.cuda.synchronize()
+        out[form] = U
+    c.D.set_rk_form("default")
+    scale = out["separate"].abs().max().item()
+    assert (out["default"] - out["separate"]).abs().max().item() <= 1e-14 * scale
+    assert not torch.equal(out["default"], U0)
+
+
 def test_workspace_errors_on_device():
     import torch
 
