@@ -285,8 +285,8 @@ def main(argv=None):
     ap.add_argument("--tet-n", type=int, default=64)
     ap.add_argument("--p", type=int, default=None)
     ap.add_argument("--seed", type=int, default=2)
-    ap.add_argument("--only", choices=["all", "colored"], default="all",
-                    help="'colored' times the colored pass only (for profiling)")
+    ap.add_argument("--only", choices=["all", "colored", "volume"], default="all",
+                    help="'colored' times the colored pass only, 'volume' the volume-term forms only (for profiling)")
     ap.add_argument("--form", choices=["auto", "default", "team", "team_prefetch", "thread"], default="auto",
                     help="face-kernel form; 'auto' runs the launch autotuner before timing")
     ap.add_argument("--block", type=int, default=0)
@@ -360,6 +360,16 @@ def main(argv=None):
     rec = D.n_var * D.n_p
     ab = algorithmic_bytes(E, E - nb, rec, 8, D.dim)
     dof = K * D.n_var * D.n_p
+
+    if args.only == "volume":
+        # each volume-term form, back to back (for counter runs of one kernel)
+        res = {}
+        for vf in ("valu", "team", "mfma"):
+            D.set_volume_form(vf)
+            res[vf + "_us"] = timed(lambda: D.volume_rhs(Ug, rhs), args.steps, args.warmup, stream)[0] * 1e3
+        log("volume forms: %s" % res)
+        print(json.dumps({"volume_forms_us": res, "n_elem": K, "p": args.p}))
+        return 0
 
     # clocks up: run the pass for ~0.5 s before any measurement
     time_call(lambda: D.surface_rhs(Ug, rhs, "colored"), reps=200, warmup=5)
