@@ -1,4 +1,5 @@
-"""Orthonormal modal (Dubiner) basis on the unit triangle and tetrahedron (oracle).
+"""Orthonormal modal bases (oracle): Dubiner on the unit triangle and
+tetrahedron, tensor Legendre on the unit square.
 
 TEST INFRASTRUCTURE ONLY.
 
@@ -180,4 +181,57 @@ def eval_grad(dim: int, p: int, pts) -> np.ndarray:
 REF_VERTS = {
     2: np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]]),
     3: np.array([[0.0, 0.0, 0.0], [1.0, 0.0, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]]),
+    "tri": np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]]),
+    "tet": np.array([[0.0, 0.0, 0.0], [1.0, 0.0, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]]),
+    "quad": np.array([[0.0, 0.0], [1.0, 0.0], [1.0, 1.0], [0.0, 1.0]]),
 }
+
+
+# -- quadrilaterals ---------------------------------------------------------
+# The unit square (0,0), (1,0), (1,1), (0,1) with the tensor-product basis
+# phi_(a,b)(xi, eta) = L_a(xi) L_b(eta), 0 <= a, b <= p, where
+# L_n(x) = sqrt(2n + 1) P_n(2x - 1) is the Legendre polynomial normalised on
+# [0, 1]; N_p = (p + 1)^2, mode index j = b (p + 1) + a.  (The paper names no
+# quadrilateral basis; this orthonormal family makes the mass matrix of an
+# affine quadrilateral the identity, as the Dubiner basis does on simplices.)
+
+def quad_modes(p: int):
+    return [(a, b) for b in range(p + 1) for a in range(p + 1)]
+
+
+def _leg01(n: int, x):
+    return math.sqrt(2 * n + 1) * jacobi(n, 0.0, 0.0, 2.0 * np.asarray(x, dtype=np.float64) - 1.0)
+
+
+def _dleg01(n: int, x):
+    """d/dx of ``_leg01``: (d/dt) P_n(t) = (n + 1)/2 P_{n-1}^(1,1)(t) with t = 2x - 1."""
+    x = np.asarray(x, dtype=np.float64)
+    if n == 0:
+        return np.zeros_like(x)
+    return math.sqrt(2 * n + 1) * (n + 1) * jacobi(n - 1, 1.0, 1.0, 2.0 * x - 1.0)
+
+
+def eval_basis_quad(p: int, pts) -> np.ndarray:
+    """Values ``[n_pts, (p+1)^2]`` of the tensor Legendre basis on the unit square."""
+    pts = np.atleast_2d(np.asarray(pts, dtype=np.float64))
+    return np.stack([_leg01(a, pts[:, 0]) * _leg01(b, pts[:, 1]) for a, b in quad_modes(p)], axis=1)
+
+
+def eval_grad_quad(p: int, pts) -> np.ndarray:
+    """Reference gradients ``[n_pts, 2, (p+1)^2]``."""
+    pts = np.atleast_2d(np.asarray(pts, dtype=np.float64))
+    gx = [_dleg01(a, pts[:, 0]) * _leg01(b, pts[:, 1]) for a, b in quad_modes(p)]
+    gy = [_leg01(a, pts[:, 0]) * _dleg01(b, pts[:, 1]) for a, b in quad_modes(p)]
+    return np.stack([np.stack(gx, axis=1), np.stack(gy, axis=1)], axis=1)
+
+
+def elem_n_modes(kind: str, p: int) -> int:
+    return (p + 1) ** 2 if kind == "quad" else n_modes(2 if kind == "tri" else 3, p)
+
+
+def elem_basis(kind: str, p: int, pts) -> np.ndarray:
+    return eval_basis_quad(p, pts) if kind == "quad" else eval_basis(2 if kind == "tri" else 3, p, pts)
+
+
+def elem_grad(kind: str, p: int, pts) -> np.ndarray:
+    return eval_grad_quad(p, pts) if kind == "quad" else eval_grad(2 if kind == "tri" else 3, p, pts)

@@ -45,10 +45,14 @@ class Discretization:
         self.mesh = mesh
         self.p = p
         self.dim = mesh.dim
-        self.n_p = basis.n_modes(self.dim, p)
+        self.kind = mesh.kind
+        self.n_p = basis.elem_n_modes(self.kind, p)
         self.M = self.dim + 2
         if self.dim == 2:
-            self.vol_pts, self.vol_w = quadrature.tri_volume_rule(p + 1)
+            if self.kind == "quad":
+                self.vol_pts, self.vol_w = quadrature.quad_volume_rule(p + 1)
+            else:
+                self.vol_pts, self.vol_w = quadrature.tri_volume_rule(p + 1)
             s, w = quadrature.gauss_legendre_01(p + 1)
             self.face_bary = np.stack([1.0 - s, s], axis=1)
             self.face_w = w
@@ -58,9 +62,9 @@ class Discretization:
                 self.face_bary, self.face_w = quadrature.tet_face_rule_p1()
             else:
                 self.face_bary, self.face_w = quadrature.tri_face_rule_bary(p + 1)
-        self.vol_B = basis.eval_basis(self.dim, p, self.vol_pts)          # [Qv, Np]
-        self.vol_D = basis.eval_grad(self.dim, p, self.vol_pts)           # [Qv, dim, Np]
-        self.phi0 = float(basis.eval_basis(self.dim, 0, self.vol_pts[:1])[0, 0])
+        self.vol_B = basis.elem_basis(self.kind, p, self.vol_pts)         # [Qv, Np]
+        self.vol_D = basis.elem_grad(self.kind, p, self.vol_pts)          # [Qv, dim, Np]
+        self.phi0 = float(basis.elem_basis(self.kind, 0, self.vol_pts[:1])[0, 0])
         self._face_cache = {}
 
     def face_basis(self, side: int) -> np.ndarray:
@@ -69,7 +73,7 @@ class Discretization:
             ref = self.mesh.face_ref[:, side]                       # [E, nfv, dim]
             pts = np.einsum("qv,evd->eqd", self.face_bary, ref)     # [E, Q, dim]
             E, Q, _ = pts.shape
-            self._face_cache[side] = basis.eval_basis(self.dim, self.p, pts.reshape(E * Q, -1)).reshape(
+            self._face_cache[side] = basis.elem_basis(self.kind, self.p, pts.reshape(E * Q, -1)).reshape(
                 E, Q, self.n_p)
         return self._face_cache[side]
 
@@ -187,19 +191,23 @@ def cfl_dt(d: Discretization, U: np.ndarray, cfl: float) -> float:
 def physical_points(mesh, ref_pts: np.ndarray) -> np.ndarray:
     """``x = x_0 + J xi`` for every element and reference point -> ``[K, nq, dim]``."""
     x0 = mesh.elem_xyz[:, 0, :]
-    J = np.stack([mesh.elem_xyz[:, k + 1, :] - x0 for k in range(mesh.dim)], axis=2)
+    axes = [1, 3] if mesh.kind == "quad" else list(range(1, mesh.dim + 1))
+    J = np.stack([mesh.elem_xyz[:, a, :] - x0 for a in axes], axis=2)
     return x0[:, None, :] + np.einsum("ked,qd->kqe", J, ref_pts)
+
+
+def _fine_rule(kind: str, n: int):
+    if kind == "quad":
+        return quadrature.quad_volume_rule(n)
+    return quadrature.tri_volume_rule(n) if kind == "tri" else quadrature.tet_volume_rule(n)
 
 
 def project(d: Discretization, func, extra: int = 3) -> np.ndarray:
     """L2 projection ``c_ij = sqrt(det J) sum_q w_q u(x_q) phi_j(xi_q)``."""
     mesh = d.mesh
     n = d.p + 1 + extra
-    if d.dim == 2:
-        pts, w = quadrature.tri_volume_rule(n)
-    else:
-        pts, w = quadrature.tet_volume_rule(n)
-    B = basis.eval_basis(d.dim, d.p, pts)
+    pts, w = _fine_rule(d.kind, n)
+    B = basis.elem_basis(d.kind, d.p, pts)
     X = physical_points(mesh, pts)
     u = func(X.reshape(-1, d.dim)).reshape(mesh.K, len(w), -1)
     return np.einsum("q,qj,kqm->kmj", w, B, u) * np.sqrt(mesh.detJ)[:, None, None]
@@ -208,8 +216,8 @@ def project(d: Discretization, func, extra: int = 3) -> np.ndarray:
 def l2_error(d: Discretization, U: np.ndarray, func, var: int = 0, extra: int = 3) -> float:
     mesh = d.mesh
     n = d.p + 1 + extra
-    pts, w = quadrature.tri_volume_rule(n) if d.dim == 2 else quadrature.tet_volume_rule(n)
-    B = basis.eval_basis(d.dim, d.p, pts)
+    pts, w = _fine_rule(d.kind, n)
+    B = basis.elem_basis(d.kind, d.p, pts)
     X = physical_points(mesh, pts)
     ex = func(X.reshape(-1, d.dim)).reshape(mesh.K, len(w), -1)[:, :, var]
     num = np.einsum("qj,kj->kq", B, U[:, var, :]) / np.sqrt(mesh.detJ)[:, None]

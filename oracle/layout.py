@@ -54,7 +54,7 @@ def morton_order(mesh, faces):
     if not faces:
         return faces
     dim = mesh.dim
-    lf = local_faces(dim)
+    lf = local_faces(mesh.kind)
     bits = 31 if dim == 2 else 21
     scale = float(2 ** bits)
     mids = []

@@ -40,10 +40,13 @@ import numpy as np
 from .basis import REF_VERTS
 
 
-def local_faces(dim: int):
-    """Local vertex lists of the faces of the reference element."""
-    if dim == 2:
+def local_faces(kind):
+    """Local vertex lists of the faces of the reference element (``kind`` is
+    "tri", "quad" or "tet"; the dimension 2 / 3 stands for tri / tet)."""
+    if kind in (2, "tri"):
         return [(0, 1), (1, 2), (2, 0)]
+    if kind == "quad":
+        return [(0, 1), (1, 2), (2, 3), (3, 0)]
     return [(1, 2, 3), (0, 2, 3), (0, 1, 3), (0, 1, 2)]
 
 
@@ -69,6 +72,11 @@ class Mesh:
     elem_measure: np.ndarray   # [K]
     face_ref: np.ndarray = None  # [E, 2, nfv, dim]: reference coordinates, seen from L / R,
     #                              of the face's vertices taken in L's order
+    kind: str = ""                 # "tri", "quad" or "tet" (default from dim)
+
+    def __post_init__(self):
+        if not self.kind:
+            self.kind = "tri" if self.dim == 2 else "tet"
 
     @property
     def n_boundary(self) -> int:
@@ -79,7 +87,7 @@ class Mesh:
         barycentric weights ``bary[q, :]`` on the face's vertices (L's order)."""
         e = self.face_elem[f, side]
         verts = list(self.elem_vert[e])
-        ref = REF_VERTS[self.dim]
+        ref = REF_VERTS[self.kind]
         loc = [verts.index(v) for v in self.face_vert[f]]
         return bary @ ref[loc]
 
@@ -89,18 +97,28 @@ def build_mesh(elem_vert, elem_xyz) -> Mesh:
     xyz = np.asarray(elem_xyz, dtype=np.float64)
     K, nv = ev.shape
     dim = xyz.shape[2]
-    if (dim, nv) not in ((2, 3), (3, 4)):
-        raise MeshError("only triangles and tetrahedra are supported")
-    lf = local_faces(dim)
+    kinds = {(2, 3): "tri", (2, 4): "quad", (3, 4): "tet"}
+    if (dim, nv) not in kinds:
+        raise MeshError("only triangles, quadrilaterals and tetrahedra are supported")
+    kind = kinds[(dim, nv)]
+    lf = local_faces(kind)
     F = len(lf)
 
-    # Jacobians: columns are the edge vectors from local vertex 0
-    J = np.stack([xyz[:, d + 1, :] - xyz[:, 0, :] for d in range(dim)], axis=2)  # J[k, e, d] = dx_e/dxi_d
+    # Jacobians: columns are the edge vectors from local vertex 0 (to vertices
+    # 1 and 2 of a simplex, to vertices 1 and 3 of a quadrilateral)
+    axes = [1, 3] if kind == "quad" else list(range(1, dim + 1))
+    J = np.stack([xyz[:, a, :] - xyz[:, 0, :] for a in axes], axis=2)  # J[k, e, d] = dx_e/dxi_d
+    if kind == "quad":
+        # the affine map of the unit square: a parallelogram
+        gap = np.abs(xyz[:, 2] - xyz[:, 1] - xyz[:, 3] + xyz[:, 0]).max(axis=1)
+        size = np.abs(J).max(axis=(1, 2))
+        if (gap > 1e-12 * size).any():
+            raise MeshError("quadrilateral %d is not a parallelogram" % int(np.argmax(gap / size)))
     detJ = np.linalg.det(J)
     if (detJ <= 0).any():
         raise MeshError("element %d has non-positive measure" % int(np.argmin(detJ)))
     Jinv = np.linalg.inv(J)  # Jinv[k, d, e] = dxi_d/dx_e
-    elem_measure = detJ / (2.0 if dim == 2 else 6.0)
+    elem_measure = detJ * {"tri": 0.5, "quad": 1.0, "tet": 1.0 / 6.0}[kind]
 
     key_to_face = {}
     face_elem = []
@@ -147,7 +165,7 @@ def build_mesh(elem_vert, elem_xyz) -> Mesh:
         measure = 0.5 * ar
     # reference coordinates of the face vertices (L's order) on each side:
     # the position of each vertex id inside the side's element
-    ref = REF_VERTS[dim]
+    ref = REF_VERTS[kind]
     face_ref = np.zeros((E, 2, dim, dim))
     for side in (0, 1):
         e = face_elem[:, side]
@@ -158,4 +176,4 @@ def build_mesh(elem_vert, elem_xyz) -> Mesh:
     return Mesh(dim=dim, K=K, E=E, elem_vert=ev, elem_xyz=xyz, face_elem=face_elem,
                 face_local=face_local, face_vert=face_vert, elem_face=elem_face,
                 normal=normal, measure=measure, detJ=detJ, Jinv=Jinv, elem_measure=elem_measure,
-                face_ref=face_ref)
+                face_ref=face_ref, kind=kind)

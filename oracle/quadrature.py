@@ -9,6 +9,8 @@ rules are the readings chosen for this project:
   each, exact for total degree ``2 n - 1``;
 * tetrahedron volume: collapsed product Gauss-Legendre x Gauss-Jacobi (1, 0)
   x Gauss-Jacobi (2, 0), ``n`` points each;
+* unit square (quadrilaterals): tensor Gauss-Legendre with ``n`` points per
+  direction (weights sum to 1); quadrilateral edges use the edge rule;
 * tetrahedron faces at ``p <= 1``: the symmetric three-point rule with
   barycentric points ``(2/3, 1/6, 1/6)`` and permutations, weight 1/3 each
   (exact for degree 2; weights sum to 1);
@@ -95,3 +97,13 @@ def tri_face_rule_bary(n: int):
     pts, w = tri_volume_rule(n)
     bary = np.stack([1.0 - pts[:, 0] - pts[:, 1], pts[:, 0], pts[:, 1]], axis=1)
     return bary, 2.0 * w
+
+
+def quad_volume_rule(n: int):
+    """Tensor Gauss-Legendre rule on the unit square: points ``[n*n, 2]`` with
+    the first coordinate running fastest, weights summing to 1 (exact for
+    degree ``2 n - 1`` in each variable)."""
+    x, w = gauss_legendre_01(n)
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    WX, WY = np.meshgrid(w, w, indexing="xy")
+    return np.stack([X.ravel(), Y.ravel()], axis=1), (WX * WY).ravel()

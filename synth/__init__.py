@@ -14,6 +14,7 @@ from .meshes import (  # noqa: F401
     element_measure,
     element_centroid,
     adapt_flags,
+    quad_grid,
     refine_flags,
 )
 from .fields import (  # noqa: F401

@@ -66,6 +66,50 @@ def periodic_tri(n: int, jitter: float = 0.1, seed: int = 1, length: float = 1.0
     return {"elem_vert": ev, "elem_xyz": xyz, "n_vert": n * n, "h": h, "periodic": True}
 
 
+def quad_grid(n: int, jitter: float = 0.1, seed: int = 1, length: float = 1.0, periodic: bool = True):
+    """``n x n`` parallelogram cells, counter-clockwise ``(i,j), (i+1,j), (i+1,j+1), (i,j+1)``.
+
+    Vertex ``(i, j)`` sits at ``(i h + a_i + t_j, j h + b_j + s_i)``: column
+    offsets ``a_i``, row offsets ``b_j`` and shears ``s_i``, ``t_j`` drawn from
+    ``U(-jitter h, jitter h)``.  A position that is a sum of a per-column and a
+    per-row vector makes every cell a parallelogram (an affine image of the
+    unit square) while cells differ in size and shape.  ``periodic``: the
+    offsets repeat with period ``n`` and vertex ids wrap (a torus; even ``n``
+    admits a 4-edge-coloring: horizontal edges by row parity, vertical ones by
+    column parity); otherwise the unit square with walls, no shears and fixed
+    boundary lines.  Element ``i + n j`` is cell ``(i, j)``.
+    """
+    if n < 2:
+        raise ValueError("quad_grid needs n >= 2")
+    h = length / n
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(-jitter * h, jitter * h, size=n + 1)
+    b = rng.uniform(-jitter * h, jitter * h, size=n + 1)
+    s = rng.uniform(-jitter * h, jitter * h, size=n + 1)
+    t = rng.uniform(-jitter * h, jitter * h, size=n + 1)
+    if periodic:
+        a[n], b[n], s[n], t[n] = a[0], b[0], s[0], t[0]
+    else:
+        a[0] = a[n] = b[0] = b[n] = 0.0
+        s[:] = 0.0
+        t[:] = 0.0
+    ii, jj = np.meshgrid(np.arange(n), np.arange(n), indexing="xy")
+    ii = ii.ravel()
+    jj = jj.ravel()
+    nv_side = n if periodic else n + 1
+
+    def vid(i, j):
+        return (i % nv_side) + nv_side * (j % nv_side) if periodic else i + nv_side * j
+
+    def pos(i, j):
+        return np.stack([i * h + a[i] + t[j], j * h + b[j] + s[i]], axis=-1)
+
+    corners = [(ii, jj), (ii + 1, jj), (ii + 1, jj + 1), (ii, jj + 1)]
+    ev = np.stack([vid(i, j) for i, j in corners], axis=1).astype(np.int32)
+    xyz = np.stack([pos(i, j) for i, j in corners], axis=1)
+    return {"elem_vert": ev, "elem_xyz": xyz, "n_vert": nv_side * nv_side, "h": h, "periodic": periodic}
+
+
 def _poisson_disc(radius: float, seed: int, max_fail: int = 12):
     """Poisson-disc points in the unit square, with boundary points every ``radius``.
 

@@ -117,13 +117,15 @@ def test_convergence_isentropic_vortex_p1():
     assert rates[-1] >= 1.8, (rates, errs)
 
 
-@pytest.mark.parametrize("kind,p", [("tri", 1), ("tri", 3), ("tet", 1), ("tet", 2)])
+@pytest.mark.parametrize("kind,p", [("tri", 1), ("tri", 3), ("quad", 1), ("quad", 3), ("tet", 1), ("tet", 2)])
 def test_face_points_coincide_from_both_sides(kind, p):
     # every face quadrature point, mapped through the left and through the right
     # element's affine map, lands on the same physical point (up to a whole
     # period on the torus): a wrong vertex order on either side fails this
     if kind == "tri":
         m = synth.periodic_tri(5, seed=4)
+    elif kind == "quad":
+        m = synth.quad_grid(5, seed=4)
     else:
         m = synth.kuhn_tets(4, seed=4)
     M = build_mesh(m["elem_vert"], m["elem_xyz"])
@@ -134,7 +136,8 @@ def test_face_points_coincide_from_both_sides(kind, p):
     for side in (0, 1):
         e = M.face_elem[inter, side]
         ref = np.einsum("qv,fvd->fqd", d.face_bary, M.face_ref[inter, side])
-        J = np.stack([xyz[e, k + 1] - xyz[e, 0] for k in range(M.dim)], axis=2)   # columns = edge vectors
+        axes = [1, 3] if M.kind == "quad" else list(range(1, M.dim + 1))
+        J = np.stack([xyz[e, a] - xyz[e, 0] for a in axes], axis=2)   # columns = edge vectors
         phys.append(xyz[e, 0][:, None, :] + np.einsum("fde,fqe->fqd", J, ref))
     diff = phys[0] - phys[1]
     assert np.abs(diff - np.round(diff)).max() < 1e-13
