@@ -58,7 +58,7 @@ typedef enum {
     DGC_E_ALLOC = -9             /* host allocation failed */
 } dgc_status;
 
-enum { DGC_TRI = 0, DGC_TET = 2 };
+enum { DGC_TRI = 0, DGC_QUAD = 1, DGC_TET = 2 };
 
 /* dgc_color_edges flags: one coloring algorithm | one layout */
 #define DGC_COLOR_PAPER      0x01u /* modified greedy + conflict resolution (Section 3.1) */

@@ -16,7 +16,8 @@ import numpy as np
 from . import _lib
 from ._lib import (  # noqa: F401
     DGC_COLOR_GREEDY_STD, DGC_COLOR_PAPER, DGC_F32, DGC_F64, DGC_LAYOUT_NONE, DGC_LAYOUT_PAPER,
-    DGC_LAYOUT_PAPER_SFC, DGC_LAYOUT_RENUMBER, DGC_SURF_ATOMIC, DGC_SURF_COLORED, DGC_SURF_GATHER, DGC_TET, DGC_TRI, DgcError,
+    DGC_LAYOUT_PAPER_SFC, DGC_LAYOUT_RENUMBER, DGC_QUAD, DGC_SURF_ATOMIC, DGC_SURF_COLORED, DGC_SURF_GATHER, DGC_TET,
+    DGC_TRI, DgcError,
 )
 
 _L = _lib.load()
@@ -45,7 +46,7 @@ class Mesh:
     def build(cls, elem_vert, elem_xyz) -> "Mesh":
         ev = np.ascontiguousarray(elem_vert, dtype=np.int32)
         xyz = np.ascontiguousarray(elem_xyz, dtype=np.float64)
-        et = DGC_TRI if ev.shape[1] == 3 else DGC_TET
+        et = DGC_TRI if ev.shape[1] == 3 else (DGC_QUAD if xyz.shape[2] == 2 else DGC_TET)
         h = C.c_void_p()
         _lib.check(_L.dgc_mesh_build(et, ev.shape[0], _ptr(ev), _ptr(xyz), C.byref(h)), "dgc_mesh_build")
         return cls(h)

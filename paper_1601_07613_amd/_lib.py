@@ -8,7 +8,7 @@ from pathlib import Path
 
 LIB_PATH = Path(__file__).resolve().parent / "libdgc.so"
 
-DGC_TRI, DGC_TET = 0, 2
+DGC_TRI, DGC_QUAD, DGC_TET = 0, 1, 2
 DGC_COLOR_PAPER, DGC_COLOR_GREEDY_STD = 0x01, 0x02
 DGC_LAYOUT_PAPER, DGC_LAYOUT_RENUMBER, DGC_LAYOUT_NONE, DGC_LAYOUT_PAPER_SFC = 0x10, 0x20, 0x40, 0x80
 DGC_MAX_COLORS = 8

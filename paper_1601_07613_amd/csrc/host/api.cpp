@@ -33,15 +33,16 @@ const char *dgc_version(void) { return "dgc 0.1 (gfx950)"; }
 dgc_status dgc_mesh_build(int32_t elem_type, int64_t n_elem, const int32_t *elem_vert, const double *elem_xyz,
                           dgc_mesh **out) {
     if (!out || !elem_vert || !elem_xyz || n_elem <= 0) return fail(DGC_E_ARG, "dgc_mesh_build: bad argument");
-    if (elem_type != DGC_TRI && elem_type != DGC_TET) return fail(DGC_E_ARG, "dgc_mesh_build: unknown element type");
+    if (elem_type != DGC_TRI && elem_type != DGC_QUAD && elem_type != DGC_TET)
+        return fail(DGC_E_ARG, "dgc_mesh_build: unknown element type");
     if (n_elem > (int64_t)1 << 30) return fail(DGC_E_ARG, "dgc_mesh_build: too many elements");
     *out = nullptr;
     try {
         dgc_mesh *h = new dgc_mesh();
         dgc::Mesh &m = h->m;
         m.elem_type = elem_type;
-        m.dim = elem_type == DGC_TRI ? 2 : 3;
-        m.nv = m.dim + 1;
+        m.dim = elem_type == DGC_TET ? 3 : 2;
+        m.nv = elem_type == DGC_TRI ? 3 : 4;
         m.F = m.nv;
         m.n_orient = m.dim == 2 ? 4 : 6;
         m.K = n_elem;

@@ -1,4 +1,5 @@
-// Face table and geometry of a conforming simplex mesh.
+// Face table and geometry of a conforming mesh of triangles, parallelograms
+// (affine quadrilaterals) or tetrahedra.
 //
 // The paper keeps the connectivity face-wise: each face points to its left
 // and right element (Section 5, Table 5a).  Faces are matched here by
@@ -18,6 +19,7 @@ namespace {
 
 // local vertex lists of the faces of the reference element
 const int kTriFace[3][2] = {{0, 1}, {1, 2}, {2, 0}};
+const int kQuadFace[4][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 0}};
 const int kTetFace[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
 
 struct FaceRec {
@@ -31,7 +33,8 @@ int perm3_index(int p0, int p1, int p2) { return p0 * 2 + (p1 > p2 ? 1 : 0); }
 }  // namespace
 
 int face_vertex(const Mesh &m, int local_face, int k) {
-    return m.dim == 2 ? kTriFace[local_face][k] : kTetFace[local_face][k];
+    if (m.dim == 3) return kTetFace[local_face][k];
+    return m.nv == 4 ? kQuadFace[local_face][k] : kTriFace[local_face][k];
 }
 
 dgc_status elem_geometry(Mesh &m) {
@@ -43,8 +46,18 @@ dgc_status elem_geometry(Mesh &m) {
     for (int64_t i = 0; i < K; ++i) {
         const double *x = &m.elem_xyz[i * nv * dim];
         if (dim == 2) {
-            double a = x[2] - x[0], b = x[4] - x[0];  // J[0][0], J[0][1]
-            double c = x[3] - x[1], d = x[5] - x[1];  // J[1][0], J[1][1]
+            // columns: vertex 1 - vertex 0 and (triangle) vertex 2 - vertex 0 or
+            // (quadrilateral) vertex 3 - vertex 0
+            const int v2 = nv == 4 ? 3 : 2;
+            double a = x[2] - x[0], b = x[2 * v2] - x[0];      // J[0][0], J[0][1]
+            double c = x[3] - x[1], d = x[2 * v2 + 1] - x[1];  // J[1][0], J[1][1]
+            if (nv == 4) {
+                // an affine image of the unit square: x2 = x1 + x3 - x0
+                const double gx = x[4] - x[2] - x[6] + x[0], gy = x[5] - x[3] - x[7] + x[1];
+                const double size = std::max(std::max(std::fabs(a), std::fabs(b)), std::max(std::fabs(c), std::fabs(d)));
+                if (std::fabs(gx) > 1e-12 * size || std::fabs(gy) > 1e-12 * size)
+                    return fail(DGC_E_MESH, "quadrilateral " + std::to_string(i) + " is not a parallelogram");
+            }
             double det = a * d - b * c;
             if (!(det > 0.0)) return fail(DGC_E_MESH, "element " + std::to_string(i) + " has non-positive area");
             m.detJ[i] = det;
@@ -89,8 +102,8 @@ dgc_status face_geometry(Mesh &m) {
         const int fL = m.face_fL[f];
         const double *x = &m.elem_xyz[L * nv * dim];
         if (dim == 2) {
-            const double *a = x + 2 * kTriFace[fL][0];
-            const double *b = x + 2 * kTriFace[fL][1];
+            const double *a = x + 2 * face_vertex(m, fL, 0);
+            const double *b = x + 2 * face_vertex(m, fL, 1);
             double tx = b[0] - a[0], ty = b[1] - a[1];
             double len = std::hypot(tx, ty);
             m.measure[f] = len;
@@ -198,7 +211,7 @@ dgc_status build_faces(Mesh &m) {
     m.edge_start.assign(E, -1);
     if (dim == 2)
         for (int64_t f = 0; f < E; ++f)
-            m.edge_start[f] = m.elem_vert[(int64_t)m.face_L[f] * nv + kTriFace[m.face_fL[f]][0]];
+            m.edge_start[f] = m.elem_vert[(int64_t)m.face_L[f] * nv + face_vertex(m, m.face_fL[f], 0)];
     m.n_colors = 0;
     m.color.assign(E, -1);
     m.laid_out = false;

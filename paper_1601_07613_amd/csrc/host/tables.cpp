@@ -146,7 +146,31 @@ void dubiner(int dim, int p, const double *xi, double *phi, double *grad /* [dim
     }
 }
 
+// tensor Legendre basis of the unit square: phi_(a,b) = L_a(x) L_b(y) with
+// L_n(x) = sqrt(2) Phat_n(2x - 1) (Phat_n normalised on [-1, 1]), mode
+// j = b (p + 1) + a; gradients by the product rule
+void legendre_tensor(int p, const double *xi, double *phi, double *grad /* [2][Np] or null */) {
+    const int n = p + 1, np = n * n;
+    std::vector<double> lx(n), dlx(n), ly(n), dly(n);
+    for (int a = 0; a < n; ++a) {
+        pnorm(a, 0.0, 0.0, 2.0 * xi[0] - 1.0, &lx[a], &dlx[a]);
+        pnorm(a, 0.0, 0.0, 2.0 * xi[1] - 1.0, &ly[a], &dly[a]);
+    }
+    const double r2 = std::sqrt(2.0);
+    for (int b = 0; b < n; ++b)
+        for (int a = 0; a < n; ++a) {
+            const int m = b * n + a;
+            phi[m] = 2.0 * lx[a] * ly[b];
+            if (grad) {
+                grad[0 * np + m] = r2 * 2.0 * dlx[a] * r2 * ly[b];
+                grad[1 * np + m] = r2 * lx[a] * r2 * 2.0 * dly[b];
+            }
+        }
+}
+
 const double kRefTri[3][2] = {{0, 0}, {1, 0}, {0, 1}};
+const double kRefQuad[4][2] = {{0, 0}, {1, 0}, {1, 1}, {0, 1}};
+const int kQuadEdge[4][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 0}};
 const double kRefTet[4][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
 const int kTriEdge[3][2] = {{0, 1}, {1, 2}, {2, 0}};
 const int kTetFace[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
@@ -155,20 +179,22 @@ const int kPerm3[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1},
 }  // namespace
 
 dgc_status build_tables(int32_t elem_type, int p, dgc_table_info *info, std::vector<double> *out) {
-    if (elem_type != DGC_TRI && elem_type != DGC_TET) return fail(DGC_E_ARG, "unknown element type");
-    const int dim = elem_type == DGC_TRI ? 2 : 3;
-    if (p < 0 || (dim == 2 && p > 5) || (dim == 3 && p > 2))
+    if (elem_type != DGC_TRI && elem_type != DGC_QUAD && elem_type != DGC_TET)
+        return fail(DGC_E_ARG, "unknown element type");
+    const bool quad = elem_type == DGC_QUAD;
+    const int dim = elem_type == DGC_TET ? 3 : 2;
+    if (p < 0 || (elem_type == DGC_TRI && p > 5) || (quad && p > 3) || (dim == 3 && p > 2))
         return fail(DGC_E_UNSUPPORTED, "order p=" + std::to_string(p) + " is not supported for this element");
     dgc_table_info ti{};
     ti.elem_type = elem_type;
     ti.p = p;
     ti.dim = dim;
-    ti.n_p = nmodes(dim, p);
+    ti.n_p = quad ? (p + 1) * (p + 1) : nmodes(dim, p);
     const int n = p + 1;
     ti.n_qv = dim == 2 ? n * n : n * n * n;
     ti.n_qf = dim == 2 ? p + 1 : (p <= 1 ? 3 : n * n);
     ti.n_orient = dim == 2 ? 4 : 6;
-    const int nfaces = dim == 2 ? 3 : 4;
+    const int nfaces = dim == 2 && !quad ? 3 : 4;
     ti.n_codes = nfaces * ti.n_orient;
     const int np = ti.n_p, qf = ti.n_qf, qv = ti.n_qv;
     ti.off_trace = 0;
@@ -176,7 +202,7 @@ dgc_status build_tables(int32_t elem_type, int p, dgc_table_info *info, std::vec
     ti.off_vb = ti.off_proj + (int64_t)ti.n_codes * qf * np;
     ti.off_vd = ti.off_vb + (int64_t)qv * np;
     ti.off_prolong = ti.off_vd + (int64_t)dim * qv * np;
-    ti.total = ti.off_prolong + (dim == 2 ? 4 * (int64_t)np * np : 0);
+    ti.total = ti.off_prolong + (elem_type == DGC_TRI ? 4 * (int64_t)np * np : 0);
     if (info) *info = ti;
     if (!out) return DGC_OK;
     out->assign(ti.total, 0.0);
@@ -213,6 +239,12 @@ dgc_status build_tables(int32_t elem_type, int p, dgc_table_info *info, std::vec
             }
     }
     std::vector<double> phi(np), grad(dim * np);
+    auto basis = [&](const double *xi, double *ph, double *gr) {
+        if (quad)
+            legendre_tensor(p, xi, ph, gr);
+        else
+            dubiner(dim, p, xi, ph, gr);
+    };
     for (int f = 0; f < nfaces; ++f) {
         for (int o = 0; o < ti.n_orient; ++o) {
             const int code = f * ti.n_orient + o;
@@ -226,7 +258,8 @@ dgc_status build_tables(int32_t elem_type, int p, dgc_table_info *info, std::vec
                         case 2: t = 0.5 - 0.5 * fs[q]; break;
                         default: t = 1.0 - 0.5 * fs[q]; break;
                     }
-                    const double *A = kRefTri[kTriEdge[f][0]], *B = kRefTri[kTriEdge[f][1]];
+                    const double *A = quad ? kRefQuad[kQuadEdge[f][0]] : kRefTri[kTriEdge[f][0]];
+                    const double *B = quad ? kRefQuad[kQuadEdge[f][1]] : kRefTri[kTriEdge[f][1]];
                     xi[0] = A[0] + t * (B[0] - A[0]);
                     xi[1] = A[1] + t * (B[1] - A[1]);
                 } else {
@@ -236,7 +269,7 @@ dgc_status build_tables(int32_t elem_type, int p, dgc_table_info *info, std::vec
                         for (int e = 0; e < 3; ++e) xi[e] += fb[q * 3 + u] * V[e];
                     }
                 }
-                dubiner(dim, p, xi, phi.data(), nullptr);
+                basis(xi, phi.data(), nullptr);
                 for (int j = 0; j < np; ++j) {
                     T[ti.off_trace + ((int64_t)code * qf + q) * np + j] = phi[j];
                     T[ti.off_proj + ((int64_t)code * qf + q) * np + j] = fw[q] * phi[j];
@@ -252,14 +285,21 @@ dgc_status build_tables(int32_t elem_type, int p, dgc_table_info *info, std::vec
     if (dim == 3) gauss_jacobi(n, 2.0, 0.0, xc, wc);
     int q = 0;
     auto put = [&](const double *xi, double w) {
-        dubiner(dim, p, xi, phi.data(), grad.data());
+        basis(xi, phi.data(), grad.data());
         for (int j = 0; j < np; ++j) {
             T[ti.off_vb + (int64_t)q * np + j] = phi[j];
             for (int d = 0; d < dim; ++d) T[ti.off_vd + ((int64_t)d * qv + q) * np + j] = w * grad[d * np + j];
         }
         ++q;
     };
-    if (dim == 2) {
+    if (quad) {
+        // tensor Gauss-Legendre, first coordinate fastest
+        for (int iy = 0; iy < n; ++iy)
+            for (int ix = 0; ix < n; ++ix) {
+                double xi[2] = {0.5 * (1.0 + xa[ix]), 0.5 * (1.0 + xa[iy])};
+                put(xi, wa[ix] * wa[iy] / 4.0);
+            }
+    } else if (dim == 2) {
         for (int i = 0; i < n; ++i)
             for (int k = 0; k < n; ++k) {
                 double r = 0.5 * (1.0 + xa[i]) * (1.0 - xb[k]) - 1.0, s = xb[k];
@@ -282,7 +322,7 @@ dgc_status build_tables(int32_t elem_type, int p, dgc_table_info *info, std::vec
     // P_k[j][l] = 1/2 sum_q w_q phi_j(xi_q) phi_l(child_k(xi_q)), the factor
     // 1/2 = sqrt(det J_child / det J_parent) of the physical basis; the
     // product has degree 2p, within the volume rule's exactness 2p+1
-    if (dim == 2) {
+    if (elem_type == DGC_TRI) {
         // child vertices in the parent's reference coordinates, each child's own order
         const double C[4][3][2] = {{{0, 0}, {0.5, 0}, {0, 0.5}},
                                    {{0.5, 0}, {1, 0}, {0.5, 0.5}},

@@ -206,6 +206,14 @@ dgc_status dispatch(const dgc_dmesh *dm, int elem_type, int p, F &&f) {
             case 5: return f(Impl<2, 21, 6, 36, T>{});
             default: break;
         }
+    } else if (elem_type == DGC_QUAD) {
+        switch (p) {
+            case 0: return f(Impl<2, 1, 1, 1, T>{});
+            case 1: return f(Impl<2, 4, 2, 4, T>{});
+            case 2: return f(Impl<2, 9, 3, 9, T>{});
+            case 3: return f(Impl<2, 16, 4, 16, T>{});
+            default: break;
+        }
     } else if (elem_type == DGC_TET) {
         switch (p) {
             case 0: return f(Impl<3, 1, 3, 1, T>{});

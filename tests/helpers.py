@@ -13,6 +13,10 @@ def make_input(kind: str, size: int, seed: int):
         return synth.poisson_delaunay(size, seed=seed)
     if kind == "tets":
         return synth.kuhn_tets(size, seed=seed)
+    if kind == "quads":
+        return synth.quad_grid(size, seed=seed)
+    if kind == "quadbox":
+        return synth.quad_grid(size, seed=seed, periodic=False)
     raise ValueError(kind)
 
 

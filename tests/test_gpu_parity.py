@@ -39,6 +39,8 @@ def _eps(kind, p):
     (orthonormal modes grow towards the vertices with the order)."""
     if kind == "tets":
         return 0.02 if p <= 1 else 0.005
+    if kind in ("quads", "quadbox"):
+        return 0.02 if p <= 2 else 0.005
     return 0.02 if p <= 3 else 0.004
 
 
@@ -114,6 +116,20 @@ def test_surface_delaunay_walls_ragged(variant, form, block, xcd):
     _check(got, dg.surface_rhs(c.d, c.U), dg.surface_abs(c.d, c.U), "surface delaunay " + variant)
 
 
+@pytest.mark.parametrize("kind,size", [("quads", 12), ("quadbox", 11)])
+@pytest.mark.parametrize("form", ["default", "team", "thread"])
+@pytest.mark.parametrize("p", [0, 1, 2, 3])
+@pytest.mark.parametrize("variant", ["colored", "atomic", "gather"])
+def test_surface_quads(p, variant, form, kind, size):
+    """Parallelogram meshes (periodic, and walled with a ragged face count),
+    four colors, tensor Legendre basis."""
+    c = Case(kind, size, 1, p)
+    c.D.set_launch(form)
+    assert c.stats["n_colors"] == 4
+    got = c.to_host(c.surface(variant))
+    _check(got, dg.surface_rhs(c.d, c.U), dg.surface_abs(c.d, c.U), "surface %s %s p=%d" % (kind, variant, p))
+
+
 @pytest.mark.parametrize("form", ["default", "team", "thread", "mode_team"])
 @pytest.mark.parametrize("p", [0, 1, 2])
 @pytest.mark.parametrize("variant", ["colored", "atomic", "gather"])
@@ -130,7 +146,8 @@ def test_surface_tets(p, variant, form):
 @pytest.mark.parametrize("kind,size,p", [("periodic", 16, 0), ("periodic", 16, 1), ("periodic", 16, 2),
                                          ("periodic", 16, 3), ("periodic", 16, 4), ("periodic", 16, 5),
                                          ("delaunay", 6000, 2), ("tets", 5, 0),
-                                         ("tets", 5, 1), ("tets", 5, 2)])
+                                         ("tets", 5, 1), ("tets", 5, 2), ("quads", 12, 1), ("quads", 12, 3),
+                                         ("quadbox", 11, 2)])
 @pytest.mark.parametrize("form", ["default", "valu"])
 def test_volume(kind, size, p, form):
     import torch
@@ -144,7 +161,8 @@ def test_volume(kind, size, p, form):
 
 
 @pytest.mark.parametrize("kind,size,p", [("periodic", 16, 0), ("periodic", 16, 1), ("periodic", 16, 2),
-                                         ("periodic", 16, 3), ("delaunay", 6000, 2), ("delaunay", 6001, 1)])
+                                         ("periodic", 16, 3), ("delaunay", 6000, 2), ("delaunay", 6001, 1),
+                                         ("quads", 12, 2), ("quadbox", 11, 3)])
 def test_volume_forms(kind, size, p):
     """The MFMA form (four elements per 16 x 16 x 4 f64 product chain), the
     one-work-item form and the team form against the oracle and each other;
@@ -271,7 +289,7 @@ def test_rk3_100_steps_vortex():
 
 
 @pytest.mark.parametrize("kind,size,p", [("delaunay", 6000, 2), ("periodic", 16, 1), ("periodic", 16, 3),
-                                         ("tets", 5, 1), ("tets", 4, 2)])
+                                         ("tets", 5, 1), ("tets", 4, 2), ("quads", 12, 2), ("quadbox", 11, 1)])
 def test_rk3_fused_combination_equals_separate(kind, size, p):
     """The stage combination fused into the last color's face kernel gives the
     separate-kernel step (same formula; only the compiler's contraction of
@@ -299,6 +317,25 @@ def test_rk3_fused_combination_equals_separate(kind, size, p):
     scale = out["separate"].abs().max().item()
     assert (out["default"] - out["separate"]).abs().max().item() <= 1e-14 * scale
     assert not torch.equal(out["default"], U0)
+
+
+def test_rk3_quads_vortex_20_steps():
+    """Isentropic vortex on a 12 x 12 periodic parallelogram mesh, p = 2:
+    20 SSP-RK3 steps (fused stage combination) against the oracle."""
+    import torch
+
+    c = Case("quads", 12, 8, 2)
+    U0 = dg.project(c.d, lambda X: synth.isentropic_vortex(X, 0.0, beta=4.0, radius=0.1))
+    dt = dg.cfl_dt(c.d, U0, 0.1)
+    Ug = torch.from_numpy(c.D.to_layout(U0)).cuda()
+    ws = c.D.workspace("rk", "colored")
+    U = U0.copy()
+    for _ in range(20):
+        c.D.rk_step(Ug, dt, ws=ws)
+        U = dg.rk3_step(c.d, U, dt)
+    torch.cuda.synchronize()
+    got = c.to_host(Ug)
+    assert np.abs(got - U).max() / np.abs(U).max() <= TOL
 
 
 def test_workspace_errors_on_device():
@@ -350,7 +387,7 @@ TOL32 = 2e-6
 
 
 @pytest.mark.parametrize("kind,size,p", [("periodic", 16, 2), ("periodic", 16, 5), ("delaunay", 6000, 2),
-                                         ("tets", 5, 1), ("tets", 5, 2)])
+                                         ("tets", 5, 1), ("tets", 5, 2), ("quads", 12, 2)])
 @pytest.mark.parametrize("variant", ["colored", "atomic", "gather"])
 def test_surface_and_volume_f32(kind, size, p, variant):
     """f32 storage and arithmetic (geometry stored in f64) against the f64

@@ -22,7 +22,8 @@ from paper_1601_07613_amd import _lib  # noqa: E402
 GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_tables.json")))
 HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "dgc.h")
 
-CASES = [("periodic", 16, 1), ("periodic", 37, 4), ("delaunay", 8000, 2), ("tets", 5, 3)]
+CASES = [("periodic", 16, 1), ("periodic", 37, 4), ("delaunay", 8000, 2), ("tets", 5, 3), ("quads", 20, 2),
+         ("quadbox", 23, 5)]
 
 
 def test_every_declared_symbol_is_exported():
@@ -118,6 +119,21 @@ def test_invalid_coloring_rejected_and_cap():
     assert M.info()["n_colors"] == 3
 
 
+def test_quad_must_be_a_parallelogram():
+    m = make_input("quads", 4, 1)
+    xyz = m["elem_xyz"].copy()
+    xyz[5, 2] += 0.01
+    with pytest.raises(dgc.DgcError) as e:
+        dgc.Mesh.build(m["elem_vert"], xyz)
+    assert e.value.name == "DGC_E_MESH"
+    M = dgc.Mesh.build(m["elem_vert"], m["elem_xyz"])
+    assert M.info()["elem_type"] == dgc.DGC_QUAD and M.info()["n_face_per_elem"] == 4
+    with pytest.raises(dgc.DgcError) as e:
+        M.color(seed=0)
+        M.refine(np.ones(M.info()["n_elem"], dtype=np.uint8))
+    assert e.value.name == "DGC_E_UNSUPPORTED"
+
+
 def test_mesh_errors():
     m = make_input("periodic", 4, 1)
     xyz = m["elem_xyz"].copy()
@@ -128,7 +144,7 @@ def test_mesh_errors():
 
 
 @pytest.mark.parametrize("et,dim,p", [(0, 2, 0), (0, 2, 1), (0, 2, 2), (0, 2, 3), (0, 2, 4), (0, 2, 5), (2, 3, 0),
-                                      (2, 3, 1), (2, 3, 2)])
+                                      (2, 3, 1), (2, 3, 2), (1, 2, 0), (1, 2, 1), (1, 2, 2), (1, 2, 3)])
 def test_tables_match_oracle_basis(et, dim, p):
     info, T = dgc.tables(et, p)
     npm, qf, qv = info["n_p"], info["n_qf"], info["n_qv"]
@@ -136,7 +152,7 @@ def test_tables_match_oracle_basis(et, dim, p):
     pr = T[info["off_proj"]:info["off_vb"]].reshape(info["n_codes"], qf, npm)
     vb = T[info["off_vb"]:info["off_vd"]].reshape(qv, npm)
     vd = T[info["off_vd"]:info["off_prolong"]].reshape(dim, qv, npm)
-    if dim == 2:
+    if et == 0:
         from oracle import transfer as otransfer
 
         Pk = T[info["off_prolong"]:info["total"]].reshape(4, npm, npm)
@@ -144,15 +160,17 @@ def test_tables_match_oracle_basis(et, dim, p):
     else:
         assert info["off_prolong"] == info["total"]
     if dim == 2:
-        x, w = oquad.tri_volume_rule(p + 1)
+        quad = et == 1
+        kind = "quad" if quad else "tri"
+        x, w = oquad.quad_volume_rule(p + 1) if quad else oquad.tri_volume_rule(p + 1)
         s, fw = oquad.gauss_legendre_01(p + 1)
-        edges = [(0, 1), (1, 2), (2, 0)]
-        V = obasis.REF_VERTS[2]
+        edges = [(0, 1), (1, 2), (2, 3), (3, 0)] if quad else [(0, 1), (1, 2), (2, 0)]
+        V = obasis.REF_VERTS[kind]
         maps = [s, 1 - s, 0.5 - 0.5 * s, 1 - 0.5 * s]
         for f, (a, b) in enumerate(edges):
             for o, t in enumerate(maps):
                 pts = V[a][None, :] + t[:, None] * (V[b] - V[a])[None, :]
-                ref = obasis.eval_basis(2, p, pts)
+                ref = obasis.elem_basis(kind, p, pts)
                 assert np.abs(tr[f * 4 + o] - ref).max() < 1e-13
                 assert np.abs(pr[f * 4 + o] - fw[:, None] * ref).max() < 1e-13
     else:
@@ -169,8 +187,9 @@ def test_tables_match_oracle_basis(et, dim, p):
                 ref = obasis.eval_basis(3, p, pts)
                 assert np.abs(tr[f * 6 + o] - ref).max() < 1e-13
                 assert np.abs(pr[f * 6 + o] - fw[:, None] * ref).max() < 1e-13
-    assert np.abs(vb - obasis.eval_basis(dim, p, x)).max() < 1e-13
-    G = obasis.eval_grad(dim, p, x)
+    kind = {0: "tri", 1: "quad", 2: "tet"}[et]
+    assert np.abs(vb - obasis.elem_basis(kind, p, x)).max() < 1e-13
+    G = obasis.elem_grad(kind, p, x)
     for d in range(dim):
         assert np.abs(vd[d] - w[:, None] * G[:, d, :]).max() < 1e-12
 
