@@ -169,6 +169,26 @@ def extra_workloads(dgc, synth, torch, steps, warmup, log):
     log("c2: %s" % out["c2_kuhn64_tets_p1"])
     del DT, T, Ua, Ub, wa, wb
 
+    # quadrilaterals: 1024 x 1024 periodic parallelograms, p = 2 (N_p = 9), four colors
+    g = synth.quad_grid(1024, jitter=0.1, seed=6)
+    Qm = dgc.Mesh.build(g["elem_vert"], g["elem_xyz"])
+    qs = Qm.color(seed=0)
+    DQ = dgc.DeviceMesh(Qm, 2)
+    info = DQ.info
+    rq = surf_stats(DQ, info["n_elem"], info["n_face"], info["n_boundary"], 8, "f64")
+    rq32 = surf_stats(DQ, info["n_elem"], info["n_face"], info["n_boundary"], 4, "f32")
+    Uq = torch.zeros((DQ.K, 4, DQ.n_p), dtype=torch.float64, device="cuda")
+    Uq[:, 0, 0] = 1.0
+    Uq[:, 3, 0] = 2.5
+    wq = DQ.workspace("rk", "colored")
+    out["quads_1024sq_p2"] = {
+        "n_elem": info["n_elem"], "n_face": info["n_face"], "n_colors": info["n_colors"],
+        "color_ms": qs["color_ms"], "conflicts_after_greedy": qs["conflicts_after_greedy"], "f64": rq, "f32": rq32,
+        "rk3_step_us": time_call(lambda: DQ.rk_step(Uq, 1e-7, ws=wq), reps=5, warmup=1) * 1e3,
+    }
+    log("quads: %s" % out["quads_1024sq_p2"])
+    del DQ, Qm, Uq, wq
+
     # c3: 128 x 128 x 2 periodic base refined to level 3 within r < 0.15, p = 2
     m = synth.periodic_tri(128, jitter=0.0, seed=4)
     A = dgc.Mesh.build(m["elem_vert"], m["elem_xyz"])
