@@ -99,7 +99,8 @@ def color_faces(mesh, seed: int = 0, max_swaps: int | None = None):
     F = mesh.elem_face.shape[1]
     E = mesh.E
     colors = list(range(F))
-    elem_face = mesh.elem_face.tolist()
+    # rows of elements with fewer faces (triangles of a mixed mesh) are -1 padded
+    elem_face = [[g for g in row if g >= 0] for row in mesh.elem_face.tolist()]
     L = mesh.face_elem[:, 0].tolist()
     R = mesh.face_elem[:, 1].tolist()
     color = [-1] * E
@@ -188,7 +189,7 @@ def greedy_standard(mesh):
     """Standard greedy coloring: each face in id order takes the smallest color
     absent from both of its elements (Section 1 of the paper)."""
     E = mesh.E
-    elem_face = mesh.elem_face.tolist()
+    elem_face = [[g for g in row if g >= 0] for row in mesh.elem_face.tolist()]
     L = mesh.face_elem[:, 0].tolist()
     R = mesh.face_elem[:, 1].tolist()
     color = [-1] * E

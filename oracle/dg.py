@@ -39,33 +39,51 @@ from . import basis, euler, quadrature
 
 
 class Discretization:
-    """Quadrature, basis values and per-face reference points for one mesh and order."""
+    """Quadrature, basis values and per-face reference points for one mesh and order.
+
+    A mixed triangle / quadrilateral mesh stores every element's DOFs in
+    ``N_p = (p + 1)^2`` slots (the quadrilateral count); a triangle uses the
+    first ``(p + 1)(p + 2)/2`` and its other slots stay zero: its tables are
+    zero beyond its own modes."""
 
     def __init__(self, mesh, p: int):
         self.mesh = mesh
         self.p = p
         self.dim = mesh.dim
         self.kind = mesh.kind
-        self.n_p = basis.elem_n_modes(self.kind, p)
+        self.kinds = ["tri", "quad"] if self.kind == "mixed" else [self.kind]
+        self.elem_kind = (mesh.elem_kind if self.kind == "mixed" else np.zeros(mesh.K, dtype=np.int64))
+        self.n_p = max(basis.elem_n_modes(k, p) for k in self.kinds)
         self.M = self.dim + 2
         if self.dim == 2:
-            if self.kind == "quad":
-                self.vol_pts, self.vol_w = quadrature.quad_volume_rule(p + 1)
-            else:
-                self.vol_pts, self.vol_w = quadrature.tri_volume_rule(p + 1)
             s, w = quadrature.gauss_legendre_01(p + 1)
             self.face_bary = np.stack([1.0 - s, s], axis=1)
             self.face_w = w
+        elif p <= 1:
+            self.face_bary, self.face_w = quadrature.tet_face_rule_p1()
         else:
-            self.vol_pts, self.vol_w = quadrature.tet_volume_rule(p + 1)
-            if p <= 1:
-                self.face_bary, self.face_w = quadrature.tet_face_rule_p1()
-            else:
-                self.face_bary, self.face_w = quadrature.tri_face_rule_bary(p + 1)
-        self.vol_B = basis.elem_basis(self.kind, p, self.vol_pts)         # [Qv, Np]
-        self.vol_D = basis.elem_grad(self.kind, p, self.vol_pts)          # [Qv, dim, Np]
-        self.phi0 = float(basis.elem_basis(self.kind, 0, self.vol_pts[:1])[0, 0])
+            self.face_bary, self.face_w = quadrature.tri_face_rule_bary(p + 1)
+        # volume rule and tables of every element kind (padded to n_p modes)
+        self.vol = []
+        for k in self.kinds:
+            pts, w = _fine_rule(k, p + 1)
+            B = self._pad(basis.elem_basis(k, p, pts))
+            D = self._pad(basis.elem_grad(k, p, pts))
+            self.vol.append((pts, w, B, D))
+        self.phi_0 = np.array([float(basis.elem_basis(k, 0, self.vol[i][0][:1])[0, 0])
+                               for i, k in enumerate(self.kinds)])
+        if len(self.kinds) == 1:
+            self.vol_pts, self.vol_w, self.vol_B, self.vol_D = self.vol[0]   # [Qv, dim], [Qv], [Qv, Np], [Qv, dim, Np]
+            self.phi0 = float(self.phi_0[0])
         self._face_cache = {}
+
+    def _pad(self, a: np.ndarray) -> np.ndarray:
+        """Zero-pad the mode axis (last) to ``n_p``."""
+        if a.shape[-1] == self.n_p:
+            return a
+        out = np.zeros(a.shape[:-1] + (self.n_p,))
+        out[..., :a.shape[-1]] = a
+        return out
 
     def face_basis(self, side: int) -> np.ndarray:
         """``[E, Q, Np]`` basis values at the face quadrature points seen from ``side``."""
@@ -73,8 +91,15 @@ class Discretization:
             ref = self.mesh.face_ref[:, side]                       # [E, nfv, dim]
             pts = np.einsum("qv,evd->eqd", self.face_bary, ref)     # [E, Q, dim]
             E, Q, _ = pts.shape
-            self._face_cache[side] = basis.elem_basis(self.kind, self.p, pts.reshape(E * Q, -1)).reshape(
-                E, Q, self.n_p)
+            e = self.mesh.face_elem[:, side]
+            ek = self.elem_kind[np.where(e >= 0, e, 0)]
+            out = np.zeros((E, Q, self.n_p))
+            for i, k in enumerate(self.kinds):
+                sel = ek == i
+                if sel.any():
+                    out[sel] = self._pad(basis.elem_basis(k, self.p, pts[sel].reshape(-1, self.dim))).reshape(
+                        -1, Q, self.n_p)
+            self._face_cache[side] = out
         return self._face_cache[side]
 
 
@@ -85,12 +110,15 @@ def traces(B, C, detJ):
 
 def volume_rhs(d: Discretization, U: np.ndarray) -> np.ndarray:
     mesh = d.mesh
-    sq = np.sqrt(mesh.detJ)
-    Uq = np.einsum("qj,kmj->kqm", d.vol_B, U) / sq[:, None, None]       # [K, Qv, M]
-    Fq = euler.physical_flux(Uq)                                        # [K, Qv, M, dim(e)]
-    G = np.einsum("kde,kqme->kqmd", mesh.Jinv, Fq)                      # contravariant
-    rhs = np.einsum("q,qdj,kqmd->kmj", d.vol_w, d.vol_D, G)
-    return rhs * sq[:, None, None]
+    rhs = np.zeros_like(U)
+    for i, (pts, w, B, D) in enumerate(d.vol):
+        idx = np.nonzero(d.elem_kind == i)[0]
+        sq = np.sqrt(mesh.detJ[idx])
+        Uq = np.einsum("qj,kmj->kqm", B, U[idx]) / sq[:, None, None]       # [k, Qv, M]
+        Fq = euler.physical_flux(Uq)                                        # [k, Qv, M, dim(e)]
+        G = np.einsum("kde,kqme->kqmd", mesh.Jinv[idx], Fq)                 # contravariant
+        rhs[idx] = np.einsum("q,qdj,kqmd->kmj", w, D, G) * sq[:, None, None]
+    return rhs
 
 
 def surface_rhs(d: Discretization, U: np.ndarray, elems=None) -> np.ndarray:
@@ -169,7 +197,7 @@ def rk3_step(d: Discretization, U: np.ndarray, dt: float) -> np.ndarray:
 
 def mean_states(d: Discretization, U: np.ndarray) -> np.ndarray:
     """Element means ``c_0 phi_0 / sqrt(det J)``."""
-    return U[:, :, 0] * d.phi0 / np.sqrt(d.mesh.detJ)[:, None]
+    return U[:, :, 0] * d.phi_0[d.elem_kind][:, None] / np.sqrt(d.mesh.detJ)[:, None]
 
 
 def inradius(mesh) -> np.ndarray:
@@ -188,11 +216,17 @@ def cfl_dt(d: Discretization, U: np.ndarray, cfl: float) -> float:
     return float(cfl * (2.0 * inradius(d.mesh)).min() / smax)
 
 
-def physical_points(mesh, ref_pts: np.ndarray) -> np.ndarray:
-    """``x = x_0 + J xi`` for every element and reference point -> ``[K, nq, dim]``."""
-    x0 = mesh.elem_xyz[:, 0, :]
-    axes = [1, 3] if mesh.kind == "quad" else list(range(1, mesh.dim + 1))
-    J = np.stack([mesh.elem_xyz[:, a, :] - x0 for a in axes], axis=2)
+def physical_points(mesh, ref_pts: np.ndarray, elems=None) -> np.ndarray:
+    """``x = x_0 + J xi`` for every (or the given) element and reference point -> ``[k, nq, dim]``."""
+    idx = np.arange(mesh.K) if elems is None else np.asarray(elems)
+    xyz = mesh.elem_xyz[idx]
+    x0 = xyz[:, 0, :]
+    if mesh.dim == 3:
+        J = np.stack([xyz[:, a, :] - x0 for a in (1, 2, 3)], axis=2)
+    else:
+        quad = np.full(len(idx), mesh.kind == "quad") if mesh.elem_kind is None else mesh.elem_kind[idx] == 1
+        second = np.where(quad, 3, 2)
+        J = np.stack([xyz[:, 1, :] - x0, xyz[np.arange(len(idx)), second, :] - x0], axis=2)
     return x0[:, None, :] + np.einsum("ked,qd->kqe", J, ref_pts)
 
 
@@ -206,19 +240,27 @@ def project(d: Discretization, func, extra: int = 3) -> np.ndarray:
     """L2 projection ``c_ij = sqrt(det J) sum_q w_q u(x_q) phi_j(xi_q)``."""
     mesh = d.mesh
     n = d.p + 1 + extra
-    pts, w = _fine_rule(d.kind, n)
-    B = basis.elem_basis(d.kind, d.p, pts)
-    X = physical_points(mesh, pts)
-    u = func(X.reshape(-1, d.dim)).reshape(mesh.K, len(w), -1)
-    return np.einsum("q,qj,kqm->kmj", w, B, u) * np.sqrt(mesh.detJ)[:, None, None]
+    out = np.zeros((mesh.K, d.M, d.n_p))
+    for i, k in enumerate(d.kinds):
+        idx = np.nonzero(d.elem_kind == i)[0]
+        pts, w = _fine_rule(k, n)
+        B = d._pad(basis.elem_basis(k, d.p, pts))
+        X = physical_points(mesh, pts, idx)
+        u = func(X.reshape(-1, d.dim)).reshape(len(idx), len(w), -1)
+        out[idx] = np.einsum("q,qj,kqm->kmj", w, B, u) * np.sqrt(mesh.detJ[idx])[:, None, None]
+    return out
 
 
 def l2_error(d: Discretization, U: np.ndarray, func, var: int = 0, extra: int = 3) -> float:
     mesh = d.mesh
     n = d.p + 1 + extra
-    pts, w = _fine_rule(d.kind, n)
-    B = basis.elem_basis(d.kind, d.p, pts)
-    X = physical_points(mesh, pts)
-    ex = func(X.reshape(-1, d.dim)).reshape(mesh.K, len(w), -1)[:, :, var]
-    num = np.einsum("qj,kj->kq", B, U[:, var, :]) / np.sqrt(mesh.detJ)[:, None]
-    return float(np.sqrt((np.einsum("q,kq->k", w, (num - ex) ** 2) * mesh.detJ).sum()))
+    tot = 0.0
+    for i, k in enumerate(d.kinds):
+        idx = np.nonzero(d.elem_kind == i)[0]
+        pts, w = _fine_rule(k, n)
+        B = d._pad(basis.elem_basis(k, d.p, pts))
+        X = physical_points(mesh, pts, idx)
+        ex = func(X.reshape(-1, d.dim)).reshape(len(idx), len(w), -1)[:, :, var]
+        num = np.einsum("qj,kj->kq", B, U[idx, var, :]) / np.sqrt(mesh.detJ[idx])[:, None]
+        tot += (np.einsum("q,kq->k", w, (num - ex) ** 2) * mesh.detJ[idx]).sum()
+    return float(np.sqrt(tot))

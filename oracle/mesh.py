@@ -72,7 +72,8 @@ class Mesh:
     elem_measure: np.ndarray   # [K]
     face_ref: np.ndarray = None  # [E, 2, nfv, dim]: reference coordinates, seen from L / R,
     #                              of the face's vertices taken in L's order
-    kind: str = ""                 # "tri", "quad" or "tet" (default from dim)
+    kind: str = ""                 # "tri", "quad", "tet" or "mixed" (default from dim)
+    elem_kind: np.ndarray = None   # [K] 0 triangle, 1 quadrilateral (mixed meshes only)
 
     def __post_init__(self):
         if not self.kind:
@@ -101,24 +102,37 @@ def build_mesh(elem_vert, elem_xyz) -> Mesh:
     if (dim, nv) not in kinds:
         raise MeshError("only triangles, quadrilaterals and tetrahedra are supported")
     kind = kinds[(dim, nv)]
-    lf = local_faces(kind)
-    F = len(lf)
+    # a quadrilateral table whose fourth vertex is -1 lists a triangle: mixed mesh
+    ek = None
+    if kind == "quad" and (ev[:, 3] < 0).any():
+        kind = "mixed"
+        ek = (ev[:, 3] >= 0).astype(np.int64)
+    is_quad = np.full(K, kind == "quad") if ek is None else ek == 1
+
+    def faces_of(i):
+        return local_faces("quad" if is_quad[i] else ("tri" if dim == 2 else "tet"))
+
+    F = 4 if dim == 3 or kind in ("quad", "mixed") else 3
 
     # Jacobians: columns are the edge vectors from local vertex 0 (to vertices
     # 1 and 2 of a simplex, to vertices 1 and 3 of a quadrilateral)
-    axes = [1, 3] if kind == "quad" else list(range(1, dim + 1))
-    J = np.stack([xyz[:, a, :] - xyz[:, 0, :] for a in axes], axis=2)  # J[k, e, d] = dx_e/dxi_d
-    if kind == "quad":
+    if dim == 3:
+        J = np.stack([xyz[:, a, :] - xyz[:, 0, :] for a in (1, 2, 3)], axis=2)  # J[k, e, d] = dx_e/dxi_d
+    else:
+        second = np.where(is_quad, 3, 2)
+        J = np.stack([xyz[:, 1, :] - xyz[:, 0, :], xyz[np.arange(K), second, :] - xyz[:, 0, :]], axis=2)
+    if is_quad.any():
         # the affine map of the unit square: a parallelogram
-        gap = np.abs(xyz[:, 2] - xyz[:, 1] - xyz[:, 3] + xyz[:, 0]).max(axis=1)
-        size = np.abs(J).max(axis=(1, 2))
+        q = np.nonzero(is_quad)[0]
+        gap = np.abs(xyz[q, 2] - xyz[q, 1] - xyz[q, 3] + xyz[q, 0]).max(axis=1)
+        size = np.abs(J[q]).max(axis=(1, 2))
         if (gap > 1e-12 * size).any():
-            raise MeshError("quadrilateral %d is not a parallelogram" % int(np.argmax(gap / size)))
+            raise MeshError("quadrilateral %d is not a parallelogram" % int(q[np.argmax(gap / size)]))
     detJ = np.linalg.det(J)
     if (detJ <= 0).any():
         raise MeshError("element %d has non-positive measure" % int(np.argmin(detJ)))
     Jinv = np.linalg.inv(J)  # Jinv[k, d, e] = dxi_d/dx_e
-    elem_measure = detJ * {"tri": 0.5, "quad": 1.0, "tet": 1.0 / 6.0}[kind]
+    elem_measure = detJ * np.where(is_quad, 1.0, 0.5 if dim == 2 else 1.0 / 6.0)
 
     key_to_face = {}
     face_elem = []
@@ -126,7 +140,7 @@ def build_mesh(elem_vert, elem_xyz) -> Mesh:
     face_vert = []
     elem_face = np.full((K, F), -1, dtype=np.int64)
     for i in range(K):
-        for k, loc in enumerate(lf):
+        for k, loc in enumerate(faces_of(i)):
             vids = tuple(int(ev[i, a]) for a in loc)
             key = tuple(sorted(vids))
             f = key_to_face.get(key)
@@ -148,9 +162,14 @@ def build_mesh(elem_vert, elem_xyz) -> Mesh:
     E = len(face_elem)
 
     # geometry from L's own coordinates (vectorised over faces)
-    LF = np.array(lf, dtype=np.int64)
     L = face_elem[:, 0]
-    P = xyz[L[:, None], LF[face_local[:, 0]], :]          # [E, nfv, dim]
+    if dim == 3:
+        LFv = np.array(local_faces("tet"), dtype=np.int64)[face_local[:, 0]]
+    else:
+        lq = np.array(local_faces("quad"), dtype=np.int64)
+        lt = np.array(local_faces("tri") + [(0, 0)], dtype=np.int64)   # padded to four rows
+        LFv = np.where(is_quad[L][:, None], lq[face_local[:, 0]], lt[face_local[:, 0]])
+    P = xyz[L[:, None], LFv, :]                           # [E, nfv, dim]
     if dim == 2:
         t = P[:, 1] - P[:, 0]
         measure = np.hypot(t[:, 0], t[:, 1])
@@ -165,15 +184,21 @@ def build_mesh(elem_vert, elem_xyz) -> Mesh:
         measure = 0.5 * ar
     # reference coordinates of the face vertices (L's order) on each side:
     # the position of each vertex id inside the side's element
-    ref = REF_VERTS[kind]
     face_ref = np.zeros((E, 2, dim, dim))
     for side in (0, 1):
         e = face_elem[:, side]
         has = e >= 0
-        evs = ev[np.where(has, e, 0)]
+        es = np.where(has, e, 0)
+        evs = ev[es]
         pos = np.argmax(evs[:, None, :] == face_vert[:, :, None], axis=2)
-        face_ref[:, side] = np.where(has[:, None, None], ref[pos], 0.0)
+        if dim == 3:
+            refs = REF_VERTS["tet"][pos]
+        else:
+            # triangles never reach position 3 (their fourth id is -1)
+            refs = np.where(is_quad[es][:, None, None], REF_VERTS["quad"][pos],
+                            REF_VERTS["tri"][np.minimum(pos, 2)])
+        face_ref[:, side] = np.where(has[:, None, None], refs, 0.0)
     return Mesh(dim=dim, K=K, E=E, elem_vert=ev, elem_xyz=xyz, face_elem=face_elem,
                 face_local=face_local, face_vert=face_vert, elem_face=elem_face,
                 normal=normal, measure=measure, detJ=detJ, Jinv=Jinv, elem_measure=elem_measure,
-                face_ref=face_ref, kind=kind)
+                face_ref=face_ref, kind=kind, elem_kind=ek)

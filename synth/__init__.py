@@ -14,6 +14,7 @@ from .meshes import (  # noqa: F401
     element_measure,
     element_centroid,
     adapt_flags,
+    hybrid_grid,
     quad_grid,
     refine_flags,
 )

@@ -110,6 +110,31 @@ def quad_grid(n: int, jitter: float = 0.1, seed: int = 1, length: float = 1.0, p
     return {"elem_vert": ev, "elem_xyz": xyz, "n_vert": nv_side * nv_side, "h": h, "periodic": periodic}
 
 
+def hybrid_grid(n: int, jitter: float = 0.1, seed: int = 1, radius: float = 0.25, center=(0.5, 0.5),
+                periodic: bool = True):
+    """Conforming triangle / quadrilateral mesh: the cells of ``quad_grid`` whose
+    center lies within ``radius`` of ``center`` are each split into two
+    triangles along the diagonal ``(i, j) - (i+1, j+1)`` (lower-right, then
+    upper-left), the others stay parallelograms.  Cells are taken row by row.
+    Returns ``elem_vert [K, 4]`` with ``-1`` as the fourth vertex of a
+    triangle and ``elem_xyz [K, 4, 2]`` with zeros there."""
+    g = quad_grid(n, jitter=jitter, seed=seed, periodic=periodic)
+    ev4, x4 = g["elem_vert"], g["elem_xyz"]
+    cen = x4.mean(axis=1)
+    split = np.hypot(cen[:, 0] - center[0], cen[:, 1] - center[1]) < radius
+    ev, xyz = [], []
+    for k in range(len(ev4)):
+        if split[k]:
+            for tri in ((0, 1, 2), (0, 2, 3)):
+                ev.append([ev4[k, a] for a in tri] + [-1])
+                xyz.append(np.concatenate([x4[k, list(tri)], np.zeros((1, 2))]))
+        else:
+            ev.append(list(ev4[k]))
+            xyz.append(x4[k])
+    return {"elem_vert": np.array(ev, dtype=np.int32), "elem_xyz": np.array(xyz), "n_vert": g["n_vert"],
+            "h": g["h"], "periodic": periodic, "n_tri": int(2 * split.sum()), "n_quad": int((~split).sum())}
+
+
 def _poisson_disc(radius: float, seed: int, max_fail: int = 12):
     """Poisson-disc points in the unit square, with boundary points every ``radius``.
 

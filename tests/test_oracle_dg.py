@@ -117,7 +117,8 @@ def test_convergence_isentropic_vortex_p1():
     assert rates[-1] >= 1.8, (rates, errs)
 
 
-@pytest.mark.parametrize("kind,p", [("tri", 1), ("tri", 3), ("quad", 1), ("quad", 3), ("tet", 1), ("tet", 2)])
+@pytest.mark.parametrize("kind,p", [("tri", 1), ("tri", 3), ("quad", 1), ("quad", 3), ("mixed", 2), ("tet", 1),
+                                    ("tet", 2)])
 def test_face_points_coincide_from_both_sides(kind, p):
     # every face quadrature point, mapped through the left and through the right
     # element's affine map, lands on the same physical point (up to a whole
@@ -126,6 +127,8 @@ def test_face_points_coincide_from_both_sides(kind, p):
         m = synth.periodic_tri(5, seed=4)
     elif kind == "quad":
         m = synth.quad_grid(5, seed=4)
+    elif kind == "mixed":
+        m = synth.hybrid_grid(8, seed=4)
     else:
         m = synth.kuhn_tets(4, seed=4)
     M = build_mesh(m["elem_vert"], m["elem_xyz"])
@@ -136,8 +139,11 @@ def test_face_points_coincide_from_both_sides(kind, p):
     for side in (0, 1):
         e = M.face_elem[inter, side]
         ref = np.einsum("qv,fvd->fqd", d.face_bary, M.face_ref[inter, side])
-        axes = [1, 3] if M.kind == "quad" else list(range(1, M.dim + 1))
-        J = np.stack([xyz[e, a] - xyz[e, 0] for a in axes], axis=2)   # columns = edge vectors
+        if M.dim == 3:
+            J = np.stack([xyz[e, a] - xyz[e, 0] for a in (1, 2, 3)], axis=2)   # columns = edge vectors
+        else:
+            quad = (M.elem_kind[e] == 1) if M.kind == "mixed" else np.full(len(e), M.kind == "quad")
+            J = np.stack([xyz[e, 1] - xyz[e, 0], xyz[e, np.where(quad, 3, 2)] - xyz[e, 0]], axis=2)
         phys.append(xyz[e, 0][:, None, :] + np.einsum("fde,fqe->fqd", J, ref))
     diff = phys[0] - phys[1]
     assert np.abs(diff - np.round(diff)).max() < 1e-13
