@@ -58,7 +58,7 @@ typedef enum {
     DGC_E_ALLOC = -9             /* host allocation failed */
 } dgc_status;
 
-enum { DGC_TRI = 0, DGC_QUAD = 1, DGC_TET = 2 };
+enum { DGC_TRI = 0, DGC_QUAD = 1, DGC_TET = 2, DGC_MIXED = 3 };
 
 /* dgc_color_edges flags: one coloring algorithm | one layout */
 #define DGC_COLOR_PAPER      0x01u /* modified greedy + conflict resolution (Section 3.1) */
@@ -103,24 +103,31 @@ typedef struct {
 /* Build the face table and geometry of a conforming mesh (face-wise
  * connectivity, Section 5 "stored as pointers"; left/right elements,
  * Section 3).
- *   elem_type  DGC_TRI (3 vertices, counter-clockwise, 2D) or DGC_TET
- *              (4 vertices, positive volume, 3D).
+ *   elem_type  DGC_TRI (3 vertices, counter-clockwise, 2D), DGC_QUAD (4
+ *              vertices, counter-clockwise, a parallelogram: the affine image
+ *              of the unit square), DGC_MIXED (triangles and parallelograms
+ *              in one 2D mesh, the hybrid meshes of Table 2: 4 vertex slots
+ *              per element, -1 as the fourth vertex id of a triangle) or
+ *              DGC_TET (4 vertices, positive volume, 3D).
  *   elem_vert  host int32 [n_elem][nv]: vertex ids; periodic images of a
  *              vertex share one id.
  *   elem_xyz   host f64 [n_elem][nv][dim]: each element's own (unwrapped)
  *              vertex coordinates; geometry of a face is taken from its
  *              left element.
  * Faces are numbered by first visit scanning elements 0..K-1 and local faces
- * 0..F-1 (triangle edge k joins local vertices k, k+1 mod 3; tetrahedron
- * face k is opposite vertex k); the first visitor is the left element, the
- * second the right one, a face with one visitor is a reflective wall.
+ * 0..F-1 (triangle edge k joins local vertices k, k+1 mod 3, quadrilateral
+ * edge k local vertices k, k+1 mod 4; tetrahedron face k is opposite vertex
+ * k); the first visitor is the left element, the second the right one, a
+ * face with one visitor is a reflective wall.  Errors: DGC_E_MESH also for a
+ * quadrilateral that is not a parallelogram.
  * Errors: DGC_E_ARG, DGC_E_MESH (non-positive measure, face with >2 elements),
  * DGC_E_ALLOC.  On success *out owns a new mesh. */
 dgc_status dgc_mesh_build(int32_t elem_type, int64_t n_elem, const int32_t *elem_vert,
                           const double *elem_xyz, dgc_mesh **out);
 
 /* Color the faces (Section 3.1) and lay the mesh out (Section 5).
- * DGC_COLOR_PAPER uses 3 colors for triangles and 4 for tetrahedra: a
+ * DGC_COLOR_PAPER uses as many colors as an element has faces at most: 3 for
+ * triangles, 4 for quadrilaterals, mixed meshes and tetrahedra: a
  * modified greedy pass with random non-conflicting colors (SplitMix64 seeded
  * with `seed`), then conflict resolution by count-preserving swaps, loop
  * breaks that uncolor a same-colored pair, and deferral of a conflict whose
@@ -202,6 +209,7 @@ enum {
     DGC_ARR_DEV_ADAPT_KIND = 25,/* int8 [K] (layout order): origin of each leaf, as DGC_ARR_ADAPT_KIND */
     DGC_ARR_DEV_ADAPT_SRC = 26, /* int32 [4][K] (layout order): its source leaves as layout ids of the
                                    previous mesh, -1 padded */
+    DGC_ARR_DEV_ELEM_KIND = 27, /* int8 [K] (layout order), mixed meshes: 0 triangle, 1 quadrilateral */
     /* refinement bookkeeping */
     DGC_ARR_ELEM_LEVEL = 30,    /* int8 [K]: refinement level of each leaf (original ids) */
     DGC_ARR_ELEM_XYZ = 31,      /* f64 [K][nv][dim]: element vertex coordinates (original ids) */
@@ -228,7 +236,9 @@ const char *dgc_last_error(void);
  * with p+1 points on edges, the symmetric 3-point rule on tetrahedron faces
  * up to p = 1 and the collapsed Gauss-Jacobi triangle rule with (p+1)^2
  * points from p = 2, collapsed Gauss-Jacobi rules with p+1 points per
- * direction in the volume).  Orders: triangles p <= 5, tetrahedra p <= 2;
+ * direction in the volume; tensor Gauss-Legendre on quadrilaterals).
+ * Orders: triangles p <= 5, quadrilaterals and mixed meshes p <= 3,
+ * tetrahedra p <= 2;
  * DGC_E_UNSUPPORTED beyond.  Layout of the f64 array (offsets in doubles,
  * from info):
  *   trace [n_codes][n_qf][n_p]  phi_j at face point q seen through code c
@@ -240,6 +250,11 @@ const char *dgc_last_error(void);
  *                               (corner children at v0, v1, v2, then the
  *                               center child; Section 3.2 split), see
  *                               dgc_adapt_transfer
+ * Mixed meshes (DGC_MIXED): n_p = (p+1)^2 slots for every element (a
+ * triangle uses its first (p+1)(p+2)/2, its tables are zero beyond them);
+ * codes 0..11 are the triangle's, 12..27 the quadrilateral's (12 + f *
+ * n_orient + o); vb and vd hold the triangle block, then the quadrilateral
+ * block ([2][n_qv][n_p], [2][dim][n_qv][n_p]).
  * Code c = f * n_orient + o addresses local face f seen with orientation o:
  * o = 0 the face's own point order, 2D: 1 reversed, 2 / 3 reversed points on
  * the first / second half of the edge (hanging edge seen from the coarse
@@ -285,6 +300,7 @@ typedef struct {
     int32_t vol_form;          /* DGC_VOL_* */
     int32_t rk_form;           /* DGC_RK_* */
     int32_t pad_;
+    const int8_t *elem_kind;   /* [n_elem] DGC_ARR_DEV_ELEM_KIND (mixed meshes; NULL otherwise) */
 } dgc_dmesh;
 
 /* dgc_rk_step forms: DGC_RK_DEFAULT fuses each stage's combination into the

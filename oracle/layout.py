@@ -54,13 +54,19 @@ def morton_order(mesh, faces):
     if not faces:
         return faces
     dim = mesh.dim
-    lf = local_faces(mesh.kind)
+
+    def faces_of(e):
+        if mesh.kind == "mixed":
+            return local_faces("quad" if mesh.elem_kind[e] == 1 else "tri")
+        return local_faces(mesh.kind)
+
     bits = 31 if dim == 2 else 21
     scale = float(2 ** bits)
     mids = []
     for f in faces:
-        x = mesh.elem_xyz[mesh.face_elem[f, 0]]
-        verts = lf[mesh.face_local[f, 0]]
+        L = mesh.face_elem[f, 0]
+        x = mesh.elem_xyz[L]
+        verts = faces_of(L)[mesh.face_local[f, 0]]
         m = []
         for d in range(dim):
             s = 0.0

@@ -16,7 +16,7 @@ import numpy as np
 from . import _lib
 from ._lib import (  # noqa: F401
     DGC_COLOR_GREEDY_STD, DGC_COLOR_PAPER, DGC_F32, DGC_F64, DGC_LAYOUT_NONE, DGC_LAYOUT_PAPER,
-    DGC_LAYOUT_PAPER_SFC, DGC_LAYOUT_RENUMBER, DGC_QUAD, DGC_SURF_ATOMIC, DGC_SURF_COLORED, DGC_SURF_GATHER, DGC_TET,
+    DGC_LAYOUT_PAPER_SFC, DGC_LAYOUT_RENUMBER, DGC_MIXED, DGC_QUAD, DGC_SURF_ATOMIC, DGC_SURF_COLORED, DGC_SURF_GATHER, DGC_TET,
     DGC_TRI, DgcError,
 )
 
@@ -46,7 +46,13 @@ class Mesh:
     def build(cls, elem_vert, elem_xyz) -> "Mesh":
         ev = np.ascontiguousarray(elem_vert, dtype=np.int32)
         xyz = np.ascontiguousarray(elem_xyz, dtype=np.float64)
-        et = DGC_TRI if ev.shape[1] == 3 else (DGC_QUAD if xyz.shape[2] == 2 else DGC_TET)
+        if ev.shape[1] == 3:
+            et = DGC_TRI
+        elif xyz.shape[2] == 3:
+            et = DGC_TET
+        else:
+            # a -1 fourth vertex marks a triangle of a mixed mesh
+            et = DGC_MIXED if (ev[:, 3] < 0).any() else DGC_QUAD
         h = C.c_void_p()
         _lib.check(_L.dgc_mesh_build(et, ev.shape[0], _ptr(ev), _ptr(xyz), C.byref(h)), "dgc_mesh_build")
         return cls(h)
@@ -150,6 +156,7 @@ class DeviceMesh:
         self.elem_geo = up(mesh.export("dev_elem_geo"))
         self.elem_slots = up(mesh.export("dev_elem_slots")) if with_slots else None
         self.tables = up(tab)
+        self.elem_kind = up(mesh.export("dev_elem_kind")) if info["elem_type"] == DGC_MIXED else None
         self.elem_new = mesh.export("elem_new").astype(np.int64)
         dm = _lib.DMesh()
         dm.elem_type = info["elem_type"]
@@ -177,6 +184,7 @@ class DeviceMesh:
         dm.xcd_remap = 0
         dm.vol_form = 0
         dm.rk_form = 0
+        dm.elem_kind = self.elem_kind.data_ptr() if self.elem_kind is not None else None
         self.dm = dm
 
     FORMS = {"default": 0, "team": 1, "thread": 2, "team_prefetch": 3, "mode_team": 4}

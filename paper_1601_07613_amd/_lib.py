@@ -8,7 +8,7 @@ from pathlib import Path
 
 LIB_PATH = Path(__file__).resolve().parent / "libdgc.so"
 
-DGC_TRI, DGC_QUAD, DGC_TET = 0, 1, 2
+DGC_TRI, DGC_QUAD, DGC_TET, DGC_MIXED = 0, 1, 2, 3
 DGC_COLOR_PAPER, DGC_COLOR_GREEDY_STD = 0x01, 0x02
 DGC_LAYOUT_PAPER, DGC_LAYOUT_RENUMBER, DGC_LAYOUT_NONE, DGC_LAYOUT_PAPER_SFC = 0x10, 0x20, 0x40, 0x80
 DGC_MAX_COLORS = 8
@@ -31,7 +31,7 @@ ARR = {
     "dev_face_geo": (22, "float64"), "dev_elem_geo": (23, "float64"), "dev_elem_slots": (24, "int32"),
     "elem_level": (30, "int8"), "elem_xyz": (31, "float64"), "elem_vert": (32, "int32"),
     "adapt_kind": (33, "int8"), "adapt_src": (34, "int32"), "dev_adapt_kind": (25, "int8"),
-    "dev_adapt_src": (26, "int32"),
+    "dev_adapt_src": (26, "int32"), "dev_elem_kind": (27, "int8"),
 }
 
 
@@ -71,7 +71,7 @@ class DMesh(C.Structure):
         ("face_lr", C.c_void_p), ("face_code", C.c_void_p), ("face_geo", C.c_void_p),
         ("elem_geo", C.c_void_p), ("elem_slots", C.c_void_p), ("tables", C.c_void_p),
         ("surf_form", C.c_int32), ("block_size", C.c_int32), ("xcd_remap", C.c_int32), ("vol_form", C.c_int32),
-        ("rk_form", C.c_int32), ("pad_", C.c_int32),
+        ("rk_form", C.c_int32), ("pad_", C.c_int32), ("elem_kind", C.c_void_p),
     ]
 
 

@@ -33,7 +33,7 @@ const char *dgc_version(void) { return "dgc 0.1 (gfx950)"; }
 dgc_status dgc_mesh_build(int32_t elem_type, int64_t n_elem, const int32_t *elem_vert, const double *elem_xyz,
                           dgc_mesh **out) {
     if (!out || !elem_vert || !elem_xyz || n_elem <= 0) return fail(DGC_E_ARG, "dgc_mesh_build: bad argument");
-    if (elem_type != DGC_TRI && elem_type != DGC_QUAD && elem_type != DGC_TET)
+    if (elem_type != DGC_TRI && elem_type != DGC_QUAD && elem_type != DGC_TET && elem_type != DGC_MIXED)
         return fail(DGC_E_ARG, "dgc_mesh_build: unknown element type");
     if (n_elem > (int64_t)1 << 30) return fail(DGC_E_ARG, "dgc_mesh_build: too many elements");
     *out = nullptr;
@@ -50,7 +50,13 @@ dgc_status dgc_mesh_build(int32_t elem_type, int64_t n_elem, const int32_t *elem
         m.elem_xyz.assign(elem_xyz, elem_xyz + n_elem * m.nv * m.dim);
         m.elem_level.assign(n_elem, 0);
         m.n_vert = 0;
+        if (elem_type == DGC_MIXED) {
+            // the fourth vertex id -1 marks a triangle
+            m.elem_kind.resize(n_elem);
+            for (int64_t i = 0; i < n_elem; ++i) m.elem_kind[i] = m.elem_vert[i * 4 + 3] >= 0 ? 1 : 0;
+        }
         for (int64_t i = 0; i < n_elem * m.nv; ++i) {
+            if (elem_type == DGC_MIXED && i % 4 == 3 && m.elem_kind[i / 4] == 0) continue;
             if (m.elem_vert[i] < 0) {
                 delete h;
                 return fail(DGC_E_ARG, "dgc_mesh_build: negative vertex id");
@@ -195,6 +201,12 @@ dgc_status dgc_mesh_export(const dgc_mesh *h, int32_t which, void *dst, size_t b
             case DGC_ARR_ELEM_LEVEL: return copy_out(m.elem_level, dst, bytes, needed);
             case DGC_ARR_ELEM_XYZ: return copy_out(m.elem_xyz, dst, bytes, needed);
             case DGC_ARR_ELEM_VERT: return copy_out(m.elem_vert, dst, bytes, needed);
+            case DGC_ARR_DEV_ELEM_KIND: {
+                if (m.elem_type != DGC_MIXED) return fail(DGC_E_ARG, "dgc_mesh_export: not a mixed mesh");
+                std::vector<int8_t> v(K);
+                for (int64_t i = 0; i < K; ++i) v[m.elem_new[i]] = m.elem_kind[i];
+                return copy_out(v, dst, bytes, needed);
+            }
             case DGC_ARR_ADAPT_KIND:
             case DGC_ARR_ADAPT_SRC:
             case DGC_ARR_DEV_ADAPT_KIND:
@@ -229,8 +241,15 @@ dgc_status dgc_mesh_export(const dgc_mesh *h, int32_t which, void *dst, size_t b
                 std::vector<uint8_t> v(2 * E);
                 for (int64_t k = 0; k < E; ++k) {
                     int32_t f = m.face_order[k];
-                    v[k] = (uint8_t)(m.face_fL[f] * m.n_orient + m.face_oL[f]);
-                    v[E + k] = m.face_R[f] >= 0 ? (uint8_t)(m.face_fR[f] * m.n_orient + m.face_oR[f]) : 0;
+                    // mixed meshes: the quadrilateral's codes follow the triangle's 3 faces
+                    const int offL = m.elem_type == DGC_MIXED && m.elem_kind[m.face_L[f]] ? 3 * m.n_orient : 0;
+                    v[k] = (uint8_t)(offL + m.face_fL[f] * m.n_orient + m.face_oL[f]);
+                    if (m.face_R[f] >= 0) {
+                        const int offR = m.elem_type == DGC_MIXED && m.elem_kind[m.face_R[f]] ? 3 * m.n_orient : 0;
+                        v[E + k] = (uint8_t)(offR + m.face_fR[f] * m.n_orient + m.face_oR[f]);
+                    } else {
+                        v[E + k] = 0;
+                    }
                 }
                 return copy_out(v, dst, bytes, needed);
             }

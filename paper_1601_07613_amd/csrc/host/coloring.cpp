@@ -45,6 +45,7 @@ struct Colorer {
         unsigned u = 0;
         const int32_t *fa = &m.elem_face[e * m.max_slots];
         for (int k = 0; k < F; ++k) {
+            if (fa[k] < 0) continue;  // padded slot (an element with fewer faces)
             int8_t c = color[fa[k]];
             if (c >= 0) u |= 1u << c;
         }
@@ -107,13 +108,13 @@ dgc_status color_paper(Mesh &m, uint64_t seed, int64_t max_swaps, dgc_color_stat
             const int32_t *fl = &m.elem_face[lc * m.max_slots];
             for (int k = 0; k < F; ++k) {
                 int64_t g = fl[k];
-                if (g != cur && color[g] >= 0 && !(uR & (1u << color[g]))) cand[nc++] = g;
+                if (g >= 0 && g != cur && color[g] >= 0 && !(uR & (1u << color[g]))) cand[nc++] = g;
             }
             if (rc >= 0) {
                 const int32_t *fr = &m.elem_face[rc * m.max_slots];
                 for (int k = 0; k < F; ++k) {
                     int64_t g = fr[k];
-                    if (g != cur && color[g] >= 0 && !(uL & (1u << color[g]))) cand[nc++] = g;
+                    if (g >= 0 && g != cur && color[g] >= 0 && !(uL & (1u << color[g]))) cand[nc++] = g;
                 }
             }
             int nu = 0;
@@ -139,10 +140,10 @@ dgc_status color_paper(Mesh &m, uint64_t seed, int64_t max_swaps, dgc_color_stat
                 int8_t x = rng.choose(buf, n);
                 int64_t gl = -1, gr = -1;
                 for (int k = 0; k < F; ++k)
-                    if (color[fl[k]] == x) gl = fl[k];
+                    if (fl[k] >= 0 && color[fl[k]] == x) gl = fl[k];
                 const int32_t *fr = &m.elem_face[rc * m.max_slots];
                 for (int k = 0; k < F; ++k)
-                    if (color[fr[k]] == x) gr = fr[k];
+                    if (fr[k] >= 0 && color[fr[k]] == x) gr = fr[k];
                 color[cur] = x;
                 color[gl] = -1;
                 color[gr] = -1;

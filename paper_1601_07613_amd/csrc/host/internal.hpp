@@ -20,7 +20,8 @@ struct Mesh {
     int n_orient = 4;             // orientation codes per local face
     int64_t K = 0, E = 0, n_boundary = 0;
 
-    std::vector<int32_t> elem_vert;  // [K][nv]
+    std::vector<int32_t> elem_vert;  // [K][nv] (mixed meshes: -1 as the fourth vertex of a triangle)
+    std::vector<int8_t> elem_kind;   // mixed meshes: [K] 0 triangle, 1 quadrilateral (else empty)
     std::vector<double> elem_xyz;    // [K][nv][dim]
     std::vector<int8_t> elem_level;  // [K] refinement level
 
@@ -83,7 +84,9 @@ struct Mesh {
 dgc_status build_faces(Mesh &m);        // face table + geometry from elem_vert / elem_xyz
 dgc_status elem_geometry(Mesh &m);      // detJ, J^-1 of every element
 dgc_status face_geometry(Mesh &m);      // normal (from the left element) and measure of every face
-int face_vertex(const Mesh &m, int local_face, int k);
+int face_vertex(const Mesh &m, int64_t elem, int local_face, int k);  // local vertex of a face
+bool elem_is_quad(const Mesh &m, int64_t elem);
+int elem_n_faces(const Mesh &m, int64_t elem);
 // coloring.cpp
 dgc_status color_paper(Mesh &m, uint64_t seed, int64_t max_swaps, dgc_color_stats *st);
 dgc_status color_greedy_std(Mesh &m, dgc_color_stats *st);

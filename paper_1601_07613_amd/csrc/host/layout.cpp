@@ -37,7 +37,7 @@ std::vector<uint64_t> morton_codes(const Mesh &m, const std::vector<int32_t> &fa
         const double *x = &m.elem_xyz[(int64_t)m.face_L[f] * m.nv * dim];
         for (int d = 0; d < dim; ++d) {
             double s = 0.0;
-            for (int a = 0; a < nfv; ++a) s += x[face_vertex(m, m.face_fL[f], a) * dim + d];
+            for (int a = 0; a < nfv; ++a) s += x[face_vertex(m, m.face_L[f], m.face_fL[f], a) * dim + d];
             const double v = s / nfv;
             mid[i * dim + d] = v;
             if (i == 0 || v < lo[d]) lo[d] = v;

@@ -32,9 +32,15 @@ int perm3_index(int p0, int p1, int p2) { return p0 * 2 + (p1 > p2 ? 1 : 0); }
 
 }  // namespace
 
-int face_vertex(const Mesh &m, int local_face, int k) {
+bool elem_is_quad(const Mesh &m, int64_t elem) {
+    return m.elem_type == DGC_QUAD || (m.elem_type == DGC_MIXED && m.elem_kind[elem] == 1);
+}
+
+int elem_n_faces(const Mesh &m, int64_t elem) { return m.dim == 3 || elem_is_quad(m, elem) ? 4 : 3; }
+
+int face_vertex(const Mesh &m, int64_t elem, int local_face, int k) {
     if (m.dim == 3) return kTetFace[local_face][k];
-    return m.nv == 4 ? kQuadFace[local_face][k] : kTriFace[local_face][k];
+    return elem_is_quad(m, elem) ? kQuadFace[local_face][k] : kTriFace[local_face][k];
 }
 
 dgc_status elem_geometry(Mesh &m) {
@@ -48,10 +54,11 @@ dgc_status elem_geometry(Mesh &m) {
         if (dim == 2) {
             // columns: vertex 1 - vertex 0 and (triangle) vertex 2 - vertex 0 or
             // (quadrilateral) vertex 3 - vertex 0
-            const int v2 = nv == 4 ? 3 : 2;
+            const bool quad = elem_is_quad(m, i);
+            const int v2 = quad ? 3 : 2;
             double a = x[2] - x[0], b = x[2 * v2] - x[0];      // J[0][0], J[0][1]
             double c = x[3] - x[1], d = x[2 * v2 + 1] - x[1];  // J[1][0], J[1][1]
-            if (nv == 4) {
+            if (quad) {
                 // an affine image of the unit square: x2 = x1 + x3 - x0
                 const double gx = x[4] - x[2] - x[6] + x[0], gy = x[5] - x[3] - x[7] + x[1];
                 const double size = std::max(std::max(std::fabs(a), std::fabs(b)), std::max(std::fabs(c), std::fabs(d)));
@@ -102,8 +109,8 @@ dgc_status face_geometry(Mesh &m) {
         const int fL = m.face_fL[f];
         const double *x = &m.elem_xyz[L * nv * dim];
         if (dim == 2) {
-            const double *a = x + 2 * face_vertex(m, fL, 0);
-            const double *b = x + 2 * face_vertex(m, fL, 1);
+            const double *a = x + 2 * face_vertex(m, L, fL, 0);
+            const double *b = x + 2 * face_vertex(m, L, fL, 1);
             double tx = b[0] - a[0], ty = b[1] - a[1];
             double len = std::hypot(tx, ty);
             m.measure[f] = len;
@@ -135,15 +142,18 @@ dgc_status build_faces(Mesh &m) {
 
     if (dgc_status g = elem_geometry(m); g != DGC_OK) return g;
 
-    // face matching
-    std::vector<FaceRec> rec(K * F);
+    // face matching (an element of a mixed mesh has 3 or 4 faces)
+    std::vector<FaceRec> rec;
+    rec.reserve(K * F);
     for (int64_t i = 0; i < K; ++i) {
-        for (int k = 0; k < F; ++k) {
-            FaceRec &r = rec[i * F + k];
+        const int Fi = elem_n_faces(m, i);
+        for (int k = 0; k < Fi; ++k) {
+            FaceRec r;
             r.key = {-1, -1, -1};
-            for (int a = 0; a < nfv; ++a) r.key[a] = m.elem_vert[i * nv + face_vertex(m, k, a)];
+            for (int a = 0; a < nfv; ++a) r.key[a] = m.elem_vert[i * nv + face_vertex(m, i, k, a)];
             std::sort(r.key.begin(), r.key.begin() + nfv);
             r.visit = i * F + k;
+            rec.push_back(r);
         }
     }
     std::sort(rec.begin(), rec.end(), [](const FaceRec &a, const FaceRec &b) {
@@ -188,8 +198,8 @@ dgc_status build_faces(Mesh &m) {
         // how the right element sees the left element's point order
         int32_t vl[3], vr[3];
         for (int a = 0; a < nfv; ++a) {
-            vl[a] = m.elem_vert[(int64_t)L * nv + face_vertex(m, fL, a)];
-            vr[a] = m.elem_vert[(int64_t)R * nv + face_vertex(m, fR, a)];
+            vl[a] = m.elem_vert[(int64_t)L * nv + face_vertex(m, L, fL, a)];
+            vr[a] = m.elem_vert[(int64_t)R * nv + face_vertex(m, R, fR, a)];
         }
         if (dim == 2) {
             if (!(vl[0] == vr[1] && vl[1] == vr[0]))
@@ -211,7 +221,7 @@ dgc_status build_faces(Mesh &m) {
     m.edge_start.assign(E, -1);
     if (dim == 2)
         for (int64_t f = 0; f < E; ++f)
-            m.edge_start[f] = m.elem_vert[(int64_t)m.face_L[f] * nv + face_vertex(m, m.face_fL[f], 0)];
+            m.edge_start[f] = m.elem_vert[(int64_t)m.face_L[f] * nv + face_vertex(m, m.face_L[f], m.face_fL[f], 0)];
     m.n_colors = 0;
     m.color.assign(E, -1);
     m.laid_out = false;

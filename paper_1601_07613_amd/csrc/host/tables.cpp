@@ -178,7 +178,47 @@ const int kPerm3[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1},
 
 }  // namespace
 
+// Mixed meshes: the triangle's and the quadrilateral's tables side by side,
+// the triangle's padded with zeros to the quadrilateral's (p+1)^2 modes.
+dgc_status build_mixed_tables(int p, dgc_table_info *info, std::vector<double> *out) {
+    if (p < 0 || p > 3) return fail(DGC_E_UNSUPPORTED, "order p=" + std::to_string(p) + " is not supported for mixed meshes");
+    dgc_table_info tt, tq;
+    std::vector<double> vt, vq;
+    dgc_status s = build_tables(DGC_TRI, p, &tt, out ? &vt : nullptr);
+    if (s == DGC_OK) s = build_tables(DGC_QUAD, p, &tq, out ? &vq : nullptr);
+    if (s != DGC_OK) return s;
+    dgc_table_info ti = tq;
+    ti.elem_type = DGC_MIXED;
+    ti.n_codes = tt.n_codes + tq.n_codes;
+    const int np = tq.n_p, ntp = tt.n_p, qf = tq.n_qf, qv = tq.n_qv;
+    ti.off_trace = 0;
+    ti.off_proj = (int64_t)ti.n_codes * qf * np;
+    ti.off_vb = ti.off_proj + (int64_t)ti.n_codes * qf * np;
+    ti.off_vd = ti.off_vb + 2 * (int64_t)qv * np;
+    ti.off_prolong = ti.off_vd + 2 * 2 * (int64_t)qv * np;
+    ti.total = ti.off_prolong;
+    if (info) *info = ti;
+    if (!out) return DGC_OK;
+    out->assign(ti.total, 0.0);
+    double *T = out->data();
+    // rows of n_src values (tri) or np values (quad) copied into rows of np
+    auto rows = [&](int64_t dst, const double *src, int64_t n_rows, int n_src) {
+        for (int64_t r = 0; r < n_rows; ++r)
+            for (int j = 0; j < n_src; ++j) T[dst + r * np + j] = src[r * n_src + j];
+    };
+    rows(ti.off_trace, vt.data() + tt.off_trace, (int64_t)tt.n_codes * qf, ntp);
+    rows(ti.off_trace + (int64_t)tt.n_codes * qf * np, vq.data() + tq.off_trace, (int64_t)tq.n_codes * qf, np);
+    rows(ti.off_proj, vt.data() + tt.off_proj, (int64_t)tt.n_codes * qf, ntp);
+    rows(ti.off_proj + (int64_t)tt.n_codes * qf * np, vq.data() + tq.off_proj, (int64_t)tq.n_codes * qf, np);
+    rows(ti.off_vb, vt.data() + tt.off_vb, qv, ntp);
+    rows(ti.off_vb + (int64_t)qv * np, vq.data() + tq.off_vb, qv, np);
+    rows(ti.off_vd, vt.data() + tt.off_vd, 2 * (int64_t)qv, ntp);
+    rows(ti.off_vd + 2 * (int64_t)qv * np, vq.data() + tq.off_vd, 2 * (int64_t)qv, np);
+    return DGC_OK;
+}
+
 dgc_status build_tables(int32_t elem_type, int p, dgc_table_info *info, std::vector<double> *out) {
+    if (elem_type == DGC_MIXED) return build_mixed_tables(p, info, out);
     if (elem_type != DGC_TRI && elem_type != DGC_QUAD && elem_type != DGC_TET)
         return fail(DGC_E_ARG, "unknown element type");
     const bool quad = elem_type == DGC_QUAD;

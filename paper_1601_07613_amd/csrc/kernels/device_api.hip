@@ -46,6 +46,8 @@ dgc_status check_dm(const dgc_dmesh *dm, dgc_table_info *ti) {
         return fail(DGC_E_ARG, "dgc_dmesh: null device array");
     if (dm->surf_form < DGC_FORM_DEFAULT || dm->surf_form > DGC_FORM_MODE_TEAM)
         return fail(DGC_E_ARG, "dgc_dmesh: unknown surf_form");
+    if (dm->elem_type == DGC_MIXED && !dm->elem_kind)
+        return fail(DGC_E_ARG, "dgc_dmesh: a mixed mesh needs elem_kind");
     if (dm->vol_form < DGC_VOL_DEFAULT || dm->vol_form > DGC_VOL_TEAM)
         return fail(DGC_E_ARG, "dgc_dmesh: unknown vol_form");
     if (dm->block_size != 0 && dm->block_size != 64 && dm->block_size != 128 && dm->block_size != 256)
@@ -69,6 +71,16 @@ struct Impl {
     using Real = T;
 
     static dgc_status volume(const dgc_dmesh *dm, const dgc_table_info &ti, const T *U, T *rhs, hipStream_t st) {
+        if constexpr (DIM == 2) {
+            if (dm->elem_type == DGC_MIXED) {
+                // per-element kind: the team form with both kinds' tables in LDS
+                hipLaunchKernelGGL((dgc_dev::volume_team_mixed_kernel<NP, QV, T>),
+                                   dim3(grid_for(dm->n_elem * dgc_dev::volume_team_size<2>())), dim3(kBlock), 0, st,
+                                   dm->n_elem, dm->elem_kind, dm->elem_geo, dm->tables + ti.off_vb,
+                                   dm->tables + ti.off_vd, U, rhs);
+                return hip_check("volume kernel launch");
+            }
+        }
         if constexpr (DIM == 2 && std::is_same_v<T, double> && NP <= 16 && QV <= 16) {
             if (dm->vol_form == DGC_VOL_MFMA) {
                 const int64_t groups = (dm->n_elem + 15) / 16;
@@ -214,6 +226,15 @@ dgc_status dispatch(const dgc_dmesh *dm, int elem_type, int p, F &&f) {
             case 3: return f(Impl<2, 16, 4, 16, T>{});
             default: break;
         }
+    } else if (elem_type == DGC_MIXED) {
+        // (p+1)^2 slots per element, the quadrilateral's count
+        switch (p) {
+            case 0: return f(Impl<2, 1, 1, 1, T>{});
+            case 1: return f(Impl<2, 4, 2, 4, T>{});
+            case 2: return f(Impl<2, 9, 3, 9, T>{});
+            case 3: return f(Impl<2, 16, 4, 16, T>{});
+            default: break;
+        }
     } else if (elem_type == DGC_TET) {
         switch (p) {
             case 0: return f(Impl<3, 1, 3, 1, T>{});
@@ -325,6 +346,7 @@ dgc_status dgc_rk_step(const dgc_dmesh *dm, double *U, double dt, int32_t varian
     // element has exactly one face of that color (see DGC_RK_DEFAULT)
     const int faces_per_elem = dm->elem_type == DGC_TRI ? 3 : 4;
     const bool fuse = !shadow && variant == DGC_SURF_COLORED && dm->rk_form == DGC_RK_DEFAULT &&
+                      dm->elem_type != DGC_MIXED &&
                       dm->n_colors == faces_per_elem && dm->max_slots == faces_per_elem &&
                       (dm->surf_form == DGC_FORM_DEFAULT || dm->surf_form == DGC_FORM_TEAM_PREFETCH ||
                        dm->surf_form == DGC_FORM_MODE_TEAM);
@@ -469,6 +491,8 @@ dgc_status dgc_batch_describe(int32_t n_mesh, const dgc_dmesh *meshes, double *c
         if (dgc_status s = check_dm(&meshes[i], &t); s != DGC_OK) return s;
         if (dgc_status s = check_colors(&meshes[i]); s != DGC_OK) return s;
         if (i == 0) ti = t;
+        if (meshes[i].elem_type == DGC_MIXED)
+            return fail(DGC_E_UNSUPPORTED, "dgc_batch_describe: mixed meshes are not batched");
         if (meshes[i].elem_type != meshes[0].elem_type || meshes[i].p != meshes[0].p)
             return fail(DGC_E_ARG, "dgc_batch_describe: meshes of one batch share element type and order");
         if (!U[i] || !ws[i]) return fail(DGC_E_ARG, "dgc_batch_describe: null state or workspace");

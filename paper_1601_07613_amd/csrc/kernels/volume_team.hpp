@@ -23,11 +23,12 @@ constexpr int volume_team_size() {
     return DIM + 2 <= 4 ? 4 : 8;
 }
 
-// element k, lane r of its team (all lanes of the team must call)
-template <int DIM, int NP, int QV, class T>
+// element k, lane r of its team (all lanes of the team must call); the
+// tables may live in global memory (f64) or in LDS
+template <int DIM, int NP, int QV, class T, class TAB = double>
 __device__ __forceinline__ void volume_team_elem(int64_t k, int r, int64_t n_elem,
-                                                 const double *__restrict__ elem_geo, const double *__restrict__ vb,
-                                                 const double *__restrict__ vd, const T *__restrict__ U,
+                                                 const double *__restrict__ elem_geo, const TAB *__restrict__ vb,
+                                                 const TAB *__restrict__ vd, const T *__restrict__ U,
                                                  T *__restrict__ rhs) {
     constexpr int M = DIM + 2;
     constexpr int REC = M * NP;
@@ -94,6 +95,28 @@ __global__ __launch_bounds__(256) void volume_team_kernel(int64_t n_elem, const 
     const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / TEAM;
     if (k >= n_elem) return;  // whole teams leave together
     volume_team_elem<DIM, NP, QV, T>(k, threadIdx.x % TEAM, n_elem, elem_geo, vb, vd, U, rhs);
+}
+
+// Mixed triangle / quadrilateral meshes (2D, N_p = (p+1)^2 slots per
+// element): both kinds' volume tables are staged in LDS and each team picks
+// its element's block; a triangle's tables are zero beyond its own modes.
+template <int NP, int QV, class T>
+__global__ __launch_bounds__(256) void volume_team_mixed_kernel(int64_t n_elem, const int8_t *__restrict__ elem_kind,
+                                                                const double *__restrict__ elem_geo,
+                                                                const double *__restrict__ vb2,
+                                                                const double *__restrict__ vd2,
+                                                                const T *__restrict__ U, T *__restrict__ rhs) {
+    constexpr int TEAM = volume_team_size<2>();
+    __shared__ T s_vb[2 * QV * NP];          // [kind][q][j]
+    __shared__ T s_vd[2 * 2 * QV * NP];      // [kind][d][q][j]
+    for (int i = threadIdx.x; i < 2 * QV * NP; i += blockDim.x) s_vb[i] = T(vb2[i]);
+    for (int i = threadIdx.x; i < 4 * QV * NP; i += blockDim.x) s_vd[i] = T(vd2[i]);
+    __syncthreads();
+    const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / TEAM;
+    if (k >= n_elem) return;  // whole teams leave together
+    const int kind = elem_kind[k] ? 1 : 0;
+    volume_team_elem<2, NP, QV, T, T>(k, threadIdx.x % TEAM, n_elem, elem_geo, s_vb + kind * QV * NP,
+                                      s_vd + kind * 2 * QV * NP, U, rhs);
 }
 
 }  // namespace dgc_dev

@@ -17,6 +17,10 @@ def make_input(kind: str, size: int, seed: int):
         return synth.quad_grid(size, seed=seed)
     if kind == "quadbox":
         return synth.quad_grid(size, seed=seed, periodic=False)
+    if kind == "hybrid":
+        return synth.hybrid_grid(size, seed=seed)
+    if kind == "hybridbox":
+        return synth.hybrid_grid(size, seed=seed, periodic=False)
     raise ValueError(kind)
 
 

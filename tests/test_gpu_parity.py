@@ -39,7 +39,7 @@ def _eps(kind, p):
     (orthonormal modes grow towards the vertices with the order)."""
     if kind == "tets":
         return 0.02 if p <= 1 else 0.005
-    if kind in ("quads", "quadbox"):
+    if kind in ("quads", "quadbox", "hybrid", "hybridbox"):
         return 0.02 if p <= 2 else 0.005
     return 0.02 if p <= 3 else 0.004
 
@@ -84,14 +84,19 @@ def _check(got, ref, scale, what):
 
 
 def _volume_abs(d, U):
+    """Sum of absolute per-point volume contributions (every element kind)."""
     from oracle import euler
 
     mesh = d.mesh
-    sq = np.sqrt(mesh.detJ)
-    Uq = np.einsum("qj,kmj->kqm", d.vol_B, U) / sq[:, None, None]
-    Fq = euler.physical_flux(Uq)
-    G = np.abs(np.einsum("kde,kqme->kqmd", mesh.Jinv, Fq))
-    return np.einsum("q,qdj,kqmd->kmj", d.vol_w, np.abs(d.vol_D), G) * sq[:, None, None]
+    out = np.zeros_like(U)
+    for i, (pts, w, B, D) in enumerate(d.vol):
+        idx = d.elem_kind == i
+        sq = np.sqrt(mesh.detJ[idx])
+        Uq = np.einsum("qj,kmj->kqm", B, U[idx]) / sq[:, None, None]
+        Fq = euler.physical_flux(Uq)
+        G = np.abs(np.einsum("kde,kqme->kqmd", mesh.Jinv[idx], Fq))
+        out[idx] = np.einsum("q,qdj,kqmd->kmj", w, np.abs(D), G) * sq[:, None, None]
+    return out
 
 
 @pytest.mark.parametrize("form", ["team", "team_prefetch", "thread"])
@@ -128,6 +133,51 @@ def test_surface_quads(p, variant, form, kind, size):
     assert c.stats["n_colors"] == 4
     got = c.to_host(c.surface(variant))
     _check(got, dg.surface_rhs(c.d, c.U), dg.surface_abs(c.d, c.U), "surface %s %s p=%d" % (kind, variant, p))
+
+
+@pytest.mark.parametrize("kind,size", [("hybrid", 14), ("hybridbox", 13)])
+@pytest.mark.parametrize("form", ["default", "thread"])
+@pytest.mark.parametrize("p", [0, 1, 2, 3])
+@pytest.mark.parametrize("variant", ["colored", "atomic", "gather"])
+def test_surface_mixed(p, variant, form, kind, size):
+    """Mixed triangle / parallelogram meshes (four colors; every element has
+    (p+1)^2 slots, a triangle's tables are zero beyond its own modes)."""
+    c = Case(kind, size, 2, p)
+    c.D.set_launch(form)
+    assert c.stats["n_colors"] == 4 and c.D.info["elem_type"] == 3
+    got = c.to_host(c.surface(variant))
+    _check(got, dg.surface_rhs(c.d, c.U), dg.surface_abs(c.d, c.U), "surface %s %s p=%d" % (kind, variant, p))
+
+
+@pytest.mark.parametrize("kind,size,p", [("hybrid", 14, 1), ("hybrid", 14, 3), ("hybridbox", 13, 2)])
+def test_volume_mixed(kind, size, p):
+    import torch
+
+    c = Case(kind, size, 5, p)
+    rhs = torch.full_like(c.Ug, 7.0)
+    c.D.volume_rhs(c.Ug, rhs)
+    torch.cuda.synchronize()
+    _check(c.to_host(rhs), dg.volume_rhs(c.d, c.U), _volume_abs(c.d, c.U), "volume %s p=%d" % (kind, p))
+
+
+def test_rk3_mixed_vortex_20_steps():
+    """Isentropic vortex on a periodic hybrid mesh (triangles around the
+    center, parallelograms elsewhere), p = 2: 20 SSP-RK3 steps against the
+    oracle."""
+    import torch
+
+    c = Case("hybrid", 14, 8, 2)
+    U0 = dg.project(c.d, lambda X: synth.isentropic_vortex(X, 0.0, beta=4.0, radius=0.1))
+    dt = dg.cfl_dt(c.d, U0, 0.1)
+    Ug = torch.from_numpy(c.D.to_layout(U0)).cuda()
+    ws = c.D.workspace("rk", "colored")
+    U = U0.copy()
+    for _ in range(20):
+        c.D.rk_step(Ug, dt, ws=ws)
+        U = dg.rk3_step(c.d, U, dt)
+    torch.cuda.synchronize()
+    got = c.to_host(Ug)
+    assert np.abs(got - U).max() / np.abs(U).max() <= TOL
 
 
 @pytest.mark.parametrize("form", ["default", "team", "thread", "mode_team"])
@@ -387,7 +437,7 @@ TOL32 = 2e-6
 
 
 @pytest.mark.parametrize("kind,size,p", [("periodic", 16, 2), ("periodic", 16, 5), ("delaunay", 6000, 2),
-                                         ("tets", 5, 1), ("tets", 5, 2), ("quads", 12, 2)])
+                                         ("tets", 5, 1), ("tets", 5, 2), ("quads", 12, 2), ("hybrid", 14, 2)])
 @pytest.mark.parametrize("variant", ["colored", "atomic", "gather"])
 def test_surface_and_volume_f32(kind, size, p, variant):
     """f32 storage and arithmetic (geometry stored in f64) against the f64

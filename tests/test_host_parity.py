@@ -23,7 +23,7 @@ GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper
 HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "dgc.h")
 
 CASES = [("periodic", 16, 1), ("periodic", 37, 4), ("delaunay", 8000, 2), ("tets", 5, 3), ("quads", 20, 2),
-         ("quadbox", 23, 5)]
+         ("quadbox", 23, 5), ("hybrid", 16, 3), ("hybridbox", 15, 6)]
 
 
 def test_every_declared_symbol_is_exported():
@@ -141,6 +141,24 @@ def test_mesh_errors():
     with pytest.raises(dgc.DgcError) as e:
         dgc.Mesh.build(m["elem_vert"], xyz)
     assert e.value.name == "DGC_E_MESH"
+
+
+@pytest.mark.parametrize("p", [0, 1, 2, 3])
+def test_mixed_tables_are_the_padded_pair(p):
+    """Mixed-mesh tables: the triangle's codes, padded to (p+1)^2 modes, then
+    the quadrilateral's; volume blocks likewise."""
+    info, T = dgc.tables(dgc.DGC_MIXED, p)
+    it, Tt = dgc.tables(dgc.DGC_TRI, p)
+    iq, Tq = dgc.tables(dgc.DGC_QUAD, p)
+    np_, ntp, qf, qv = iq["n_p"], it["n_p"], iq["n_qf"], iq["n_qv"]
+    assert (info["n_p"], info["n_codes"], info["n_qf"], info["n_qv"]) == (np_, 28, qf, qv)
+    tr = T[info["off_trace"]:info["off_proj"]].reshape(28, qf, np_)
+    assert np.array_equal(tr[:12, :, :ntp], Tt[it["off_trace"]:it["off_proj"]].reshape(12, qf, ntp))
+    assert not tr[:12, :, ntp:].any()
+    assert np.array_equal(tr[12:], Tq[iq["off_trace"]:iq["off_proj"]].reshape(16, qf, np_))
+    vd = T[info["off_vd"]:info["off_prolong"]].reshape(2, 2, qv, np_)
+    assert np.array_equal(vd[0, :, :, :ntp], Tt[it["off_vd"]:it["off_prolong"]].reshape(2, qv, ntp))
+    assert np.array_equal(vd[1], Tq[iq["off_vd"]:iq["off_prolong"]].reshape(2, qv, np_))
 
 
 @pytest.mark.parametrize("et,dim,p", [(0, 2, 0), (0, 2, 1), (0, 2, 2), (0, 2, 3), (0, 2, 4), (0, 2, 5), (2, 3, 0),
