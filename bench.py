@@ -189,6 +189,19 @@ def extra_workloads(dgc, synth, torch, steps, warmup, log):
     log("quads: %s" % out["quads_1024sq_p2"])
     del DQ, Qm, Uq, wq
 
+    # mixed: the same grid with the cells within 0.3 of the center split into triangles, p = 2
+    g = synth.hybrid_grid(1024, jitter=0.1, seed=6, radius=0.3)
+    Hm = dgc.Mesh.build(g["elem_vert"], g["elem_xyz"])
+    hs = Hm.color(seed=0)
+    DH = dgc.DeviceMesh(Hm, 2)
+    info = DH.info
+    rh = surf_stats(DH, info["n_elem"], info["n_face"], info["n_boundary"], 8, "f64")
+    out["mixed_1024sq_p2"] = {"n_elem": info["n_elem"], "n_tri": g["n_tri"], "n_quad": g["n_quad"],
+                              "n_face": info["n_face"], "n_colors": info["n_colors"], "color_ms": hs["color_ms"],
+                              "conflicts_after_greedy": hs["conflicts_after_greedy"], "f64": rh}
+    log("mixed: %s" % out["mixed_1024sq_p2"])
+    del DH, Hm
+
     # c3: 128 x 128 x 2 periodic base refined to level 3 within r < 0.15, p = 2
     m = synth.periodic_tri(128, jitter=0.0, seed=4)
     A = dgc.Mesh.build(m["elem_vert"], m["elem_xyz"])

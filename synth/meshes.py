@@ -122,16 +122,19 @@ def hybrid_grid(n: int, jitter: float = 0.1, seed: int = 1, radius: float = 0.25
     ev4, x4 = g["elem_vert"], g["elem_xyz"]
     cen = x4.mean(axis=1)
     split = np.hypot(cen[:, 0] - center[0], cen[:, 1] - center[1]) < radius
-    ev, xyz = [], []
-    for k in range(len(ev4)):
-        if split[k]:
-            for tri in ((0, 1, 2), (0, 2, 3)):
-                ev.append([ev4[k, a] for a in tri] + [-1])
-                xyz.append(np.concatenate([x4[k, list(tri)], np.zeros((1, 2))]))
-        else:
-            ev.append(list(ev4[k]))
-            xyz.append(x4[k])
-    return {"elem_vert": np.array(ev, dtype=np.int32), "elem_xyz": np.array(xyz), "n_vert": g["n_vert"],
+    # output rows in cell order: a split cell gives two consecutive rows
+    start = np.concatenate([[0], np.cumsum(np.where(split, 2, 1))[:-1]])
+    K = int(start[-1] + (2 if split[-1] else 1))
+    ev = np.full((K, 4), -1, dtype=np.int32)
+    xyz = np.zeros((K, 4, 2))
+    q = ~split
+    ev[start[q]] = ev4[q]
+    xyz[start[q]] = x4[q]
+    for r, tri in enumerate(((0, 1, 2), (0, 2, 3))):
+        rows = start[split] + r
+        ev[rows, :3] = ev4[split][:, list(tri)]
+        xyz[rows, :3] = x4[split][:, list(tri)]
+    return {"elem_vert": ev, "elem_xyz": xyz, "n_vert": g["n_vert"],
             "h": g["h"], "periodic": periodic, "n_tri": int(2 * split.sum()), "n_quad": int((~split).sum())}
 
 
