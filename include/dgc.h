@@ -317,7 +317,11 @@ enum { DGC_RK_DEFAULT = 0, DGC_RK_SEPARATE = 1 };
  * p <= 3; other cases fall back to DGC_VOL_VALU) runs the two basis
  * contractions of four elements at a time on the matrix cores
  * (v_mfma_f64_16x16x4f64) and the flux between them on the vector units.
- * DGC_VOL_DEFAULT is the team form. */
+ * DGC_VOL_DEFAULT picks the form measured fastest for the element type and
+ * order: the matrix-core form for quadrilaterals at p >= 2 (f64; the team
+ * form in f32), one work-item per element for triangles at p = 3, 4 and for
+ * tetrahedra, the team form otherwise; mixed meshes always use their own
+ * team kernel. */
 enum { DGC_VOL_DEFAULT = 0, DGC_VOL_VALU = 1, DGC_VOL_MFMA = 2, DGC_VOL_TEAM = 3 };
 
 /* Face-kernel forms: DGC_FORM_TEAM gives each face a team of lanes (one lane

@@ -75,13 +75,18 @@ __global__ __launch_bounds__(256) void batch_volume_kernel(const char *__restric
     const Header *h = bh(desc);
     const int32_t m = reinterpret_cast<const int32_t *>(desc + h->off_map_elem)[blockIdx.x];
     const Entry *e = bentry(desc, m);
-    // the team form of the single-mesh default (volume_team_size lanes per element)
-    constexpr int TEAM = volume_team_size<DIM>();
-    const int64_t k = (((int64_t)blockIdx.x - e->blk_elem) * blockDim.x + threadIdx.x) / TEAM;
+    // a team of lanes per element or one work-item per element (batch_volume_lanes)
+    constexpr int LANES = batch_volume_lanes(DIM, NP);
+    const int64_t k = (((int64_t)blockIdx.x - e->blk_elem) * blockDim.x + threadIdx.x) / LANES;
     if (k >= e->n_elem) return;  // whole teams leave together
     const dgc_batch::RkWs w = dgc_batch::rk_ws(e->ws, (size_t)e->n_dof, sizeof(T) == 4);
-    volume_team_elem<DIM, NP, QV, T>(k, threadIdx.x % TEAM, e->n_elem, e->elem_geo, h->tables + h->off_vb,
-                                     h->tables + h->off_vd, stage_input<T>(e, w, stage), static_cast<T *>(w.rhs));
+    if constexpr (LANES == 1)
+        volume_elem<DIM, NP, QV, T>(k, e->n_elem, e->elem_geo, h->tables + h->off_vb, h->tables + h->off_vd,
+                                    stage_input<T>(e, w, stage), static_cast<T *>(w.rhs));
+    else
+        volume_team_elem<DIM, NP, QV, T>(k, threadIdx.x % LANES, e->n_elem, e->elem_geo, h->tables + h->off_vb,
+                                         h->tables + h->off_vd, stage_input<T>(e, w, stage),
+                                         static_cast<T *>(w.rhs));
 }
 
 // SSP-RK3 stage combination of every mesh, out = a x + b (y + dt r) with the

@@ -23,6 +23,15 @@ namespace {
 
 constexpr int kBlock = 256;
 
+// DGC_VOL_DEFAULT: the volume form measured fastest for each element type and
+// order (f64, ~1M elements; mixed meshes always use their own team kernel)
+int default_volume_form(int elem_type, int p) {
+    if (elem_type == DGC_QUAD) return p >= 2 ? DGC_VOL_MFMA : DGC_VOL_TEAM;
+    if (elem_type == DGC_TRI) return (p == 3 || p == 4) ? DGC_VOL_VALU : DGC_VOL_TEAM;
+    // tetrahedra: the 8-lane team (5 variables) is 2-9x slower than one work-item per element
+    return DGC_VOL_VALU;
+}
+
 inline unsigned grid_for(int64_t n, int block = kBlock) { return (unsigned)((n + block - 1) / block); }
 
 dgc_status hip_check(const char *what) {
@@ -81,8 +90,9 @@ struct Impl {
                 return hip_check("volume kernel launch");
             }
         }
+        const int vf = dm->vol_form == DGC_VOL_DEFAULT ? default_volume_form(dm->elem_type, dm->p) : dm->vol_form;
         if constexpr (DIM == 2 && std::is_same_v<T, double> && NP <= 16 && QV <= 16) {
-            if (dm->vol_form == DGC_VOL_MFMA) {
+            if (vf == DGC_VOL_MFMA) {
                 const int64_t groups = (dm->n_elem + 15) / 16;
                 const unsigned grid = (unsigned)(groups < 4096 ? groups : 4096);
                 hipLaunchKernelGGL((dgc_dev::volume_mfma_kernel<NP, QV>), dim3(grid), dim3(256), 0, st, dm->n_elem,
@@ -90,7 +100,8 @@ struct Impl {
                 return hip_check("volume kernel launch");
             }
         }
-        if (dm->vol_form == DGC_VOL_DEFAULT || dm->vol_form == DGC_VOL_TEAM) {
+        // the team form, also where the default's matrix-core form does not apply (f32)
+        if (vf == DGC_VOL_TEAM || (dm->vol_form == DGC_VOL_DEFAULT && vf == DGC_VOL_MFMA)) {
             constexpr int TEAM = DIM + 2 <= 4 ? 4 : 8;
             hipLaunchKernelGGL((dgc_dev::volume_team_kernel<DIM, NP, QV, T>), dim3(grid_for(dm->n_elem * TEAM)),
                                dim3(kBlock), 0, st, dm->n_elem, dm->elem_geo, dm->tables + ti.off_vb,
@@ -501,8 +512,8 @@ dgc_status dgc_batch_describe(int32_t n_mesh, const dgc_dmesh *meshes, double *c
     // lanes per face of batch_surface_kernel (batch_team<DIM, NP>)
     const int team = (ti.dim == 3 && ti.n_p == 4) ? 4 : (ti.dim + 2 <= 4 ? 4 : 8);
     const int fpb = kBlock / team;
-    // lanes per element of batch_volume_kernel (volume_team_size<DIM>)
-    const int vteam = ti.dim + 2 <= 4 ? 4 : 8;
+    // lanes per element of batch_volume_kernel
+    const int vteam = dgc_dev::batch_volume_lanes(ti.dim, ti.n_p);
     int nc = 0;
     for (int32_t i = 0; i < n_mesh; ++i) nc = meshes[i].n_colors > nc ? meshes[i].n_colors : nc;
     // work-group counts

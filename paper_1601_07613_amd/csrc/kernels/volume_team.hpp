@@ -23,6 +23,14 @@ constexpr int volume_team_size() {
     return DIM + 2 <= 4 ? 4 : 8;
 }
 
+// Lanes per element of the batched volume term: the team form where it is
+// the faster vector form, one work-item per element where that is faster
+// (tetrahedra; 2D with 9, 10 or 15 modes: quadrilaterals at p = 2, triangles
+// at p = 3, 4; measured on 1M-element meshes).  Host and device share this rule.
+__host__ __device__ constexpr int batch_volume_lanes(int dim, int np) {
+    return (dim == 3 || np == 9 || np == 10 || np == 15) ? 1 : 4;
+}
+
 // element k, lane r of its team (all lanes of the team must call); the
 // tables may live in global memory (f64) or in LDS
 template <int DIM, int NP, int QV, class T, class TAB = double>

@@ -120,7 +120,7 @@ def hybrid_grid(n: int, jitter: float = 0.1, seed: int = 1, radius: float = 0.25
     triangle and ``elem_xyz [K, 4, 2]`` with zeros there."""
     g = quad_grid(n, jitter=jitter, seed=seed, periodic=periodic)
     ev4, x4 = g["elem_vert"], g["elem_xyz"]
-    cen = x4.mean(axis=1)
+    cen = x4.mean(axis=1)                    # cell centers
     split = np.hypot(cen[:, 0] - center[0], cen[:, 1] - center[1]) < radius
     # output rows in cell order: a split cell gives two consecutive rows
     start = np.concatenate([[0], np.cumsum(np.where(split, 2, 1))[:-1]])
@@ -298,13 +298,26 @@ def kuhn_tets(n: int, jitter: float = 0.05, seed: int = 3, length: float = 1.0):
     return {"elem_vert": ev, "elem_xyz": xyz, "n_vert": n ** 3, "h": h, "periodic": True}
 
 
-def element_measure(elem_xyz: np.ndarray) -> np.ndarray:
-    """Signed area (triangles) or volume (tetrahedra) of each element."""
+def _tri_rows(elem_xyz, elem_vert):
+    """Rows of a 4-slot 2D table that hold triangles (fourth vertex id -1)."""
+    if elem_vert is None:
+        return np.zeros(len(elem_xyz), dtype=bool)
+    return np.asarray(elem_vert)[:, 3] < 0
+
+
+def element_measure(elem_xyz: np.ndarray, elem_vert=None) -> np.ndarray:
+    """Signed area (triangles, parallelograms) or volume (tetrahedra) of each
+    element; for a 4-slot 2D table pass ``elem_vert`` so that the rows with a
+    -1 fourth vertex are taken as triangles."""
     x = np.asarray(elem_xyz, dtype=np.float64)
-    if x.shape[1] == 3 and x.shape[2] == 2:
+    if x.shape[2] == 2 and x.shape[1] in (3, 4):
         a = x[:, 1] - x[:, 0]
-        b = x[:, 2] - x[:, 0]
-        return 0.5 * (a[:, 0] * b[:, 1] - a[:, 1] * b[:, 0])
+        if x.shape[1] == 3:
+            b = x[:, 2] - x[:, 0]
+            return 0.5 * (a[:, 0] * b[:, 1] - a[:, 1] * b[:, 0])
+        tri = _tri_rows(x, elem_vert)
+        b = np.where(tri[:, None], x[:, 2] - x[:, 0], x[:, 3] - x[:, 0])
+        return np.where(tri, 0.5, 1.0) * (a[:, 0] * b[:, 1] - a[:, 1] * b[:, 0])
     if x.shape[1] == 4 and x.shape[2] == 3:
         a = x[:, 1] - x[:, 0]
         b = x[:, 2] - x[:, 0]
@@ -313,8 +326,15 @@ def element_measure(elem_xyz: np.ndarray) -> np.ndarray:
     raise ValueError("unsupported element shape %r" % (x.shape,))
 
 
-def element_centroid(elem_xyz: np.ndarray) -> np.ndarray:
-    return np.asarray(elem_xyz, dtype=np.float64).mean(axis=1)
+def element_centroid(elem_xyz: np.ndarray, elem_vert=None) -> np.ndarray:
+    """Vertex average of each element (a 4-slot 2D table with ``elem_vert``:
+    the triangles' first three vertices)."""
+    x = np.asarray(elem_xyz, dtype=np.float64)
+    c = x.mean(axis=1)
+    if x.shape[1] == 4 and x.shape[2] == 2 and elem_vert is not None:
+        tri = _tri_rows(x, elem_vert)
+        c[tri] = x[tri, :3].mean(axis=1)
+    return c
 
 
 def refine_flags(elem_xyz: np.ndarray, levels: np.ndarray, level: int, center=(0.5, 0.5),

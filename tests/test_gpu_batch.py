@@ -22,7 +22,9 @@ def _member(kind, size, seed, p, precision="f64", smooth=False):
         st = synth.uniform_states(len(cen), vel=(0.3, -0.2, 0.1)[:D.dim])
     else:
         st = synth.density_wave_states(cen) if D.dim == 3 else synth.shock_tube_states(cen)
-    U = synth.perturbed_dofs(synth.element_measure(m["elem_xyz"]), st, D.n_p, eps=0.02, seed=seed)
+    # smaller high-mode noise at p >= 3 keeps every trace state physical
+    U = synth.perturbed_dofs(synth.element_measure(m["elem_xyz"]), st, D.n_p, eps=0.02 if p <= 2 else 0.005,
+                             seed=seed)
     Ug = torch.from_numpy(D.to_layout(U)).cuda()
     ws = D.workspace("rk", "colored", precision)
     dt = 1e-4 * (1 + seed % 3)
@@ -33,18 +35,23 @@ def _member(kind, size, seed, p, precision="f64", smooth=False):
 TRI = [("periodic", 12, 1), ("delaunay", 3000, 2), ("periodic", 16, 3), ("periodic", 9, 4), ("delaunay", 1200, 5)]
 
 
-@pytest.mark.parametrize("p", [1, 2])
-def test_batched_stage_rhs_is_bitwise_single(p):
+QUAD = [("quads", 8, 1), ("quadbox", 9, 2), ("quads", 12, 3)]
+
+
+@pytest.mark.parametrize("family,p", [("tri", 1), ("tri", 2), ("tri", 3), ("quad", 1), ("quad", 2), ("quad", 3)])
+def test_batched_stage_rhs_is_bitwise_single(family, p):
     import torch
 
     import paper_1601_07613_amd as dgc
 
-    members = [_member(k, s, sd, p) for k, s, sd in TRI]
+    members = [_member(k, s, sd, p) for k, s, sd in (TRI if family == "tri" else QUAD)]
     B = dgc.Batch(members)
     B.volume(0)
     B.surface(0)
     torch.cuda.synchronize()
     for i, (D, Ug, ws, dt) in enumerate(members):
+        # the batch runs the vector volume forms: compare against the same form
+        D.set_volume_form("valu" if D.dim == 3 or D.n_p in (9, 10, 15) else "team")
         r = torch.zeros_like(Ug)
         D.volume_rhs(Ug, r)
         D.surface_rhs(Ug, r)

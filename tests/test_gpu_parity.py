@@ -28,7 +28,7 @@ def _dgc():
 
 
 def _states(m, K):
-    cen = synth.element_centroid(m["elem_xyz"])
+    cen = synth.element_centroid(m["elem_xyz"], m["elem_vert"])
     if m["elem_xyz"].shape[2] == 3:
         return synth.density_wave_states(cen)
     return synth.shock_tube_states(cen)
