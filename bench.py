@@ -122,9 +122,15 @@ def extra_workloads(dgc, synth, torch, steps, warmup, log):
     ws = D.workspace("rk", "colored")
     B = dgc.Batch([(D, U, ws, 1e-9)])
     g = B.capture(steps=10)
+    forms = {}
+    for rf in ("block", "fused", "separate"):
+        D.set_rk_form(rf)
+        forms[rf] = time_call(lambda: D.rk_step(U, 1e-9, ws=ws), reps=100, warmup=10) * 1e3
+    D.set_rk_form("default")
     out["c0_periodic512_p1"] = {
         "surface_pass_us": time_call(lambda: D.surface_rhs(U, rhs), reps=200, warmup=20) * 1e3,
         "rk3_step_us": time_call(lambda: D.rk_step(U, 1e-9, ws=ws), reps=100, warmup=10) * 1e3,
+        "rk3_step_by_form_us": forms,
         "rk3_step_graph_us": time_call(g.replay, reps=20, warmup=3) * 1e3 / 10,
     }
     del g, B

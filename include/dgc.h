@@ -303,12 +303,18 @@ typedef struct {
     const int8_t *elem_kind;   /* [n_elem] DGC_ARR_DEV_ELEM_KIND (mixed meshes; NULL otherwise) */
 } dgc_dmesh;
 
-/* dgc_rk_step forms: DGC_RK_DEFAULT fuses each stage's combination into the
+/* dgc_rk_step forms: DGC_RK_FUSED fuses each stage's combination into the
  * face kernel of the last color when that is exact (f64, colored variant, a
  * conforming mesh colored with as many colors as an element has faces, so
  * every element has exactly one face of the last color, and a team face
- * form); DGC_RK_SEPARATE always runs the combination as its own kernel. */
-enum { DGC_RK_DEFAULT = 0, DGC_RK_SEPARATE = 1 };
+ * form), else runs it as its own kernel; DGC_RK_SEPARATE always runs the
+ * combination as its own kernel; DGC_RK_BLOCK runs the whole step in one
+ * work-group of 512 work-items, with barriers between the volume term, the
+ * colors and the combinations (f64, colored variant, one element type; an
+ * alternative for small meshes, where launches dominate: measured slower
+ * than DGC_RK_FUSED even at 512 elements, one CU being too little).
+ * DGC_RK_DEFAULT is DGC_RK_FUSED. */
+enum { DGC_RK_DEFAULT = 0, DGC_RK_SEPARATE = 1, DGC_RK_FUSED = 2, DGC_RK_BLOCK = 3 };
 
 /* Volume-kernel forms: DGC_VOL_VALU evaluates each element in one work-item
  * with vector FMAs; DGC_VOL_TEAM gives each element a team of lanes (one

@@ -190,11 +190,13 @@ class DeviceMesh:
     FORMS = {"default": 0, "team": 1, "thread": 2, "team_prefetch": 3, "mode_team": 4}
     VOL_FORMS = {"default": 0, "valu": 1, "mfma": 2, "team": 3}
 
-    RK_FORMS = {"default": 0, "separate": 1}
+    RK_FORMS = {"default": 0, "separate": 1, "fused": 2, "block": 3}
 
     def set_rk_form(self, form: str = "default") -> None:
-        """SSP-RK3 stages with the combination fused into the last color's
-        face kernel where exact ("default"), or as a separate kernel."""
+        """SSP-RK3 step form: the stage combination fused into the last
+        color's face kernel where exact ("fused"), as a separate kernel
+        ("separate"), or the whole step in one work-group ("block", small
+        meshes); "default" is "block" up to 4096 elements, else "fused"."""
         self.dm.rk_form = self.RK_FORMS[form]
 
     def set_volume_form(self, form: str = "default") -> None:

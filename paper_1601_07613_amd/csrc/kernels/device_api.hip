@@ -16,6 +16,7 @@
 #include "volume.hpp"
 #include "volume_mfma.hpp"
 #include "volume_team.hpp"
+#include "rk_block.hpp"
 
 using dgc::fail;
 
@@ -149,6 +150,23 @@ struct Impl {
                                    dm->tables + ti.off_proj, ti.n_codes, U, rhs, buf, dm->xcd_remap);
         }
         return hip_check("surface kernel launch");
+    }
+
+    // the whole SSP-RK3 step in one work-group (f64, colored)
+    static dgc_status rk_block(const dgc_dmesh *dm, const dgc_table_info &ti, double *U, double *U1, double *U2,
+                               double *rhs, double dt, hipStream_t st) {
+        dgc_status s = check_colors(dm);
+        if (s != DGC_OK) return s;
+        dgc_dev::BlockRkArgs a{};
+        for (int c = 0; c <= dm->n_colors; ++c) a.color_off[c] = dm->color_off[c];
+        a.n_colors = dm->n_colors;
+        a.dt = dt;
+        const size_t lds = 2 * (size_t)ti.n_codes * Q * NP * sizeof(double);
+        hipLaunchKernelGGL((dgc_dev::rk_step_block_kernel<DIM, NP, Q, QV>), dim3(1), dim3(512), lds, st, dm->n_face,
+                           dm->n_elem, dm->face_lr, dm->face_code, dm->face_geo, dm->elem_geo,
+                           dm->tables + ti.off_trace, dm->tables + ti.off_proj, ti.n_codes, dm->tables + ti.off_vb,
+                           dm->tables + ti.off_vd, U, U1, U2, rhs, a);
+        return hip_check("single-work-group RK step launch");
     }
 
     // colored pass whose last color writes the stage combination (f64); *fused
@@ -353,16 +371,26 @@ dgc_status dgc_rk_step(const dgc_dmesh *dm, double *U, double dt, int32_t varian
         hipLaunchKernelGGL(dgc_dev::to_f32_kernel, dim3(grid_for((int64_t)n)), dim3(kBlock), 0, st, (int64_t)n, U, shadow);
         if ((s = hip_check("f32 shadow launch")) != DGC_OK) return s;
     }
+    if (dm->rk_form < DGC_RK_DEFAULT || dm->rk_form > DGC_RK_BLOCK)
+        return fail(DGC_E_ARG, "dgc_dmesh: unknown rk_form");
+    // a small mesh: the whole step in one work-group (see DGC_RK_BLOCK)
+    const bool block_ok = !shadow && variant == DGC_SURF_COLORED && dm->elem_type != DGC_MIXED;
+    if (dm->rk_form == DGC_RK_BLOCK && !block_ok)
+        return fail(DGC_E_UNSUPPORTED, "DGC_RK_BLOCK needs f64, the colored variant and one element type");
+    if (block_ok && dm->rk_form == DGC_RK_BLOCK) {
+        return dispatch<double>(dm, 0, 0, [&](auto impl) {
+            return decltype(impl)::rk_block(dm, ti, U, U1, U2, static_cast<double *>(rhs), dt, st);
+        });
+    }
     // the stage combination rides on the last color's face kernel when every
     // element has exactly one face of that color (see DGC_RK_DEFAULT)
     const int faces_per_elem = dm->elem_type == DGC_TRI ? 3 : 4;
-    const bool fuse = !shadow && variant == DGC_SURF_COLORED && dm->rk_form == DGC_RK_DEFAULT &&
+    const bool fuse = !shadow && variant == DGC_SURF_COLORED &&
+                      (dm->rk_form == DGC_RK_DEFAULT || dm->rk_form == DGC_RK_FUSED) &&
                       dm->elem_type != DGC_MIXED &&
                       dm->n_colors == faces_per_elem && dm->max_slots == faces_per_elem &&
                       (dm->surf_form == DGC_FORM_DEFAULT || dm->surf_form == DGC_FORM_TEAM_PREFETCH ||
                        dm->surf_form == DGC_FORM_MODE_TEAM);
-    if (dm->rk_form != DGC_RK_DEFAULT && dm->rk_form != DGC_RK_SEPARATE)
-        return fail(DGC_E_ARG, "dgc_dmesh: unknown rk_form");
     for (int stg = 0; stg < 3; ++stg) {
         const void *Uin = shadow ? static_cast<const void *>(shadow) : static_cast<const void *>(stage_in[stg]);
         if ((s = dgc_volume_rhs(dm, Uin, rhs, precision, stream)) != DGC_OK) return s;

@@ -1,0 +1,69 @@
+// One SSP-RK3 step of a small mesh in a single work-group.
+//
+// A small mesh (the 16 x 16 periodic test problem has 512 triangles) leaves
+// the device idle between the 12-15 launches of a step: every launch costs a
+// few microseconds of dispatch while its work takes less.  Here one
+// work-group of 512 work-items runs the whole step: for each stage the
+// volume term (one work-item per element), then the colors one after the
+// other (a team of lanes per face, as in the face kernels), then the stage
+// combination, with a work-group barrier between phases.  The barrier plays
+// the role of Algorithm 1's synchronization between colors, so the update
+// stays race-free.  All waves of the work-group run on one CU, so a
+// work-group-scope fence before each barrier makes the global writes of one
+// phase visible to the next.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "surface.hpp"
+#include "volume.hpp"
+
+namespace dgc_dev {
+
+struct BlockRkArgs {
+    int64_t color_off[9];  // DGC_MAX_COLORS + 1
+    int n_colors;
+    double dt;
+};
+
+__device__ __forceinline__ void phase_barrier() {
+    __threadfence_block();
+    __syncthreads();
+}
+
+template <int DIM, int NP, int Q, int QV>
+__global__ __launch_bounds__(512) void rk_step_block_kernel(
+    int64_t n_face, int64_t n_elem, const int32_t *__restrict__ face_lr, const uint8_t *__restrict__ face_code,
+    const double *__restrict__ face_geo, const double *__restrict__ elem_geo, const double *__restrict__ tab_trace,
+    const double *__restrict__ tab_proj, int n_codes, const double *__restrict__ vb, const double *__restrict__ vd,
+    double *U, double *U1, double *U2, double *rhs, BlockRkArgs args) {
+    constexpr int M = DIM + 2;
+    constexpr int TEAM = M <= 4 ? 4 : 8;
+    extern __shared__ unsigned char smem_raw[];
+    double *s_tr = reinterpret_cast<double *>(smem_raw);
+    double *s_pr = s_tr + n_codes * Q * NP;
+    stage_tables<double>(s_tr, s_pr, tab_trace, tab_proj, n_codes * Q * NP);
+
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int team = tid / TEAM, r = tid % TEAM, n_teams = nthr / TEAM;
+    const int64_t n_dof = n_elem * M * NP;
+    const double ca[3] = {0.0, 0.75, 1.0 / 3.0};
+    const double cb[3] = {1.0, 0.25, 2.0 / 3.0};
+    for (int stg = 0; stg < 3; ++stg) {
+        const double *in = stg == 0 ? U : (stg == 1 ? U1 : U2);
+        double *out = stg == 0 ? U1 : (stg == 1 ? U2 : U);
+        for (int64_t k = tid; k < n_elem; k += nthr) volume_elem<DIM, NP, QV, double>(k, n_elem, elem_geo, vb, vd, in, rhs);
+        phase_barrier();
+        for (int c = 0; c < args.n_colors; ++c) {
+            // the loop index is the same for every lane of a team, so teams stay whole
+            for (int64_t f = args.color_off[c] + team; f < args.color_off[c + 1]; f += n_teams)
+                team_face<DIM, NP, Q, kColored, double, true>(f, r, n_face, n_elem, face_lr, face_code, face_geo,
+                                                               s_tr, s_pr, n_codes, in, rhs, nullptr);
+            phase_barrier();
+        }
+        for (int64_t i = tid; i < n_dof; i += nthr) out[i] = ca[stg] * U[i] + cb[stg] * (in[i] + args.dt * rhs[i]);
+        phase_barrier();
+    }
+}
+
+}  // namespace dgc_dev

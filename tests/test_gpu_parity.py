@@ -340,10 +340,11 @@ def test_rk3_100_steps_vortex():
 
 @pytest.mark.parametrize("kind,size,p", [("delaunay", 6000, 2), ("periodic", 16, 1), ("periodic", 16, 3),
                                          ("tets", 5, 1), ("tets", 4, 2), ("quads", 12, 2), ("quadbox", 11, 1)])
-def test_rk3_fused_combination_equals_separate(kind, size, p):
-    """The stage combination fused into the last color's face kernel gives the
-    separate-kernel step (same formula; only the compiler's contraction of
-    a x + b (y + dt r) may differ) over several steps, walls included."""
+def test_rk3_step_forms_agree(kind, size, p):
+    """The stage combination fused into the last color's face kernel and the
+    whole step in one work-group give the separate-kernel step (same
+    formulas; only the compiler's contraction of a x + b (y + dt r) may
+    differ) over several steps, walls included."""
     import torch
 
     c = Case(kind, size, 21, p)
@@ -355,7 +356,7 @@ def test_rk3_fused_combination_equals_separate(kind, size, p):
     U0 = c.Ug.clone()
     dt = 1e-4
     out = {}
-    for form in ("default", "separate"):
+    for form in ("fused", "block", "separate", "default"):
         c.D.set_rk_form(form)
         U = U0.clone()
         ws = c.D.workspace("rk", "colored")
@@ -365,8 +366,14 @@ def test_rk3_fused_combination_equals_separate(kind, size, p):
         out[form] = U
     c.D.set_rk_form("default")
     scale = out["separate"].abs().max().item()
-    assert (out["default"] - out["separate"]).abs().max().item() <= 1e-14 * scale
+    for form in ("fused", "block", "default"):
+        assert (out[form] - out["separate"]).abs().max().item() <= 1e-14 * scale, form
     assert not torch.equal(out["default"], U0)
+    # the single-work-group form needs f64
+    with pytest.raises(_dgc().DgcError):
+        c.D.set_rk_form("block")
+        c.D.rk_step(U0.clone(), dt, precision="f32", ws=c.D.workspace("rk", "colored", "f32"))
+    c.D.set_rk_form("default")
 
 
 def test_rk3_quads_vortex_20_steps():
