@@ -195,8 +195,8 @@ class DeviceMesh:
     def set_rk_form(self, form: str = "default") -> None:
         """SSP-RK3 step form: the stage combination fused into the last
         color's face kernel where exact ("fused"), as a separate kernel
-        ("separate"), or the whole step in one work-group ("block", small
-        meshes); "default" is "block" up to 4096 elements, else "fused"."""
+        ("separate"), or the whole step in one work-group ("block", an
+        alternative for small meshes, measured slower); "default" is "fused"."""
         self.dm.rk_form = self.RK_FORMS[form]
 
     def set_volume_form(self, form: str = "default") -> None:

@@ -8,7 +8,9 @@
 // other (a team of lanes per face, as in the face kernels), then the stage
 // combination, with a work-group barrier between phases.  The barrier plays
 // the role of Algorithm 1's synchronization between colors, so the update
-// stays race-free.  All waves of the work-group run on one CU, so a
+// stays race-free.  (Measured: 60 us per step at 512 triangles, p = 1,
+// against 43 us for the multi-launch fused step: one CU does all the work.)
+// All waves of the work-group run on one CU, so a
 // work-group-scope fence before each barrier makes the global writes of one
 // phase visible to the next.
 #pragma once
