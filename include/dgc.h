@@ -334,10 +334,13 @@ enum { DGC_VOL_DEFAULT = 0, DGC_VOL_VALU = 1, DGC_VOL_MFMA = 2, DGC_VOL_TEAM = 3
  * per conserved variable) so that loads of one element record are
  * contiguous across lanes; DGC_FORM_TEAM_PREFETCH is the same with the
  * right-hand-side reads of the colored update issued before the flux
- * evaluation (the default, except for tetrahedra at p = 1); DGC_FORM_THREAD
- * gives each face one work-item; DGC_FORM_MODE_TEAM (tetrahedra, p = 1, the
- * default there) gives each face 4 lanes, one per mode, and sums the traces
- * across them. */
+ * evaluation; DGC_FORM_THREAD gives each face one work-item;
+ * DGC_FORM_MODE_TEAM (tetrahedra, p = 1) gives each face 4 lanes, one per
+ * mode, and sums the traces across them.  DGC_FORM_DEFAULT picks the form
+ * measured fastest for the element type and order: the team with prefetch,
+ * the team without it for triangles at p = 4 and parallelograms (and mixed
+ * meshes) at p = 1, 3, the mode team for tetrahedra at p = 1 and one
+ * work-item per face for tetrahedra at p = 2. */
 enum { DGC_FORM_DEFAULT = 0, DGC_FORM_TEAM = 1, DGC_FORM_THREAD = 2, DGC_FORM_TEAM_PREFETCH = 3,
        DGC_FORM_MODE_TEAM = 4 };
 

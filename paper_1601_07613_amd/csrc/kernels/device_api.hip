@@ -24,6 +24,23 @@ namespace {
 
 constexpr int kBlock = 256;
 
+// DGC_FORM_DEFAULT: the face-kernel form measured fastest for each element
+// type and order (f64 colored pass, ~1M elements): the team with
+// right-hand-side prefetch, except where its registers cost more than the
+// prefetch gains (triangles p = 4, parallelograms p = 1 and 3: the team
+// without prefetch), the mode team for tetrahedra at p = 1, and one
+// work-item per face for tetrahedra at p = 2 (8-lane teams of 10 modes)
+int default_surface_form(int elem_type, int p) {
+    if (elem_type == DGC_TET) return p == 1 ? DGC_FORM_MODE_TEAM : (p == 2 ? DGC_FORM_THREAD : DGC_FORM_TEAM_PREFETCH);
+    if (elem_type == DGC_QUAD || elem_type == DGC_MIXED)
+        return (p == 1 || p == 3) ? DGC_FORM_TEAM : DGC_FORM_TEAM_PREFETCH;
+    return p == 4 ? DGC_FORM_TEAM : DGC_FORM_TEAM_PREFETCH;
+}
+
+int resolved_surface_form(const dgc_dmesh *dm) {
+    return dm->surf_form == DGC_FORM_DEFAULT ? default_surface_form(dm->elem_type, dm->p) : dm->surf_form;
+}
+
 // DGC_VOL_DEFAULT: the volume form measured fastest for each element type and
 // order (f64, ~1M elements; mixed meshes always use their own team kernel)
 int default_volume_form(int elem_type, int p) {
@@ -120,9 +137,10 @@ struct Impl {
         if (f1 <= f0) return DGC_OK;
         const size_t lds = 2 * (size_t)ti.n_codes * Q * NP * sizeof(T);
         const int block = dm->block_size ? dm->block_size : kBlock;
+        const int form = resolved_surface_form(dm);
         if constexpr (NP == 4 && DIM == 3) {
-            // tetrahedra at p = 1: the mode team (4 lanes, lane = mode) unless another form is asked for
-            if (dm->surf_form == DGC_FORM_DEFAULT || dm->surf_form == DGC_FORM_MODE_TEAM) {
+            // tetrahedra at p = 1: the mode team (4 lanes, lane = mode)
+            if (form == DGC_FORM_MODE_TEAM) {
                 hipLaunchKernelGGL((dgc_dev::surface_mode_team_kernel<DIM, NP, Q, MODE, T>),
                                    dim3(grid_for((f1 - f0) * 4, block)), dim3(block), lds, st, f0, f1, dm->n_face,
                                    dm->n_elem, dm->face_lr, dm->face_code, dm->face_geo, dm->tables + ti.off_trace,
@@ -130,15 +148,15 @@ struct Impl {
                 return hip_check("surface kernel launch");
             }
         }
-        if (dm->surf_form == DGC_FORM_MODE_TEAM) return fail(DGC_E_UNSUPPORTED, "mode teams need N_p = 4 in 3D");
-        if (dm->surf_form == DGC_FORM_THREAD) {
+        if (form == DGC_FORM_MODE_TEAM) return fail(DGC_E_UNSUPPORTED, "mode teams need N_p = 4 in 3D");
+        if (form == DGC_FORM_THREAD) {
             hipLaunchKernelGGL((dgc_dev::surface_kernel<DIM, NP, Q, MODE, T>), dim3(grid_for(f1 - f0, block)),
                                dim3(block), lds, st, f0, f1, dm->n_face, dm->n_elem, dm->face_lr, dm->face_code,
                                dm->face_geo, dm->tables + ti.off_trace, dm->tables + ti.off_proj, ti.n_codes, U, rhs,
                                buf, dm->xcd_remap);
         } else {
             constexpr int TEAM = DIM + 2 <= 4 ? 4 : 8;
-            if (dm->surf_form == DGC_FORM_TEAM_PREFETCH || dm->surf_form == DGC_FORM_DEFAULT)
+            if (form == DGC_FORM_TEAM_PREFETCH)
                 hipLaunchKernelGGL((dgc_dev::surface_team_kernel<DIM, NP, Q, MODE, T, true>),
                                    dim3(grid_for((f1 - f0) * TEAM, block)), dim3(block), lds, st, f0, f1, dm->n_face,
                                    dm->n_elem, dm->face_lr, dm->face_code, dm->face_geo, dm->tables + ti.off_trace,
@@ -188,7 +206,7 @@ struct Impl {
             const size_t lds = 2 * (size_t)ti.n_codes * Q * NP * sizeof(double);
             const int block = dm->block_size ? dm->block_size : kBlock;
             constexpr bool kMT = DIM == 3 && NP == 4;
-            if (kMT && dm->surf_form != DGC_FORM_TEAM_PREFETCH) {
+            if (kMT && resolved_surface_form(dm) == DGC_FORM_MODE_TEAM) {
                 hipLaunchKernelGGL((dgc_dev::surface_combine_kernel<DIM, NP, Q, kMT>),
                                    dim3(grid_for((f1 - f0) * 4, block)), dim3(block), lds, st, f0, f1, dm->n_face,
                                    dm->n_elem, dm->face_lr, dm->face_code, dm->face_geo, dm->tables + ti.off_trace,
@@ -389,8 +407,7 @@ dgc_status dgc_rk_step(const dgc_dmesh *dm, double *U, double dt, int32_t varian
                       (dm->rk_form == DGC_RK_DEFAULT || dm->rk_form == DGC_RK_FUSED) &&
                       dm->elem_type != DGC_MIXED &&
                       dm->n_colors == faces_per_elem && dm->max_slots == faces_per_elem &&
-                      (dm->surf_form == DGC_FORM_DEFAULT || dm->surf_form == DGC_FORM_TEAM_PREFETCH ||
-                       dm->surf_form == DGC_FORM_MODE_TEAM);
+                      resolved_surface_form(dm) != DGC_FORM_THREAD;
     for (int stg = 0; stg < 3; ++stg) {
         const void *Uin = shadow ? static_cast<const void *>(shadow) : static_cast<const void *>(stage_in[stg]);
         if ((s = dgc_volume_rhs(dm, Uin, rhs, precision, stream)) != DGC_OK) return s;
