@@ -32,7 +32,7 @@ PROFILES = {
     "tets": os.path.join(ROOT, "profiles", "surface_colored_mode_team_kuhn64_tets_p1_f64.md"),
 }
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1601_07613_amd", "csrc", "kernels", f)
-                  for f in ("surface.hpp", "euler_dev.hpp")]
+                  for f in ("surface.hpp", "euler_dev.hpp", "team.hpp")]
 
 
 def profiled_traffic(args, launch):
@@ -123,7 +123,7 @@ def extra_workloads(dgc, synth, torch, steps, warmup, log):
     B = dgc.Batch([(D, U, ws, 1e-9)])
     g = B.capture(steps=10)
     forms = {}
-    for rf in ("block", "fused", "separate"):
+    for rf in ("block", "fused", "fused_volume", "separate"):
         D.set_rk_form(rf)
         forms[rf] = time_call(lambda: D.rk_step(U, 1e-9, ws=ws), reps=100, warmup=10) * 1e3
     D.set_rk_form("default")
@@ -166,10 +166,18 @@ def extra_workloads(dgc, synth, torch, steps, warmup, log):
     diff = ((Ub - Ua) ** 2).sum(dim=(0, 2)).sqrt() / (Ua ** 2).sum(dim=(0, 2)).sqrt()
     rk64 = time_call(lambda: DT.rk_step(Ua, dt, precision="f64", ws=wa), reps=5, warmup=1)
     rk32 = time_call(lambda: DT.rk_step(Ub, dt, precision="f32", ws=wb), reps=5, warmup=1)
+    rk_forms = {}
+    for rf in ("fused_volume", "fused", "separate"):
+        DT.set_rk_form(rf)
+        rk_forms["f64_" + rf] = time_call(lambda: DT.rk_step(Ua, dt, precision="f64", ws=wa), reps=5, warmup=1) * 1e3
+        rk_forms["f32_form_" + rf] = time_call(lambda: DT.rk_step(Ub, dt, precision="f32", ws=wb), reps=5,
+                                               warmup=1) * 1e3
+    DT.set_rk_form("default")
     out["c2_kuhn64_tets_p1"] = {
         "n_elem": info["n_elem"], "n_face": info["n_face"], "n_colors": info["n_colors"],
         "color_ms": cs["color_ms"], "f64": r64, "f32": r32, "f64_thread_form": r64t, "f64_variable_team_form": r64v,
         "rk3_step_us": {"f64": rk64 * 1e3, "f32_form": rk32 * 1e3},
+        "rk3_step_by_form_us": rk_forms,
         "f32_form_rel_L2_after_10_steps": [float(x) for x in diff.cpu()],
     }
     log("c2: %s" % out["c2_kuhn64_tets_p1"])
@@ -192,6 +200,12 @@ def extra_workloads(dgc, synth, torch, steps, warmup, log):
         "color_ms": qs["color_ms"], "conflicts_after_greedy": qs["conflicts_after_greedy"], "f64": rq, "f32": rq32,
         "rk3_step_us": time_call(lambda: DQ.rk_step(Uq, 1e-7, ws=wq), reps=5, warmup=1) * 1e3,
     }
+    rk_forms = {}
+    for rf in ("fused_volume", "fused"):
+        DQ.set_rk_form(rf)
+        rk_forms[rf] = time_call(lambda: DQ.rk_step(Uq, 1e-7, ws=wq), reps=5, warmup=1) * 1e3
+    DQ.set_rk_form("default")
+    out["quads_1024sq_p2"]["rk3_step_by_form_us"] = rk_forms
     log("quads: %s" % out["quads_1024sq_p2"])
     del DQ, Qm, Uq, wq
 
@@ -445,7 +459,20 @@ def main(argv=None):
         D.set_rk_form("separate")
         extra["rk3_step_separate_combine_us"] = timed(lambda: D.rk_step(Ur, 1e-7, ws=wsr), max(args.steps // 5, 3), 2,
                                                       stream)[0] * 1e3
+        D.set_rk_form("fused")
+        extra["rk3_step_fused_combine_us"] = timed(lambda: D.rk_step(Ur, 1e-7, ws=wsr), max(args.steps // 5, 3), 2,
+                                                   stream)[0] * 1e3
+        D.set_rk_form("fused_volume")
+        extra["rk3_step_fused_volume_us"] = timed(lambda: D.rk_step(Ur, 1e-7, ws=wsr), max(args.steps // 5, 3), 2,
+                                                  stream)[0] * 1e3
         D.set_rk_form("default")
+        wsr32 = D.workspace("rk", "colored", "f32")
+        for rf in ("separate", "fused_volume"):
+            D.set_rk_form(rf)
+            extra["rk3_step_f32_form_%s_us" % rf] = timed(lambda: D.rk_step(Ur, 1e-7, precision="f32", ws=wsr32),
+                                                          max(args.steps // 5, 3), 2, stream)[0] * 1e3
+        D.set_rk_form("default")
+        del wsr32
         D.set_launch("thread", 256)
         extra["colored_thread_form_us"] = timed(lambda: D.surface_rhs(Ug, rhs, "colored"), args.steps, args.warmup,
                                                 stream)[0] * 1e3

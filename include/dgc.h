@@ -313,21 +313,36 @@ typedef struct {
  * colors and the combinations (f64, colored variant, one element type; an
  * alternative for small meshes, where launches dominate: measured slower
  * than DGC_RK_FUSED even at 512 elements, one CU being too little).
- * DGC_RK_DEFAULT is DGC_RK_FUSED. */
-enum { DGC_RK_DEFAULT = 0, DGC_RK_SEPARATE = 1, DGC_RK_FUSED = 2, DGC_RK_BLOCK = 3 };
+ * DGC_RK_FUSED_VOLUME also moves each stage's volume term into the face
+ * kernel of the first color under the same conditions (every element has
+ * exactly one face of the first color; f64 and the f32 form; the element
+ * records read for the traces feed the volume term too, and the first color
+ * writes rhs without reading it): one launch and three record passes fewer
+ * per stage; the volume term is then computed by the face team (lane =
+ * variable, or lane = mode for tetrahedra at p = 1) whatever vol_form says.
+ * Where its conditions fail it falls back to DGC_RK_FUSED.
+ * DGC_RK_DEFAULT is DGC_RK_FUSED_VOLUME for triangles at p <= 3 and for
+ * quadrilaterals when vol_form is DGC_VOL_DEFAULT (measured 4-18 % faster
+ * per step on ~1M elements), and DGC_RK_FUSED otherwise (triangles at
+ * p = 4, 5: the face kernel's registers run out; tetrahedra: no gain, the
+ * face team evaluates the flux of the volume term on each of its four
+ * lanes). */
+enum { DGC_RK_DEFAULT = 0, DGC_RK_SEPARATE = 1, DGC_RK_FUSED = 2, DGC_RK_BLOCK = 3, DGC_RK_FUSED_VOLUME = 4 };
 
 /* Volume-kernel forms: DGC_VOL_VALU evaluates each element in one work-item
  * with vector FMAs; DGC_VOL_TEAM gives each element a team of lanes (one
  * per conserved variable, the element record read as one contiguous
- * stretch) that exchange the point values; DGC_VOL_MFMA (triangles, f64,
- * p <= 3; other cases fall back to DGC_VOL_VALU) runs the two basis
- * contractions of four elements at a time on the matrix cores
- * (v_mfma_f64_16x16x4f64) and the flux between them on the vector units.
- * DGC_VOL_DEFAULT picks the form measured fastest for the element type and
- * order: the matrix-core form for quadrilaterals at p >= 2 (f64; the team
- * form in f32), one work-item per element for triangles at p = 3, 4 and for
- * tetrahedra, the team form otherwise; mixed meshes always use their own
- * team kernel. */
+ * stretch) that exchange the point values; DGC_VOL_MFMA (2D, f64, at most 16
+ * modes and 16 points: triangles p <= 3, quadrilaterals p <= 3; other cases
+ * fall back to DGC_VOL_VALU) runs the two basis contractions of four
+ * elements at a time on the matrix cores (v_mfma_f64_16x16x4f64) and the
+ * flux between them on the vector units.  DGC_VOL_DEFAULT picks the form
+ * measured fastest for the element type, order and precision: in f64 the
+ * team form (one work-item per element for triangles at p = 3), in f32 one
+ * work-item per element (the team form for quadrilaterals at p <= 2), one
+ * work-item per element for tetrahedra; mixed meshes always use their own
+ * team kernel.  The matrix-core form is an explicit choice only: slower
+ * than the vector forms at every order measured. */
 enum { DGC_VOL_DEFAULT = 0, DGC_VOL_VALU = 1, DGC_VOL_MFMA = 2, DGC_VOL_TEAM = 3 };
 
 /* Face-kernel forms: DGC_FORM_TEAM gives each face a team of lanes (one lane

@@ -190,19 +190,23 @@ class DeviceMesh:
     FORMS = {"default": 0, "team": 1, "thread": 2, "team_prefetch": 3, "mode_team": 4}
     VOL_FORMS = {"default": 0, "valu": 1, "mfma": 2, "team": 3}
 
-    RK_FORMS = {"default": 0, "separate": 1, "fused": 2, "block": 3}
+    RK_FORMS = {"default": 0, "separate": 1, "fused": 2, "block": 3, "fused_volume": 4}
 
     def set_rk_form(self, form: str = "default") -> None:
         """SSP-RK3 step form: the stage combination fused into the last
-        color's face kernel where exact ("fused"), as a separate kernel
-        ("separate"), or the whole step in one work-group ("block", an
-        alternative for small meshes, measured slower); "default" is "fused"."""
+        color's face kernel where exact ("fused"); in addition the volume term
+        fused into the first color's face kernel ("fused_volume"); the
+        combination as a separate kernel ("separate"); or the whole step in
+        one work-group ("block", an alternative for small meshes, measured
+        slower).  "default" is "fused_volume" for triangles at p <= 3 and
+        quadrilaterals (with the default volume form), else "fused"."""
         self.dm.rk_form = self.RK_FORMS[form]
 
     def set_volume_form(self, form: str = "default") -> None:
         """Volume-kernel form: one work-item per element ("valu"), a team of
-        lanes per element ("team", the default), or the two basis
-        contractions on the matrix cores ("mfma": triangles, f64, p <= 3)."""
+        lanes per element ("team"), or the two basis contractions on the
+        matrix cores ("mfma": 2D, f64, p <= 3); "default" picks the form
+        measured fastest for the element type, order and precision."""
         self.dm.vol_form = self.VOL_FORMS[form]
 
     def set_launch(self, form: str = "default", block: int = 0, xcd_remap: bool = False) -> None:

@@ -76,7 +76,7 @@ __global__ __launch_bounds__(256) void batch_volume_kernel(const char *__restric
     const int32_t m = reinterpret_cast<const int32_t *>(desc + h->off_map_elem)[blockIdx.x];
     const Entry *e = bentry(desc, m);
     // a team of lanes per element or one work-item per element (batch_volume_lanes)
-    constexpr int LANES = batch_volume_lanes(DIM, NP);
+    constexpr int LANES = batch_volume_lanes(DIM, NP, sizeof(T) == 4);
     const int64_t k = (((int64_t)blockIdx.x - e->blk_elem) * blockDim.x + threadIdx.x) / LANES;
     if (k >= e->n_elem) return;  // whole teams leave together
     const dgc_batch::RkWs w = dgc_batch::rk_ws(e->ws, (size_t)e->n_dof, sizeof(T) == 4);

@@ -41,14 +41,23 @@ int resolved_surface_form(const dgc_dmesh *dm) {
     return dm->surf_form == DGC_FORM_DEFAULT ? default_surface_form(dm->elem_type, dm->p) : dm->surf_form;
 }
 
-// DGC_VOL_DEFAULT: the volume form measured fastest for each element type and
-// order (f64, ~1M elements; mixed meshes always use their own team kernel)
-int default_volume_form(int elem_type, int p) {
-    if (elem_type == DGC_QUAD) return p >= 2 ? DGC_VOL_MFMA : DGC_VOL_TEAM;
-    if (elem_type == DGC_TRI) return (p == 3 || p == 4) ? DGC_VOL_VALU : DGC_VOL_TEAM;
-    // tetrahedra: the 8-lane team (5 variables) is 2-9x slower than one work-item per element
-    return DGC_VOL_VALU;
+// DGC_VOL_DEFAULT: the volume form measured fastest for each element type,
+// order and precision (~1M elements; mixed meshes always use their own team
+// kernel): in f64 the team (one work-item per element for triangles at
+// p = 3), in f32 one work-item per element (the team for quadrilaterals at
+// p <= 2), and one work-item per element for tetrahedra, where the 8-lane
+// team (5 variables) is 2-9x slower.  The matrix-core form is slower at
+// every order measured (its 16 x 16 x 4 tiles are mostly padding).
+int default_volume_form(int elem_type, int p, bool f32) {
+    if (elem_type == DGC_TET) return DGC_VOL_VALU;
+    if (f32) return (elem_type == DGC_QUAD && p <= 2) ? DGC_VOL_TEAM : DGC_VOL_VALU;
+    return (elem_type == DGC_TRI && p == 3) ? DGC_VOL_VALU : DGC_VOL_TEAM;
 }
+
+// DGC_RK_DEFAULT fuses the volume term into the first color's face kernel
+// where the face team carries it without slowing the pass down (measured on
+// ~1M-element meshes)
+bool default_fuse_volume(int elem_type, int p) { return (elem_type == DGC_TRI && p <= 3) || elem_type == DGC_QUAD; }
 
 inline unsigned grid_for(int64_t n, int block = kBlock) { return (unsigned)((n + block - 1) / block); }
 
@@ -108,7 +117,8 @@ struct Impl {
                 return hip_check("volume kernel launch");
             }
         }
-        const int vf = dm->vol_form == DGC_VOL_DEFAULT ? default_volume_form(dm->elem_type, dm->p) : dm->vol_form;
+        const int vf = dm->vol_form == DGC_VOL_DEFAULT ? default_volume_form(dm->elem_type, dm->p, sizeof(T) == 4)
+                                                       : dm->vol_form;
         if constexpr (DIM == 2 && std::is_same_v<T, double> && NP <= 16 && QV <= 16) {
             if (vf == DGC_VOL_MFMA) {
                 const int64_t groups = (dm->n_elem + 15) / 16;
@@ -118,8 +128,7 @@ struct Impl {
                 return hip_check("volume kernel launch");
             }
         }
-        // the team form, also where the default's matrix-core form does not apply (f32)
-        if (vf == DGC_VOL_TEAM || (dm->vol_form == DGC_VOL_DEFAULT && vf == DGC_VOL_MFMA)) {
+        if (vf == DGC_VOL_TEAM) {
             constexpr int TEAM = DIM + 2 <= 4 ? 4 : 8;
             hipLaunchKernelGGL((dgc_dev::volume_team_kernel<DIM, NP, QV, T>), dim3(grid_for(dm->n_elem * TEAM)),
                                dim3(kBlock), 0, st, dm->n_elem, dm->elem_geo, dm->tables + ti.off_vb,
@@ -187,10 +196,47 @@ struct Impl {
         return hip_check("single-work-group RK step launch");
     }
 
+    // first color of a stage with the volume term fused in: rhs = volume +
+    // first-color surface term, for every element (see DGC_RK_FUSED_VOLUME)
+    static dgc_status faces_volume(const dgc_dmesh *dm, const dgc_table_info &ti, int64_t f0, int64_t f1, const T *U,
+                                   T *rhs, hipStream_t st) {
+        const int block = dm->block_size ? dm->block_size : kBlock;
+        const int form = resolved_surface_form(dm);
+        const dgc_dev::VolArgs va{dm->elem_geo, dm->tables + ti.off_vb, dm->tables + ti.off_vd};
+        const size_t lds = 2 * (size_t)ti.n_codes * Q * NP * sizeof(T);
+        if constexpr (NP == 4 && DIM == 3) {
+            if (form == DGC_FORM_MODE_TEAM) {
+                const size_t lds_v = lds + (size_t)(1 + DIM) * QV * NP * sizeof(T);
+                hipLaunchKernelGGL((dgc_dev::surface_volume_kernel<DIM, NP, Q, QV, true, T>),
+                                   dim3(grid_for((f1 - f0) * 4, block)), dim3(block), lds_v, st, f0, f1, dm->n_face,
+                                   dm->n_elem, dm->face_lr, dm->face_code, dm->face_geo, dm->tables + ti.off_trace,
+                                   dm->tables + ti.off_proj, ti.n_codes, U, rhs, va, dm->xcd_remap);
+                return hip_check("fused volume and surface kernel launch");
+            }
+        }
+        if (form != DGC_FORM_TEAM && form != DGC_FORM_TEAM_PREFETCH)
+            return fail(DGC_E_UNSUPPORTED, "the fused volume term needs a team face form");
+        constexpr int TEAM = DIM + 2 <= 4 ? 4 : 8;
+        hipLaunchKernelGGL((dgc_dev::surface_volume_kernel<DIM, NP, Q, QV, false, T>),
+                           dim3(grid_for((f1 - f0) * TEAM, block)), dim3(block), lds, st, f0, f1, dm->n_face,
+                           dm->n_elem, dm->face_lr, dm->face_code, dm->face_geo, dm->tables + ti.off_trace,
+                           dm->tables + ti.off_proj, ti.n_codes, U, rhs, va, dm->xcd_remap);
+        return hip_check("fused volume and surface kernel launch");
+    }
+
+    // colors [c0, c1) of a colored pass
+    static dgc_status colors(const dgc_dmesh *dm, const dgc_table_info &ti, int c0, int c1, const T *U, T *rhs,
+                             hipStream_t st) {
+        dgc_status s = DGC_OK;
+        for (int c = c0; c < c1 && s == DGC_OK; ++c)
+            s = faces<dgc_dev::kColored>(dm, ti, dm->color_off[c], dm->color_off[c + 1], U, rhs, nullptr, st);
+        return s;
+    }
+
     // colored pass whose last color writes the stage combination (f64); *fused
     // is false (and nothing is launched) when the last color is empty
     static dgc_status surface_fused(const dgc_dmesh *dm, const dgc_table_info &ti, const T *U, T *rhs,
-                                    const dgc_dev::CombineArgs &cmb, bool *fused, hipStream_t st) {
+                                    const dgc_dev::CombineArgs &cmb, int first_color, bool *fused, hipStream_t st) {
         *fused = false;
         if constexpr (!std::is_same_v<T, double>) {
             return fail(DGC_E_ARG, "fused stage combination is f64 only");
@@ -199,10 +245,8 @@ struct Impl {
             if (s != DGC_OK) return s;
             const int nc = dm->n_colors;
             const int64_t f0 = dm->color_off[nc - 1], f1 = dm->color_off[nc];
-            if (f1 <= f0) return DGC_OK;
-            for (int c = 0; c < nc - 1 && s == DGC_OK; ++c)
-                s = faces<dgc_dev::kColored>(dm, ti, dm->color_off[c], dm->color_off[c + 1], U, rhs, nullptr, st);
-            if (s != DGC_OK) return s;
+            if (f1 <= f0 || first_color > nc - 1) return DGC_OK;
+            if ((s = colors(dm, ti, first_color, nc - 1, U, rhs, st)) != DGC_OK) return s;
             const size_t lds = 2 * (size_t)ti.n_codes * Q * NP * sizeof(double);
             const int block = dm->block_size ? dm->block_size : kBlock;
             constexpr bool kMT = DIM == 3 && NP == 4;
@@ -389,7 +433,7 @@ dgc_status dgc_rk_step(const dgc_dmesh *dm, double *U, double dt, int32_t varian
         hipLaunchKernelGGL(dgc_dev::to_f32_kernel, dim3(grid_for((int64_t)n)), dim3(kBlock), 0, st, (int64_t)n, U, shadow);
         if ((s = hip_check("f32 shadow launch")) != DGC_OK) return s;
     }
-    if (dm->rk_form < DGC_RK_DEFAULT || dm->rk_form > DGC_RK_BLOCK)
+    if (dm->rk_form < DGC_RK_DEFAULT || dm->rk_form > DGC_RK_FUSED_VOLUME)
         return fail(DGC_E_ARG, "dgc_dmesh: unknown rk_form");
     // a small mesh: the whole step in one work-group (see DGC_RK_BLOCK)
     const bool block_ok = !shadow && variant == DGC_SURF_COLORED && dm->elem_type != DGC_MIXED;
@@ -400,28 +444,63 @@ dgc_status dgc_rk_step(const dgc_dmesh *dm, double *U, double dt, int32_t varian
             return decltype(impl)::rk_block(dm, ti, U, U1, U2, static_cast<double *>(rhs), dt, st);
         });
     }
-    // the stage combination rides on the last color's face kernel when every
-    // element has exactly one face of that color (see DGC_RK_DEFAULT)
+    // the stage combination rides on the last color's face kernel, and the
+    // volume term on the first color's, when every element has exactly one
+    // face of each color (see DGC_RK_FUSED and DGC_RK_FUSED_VOLUME)
+    if (variant == DGC_SURF_COLORED && (s = check_colors(dm)) != DGC_OK) return s;
     const int faces_per_elem = dm->elem_type == DGC_TRI ? 3 : 4;
-    const bool fuse = !shadow && variant == DGC_SURF_COLORED &&
-                      (dm->rk_form == DGC_RK_DEFAULT || dm->rk_form == DGC_RK_FUSED) &&
-                      dm->elem_type != DGC_MIXED &&
-                      dm->n_colors == faces_per_elem && dm->max_slots == faces_per_elem &&
-                      resolved_surface_form(dm) != DGC_FORM_THREAD;
+    const int sform = resolved_surface_form(dm);
+    const bool one_face_per_color = variant == DGC_SURF_COLORED && dm->elem_type != DGC_MIXED &&
+                                    dm->n_colors == faces_per_elem && dm->max_slots == faces_per_elem &&
+                                    sform != DGC_FORM_THREAD && dm->color_off[1] > dm->color_off[0];
+    const bool fuse = !shadow && one_face_per_color && dm->rk_form != DGC_RK_SEPARATE;
+    const bool vol_team_face = sform == DGC_FORM_TEAM || sform == DGC_FORM_TEAM_PREFETCH ||
+                               (sform == DGC_FORM_MODE_TEAM && dm->elem_type == DGC_TET && dm->p == 1);
+    const bool fuse_vol = one_face_per_color && vol_team_face &&
+                          (dm->rk_form == DGC_RK_FUSED_VOLUME ||
+                           (dm->rk_form == DGC_RK_DEFAULT && dm->vol_form == DGC_VOL_DEFAULT &&
+                            default_fuse_volume(dm->elem_type, dm->p)));
+    const int first = fuse_vol ? 1 : 0;
     for (int stg = 0; stg < 3; ++stg) {
         const void *Uin = shadow ? static_cast<const void *>(shadow) : static_cast<const void *>(stage_in[stg]);
-        if ((s = dgc_volume_rhs(dm, Uin, rhs, precision, stream)) != DGC_OK) return s;
+        if (fuse_vol) {
+            const int64_t f0 = dm->color_off[0], f1 = dm->color_off[1];
+            if (shadow)
+                s = dispatch<float>(dm, 0, 0, [&](auto impl) {
+                    return decltype(impl)::faces_volume(dm, ti, f0, f1, shadow, static_cast<float *>(rhs), st);
+                });
+            else
+                s = dispatch<double>(dm, 0, 0, [&](auto impl) {
+                    return decltype(impl)::faces_volume(dm, ti, f0, f1, stage_in[stg], static_cast<double *>(rhs),
+                                                        st);
+                });
+        } else {
+            s = dgc_volume_rhs(dm, Uin, rhs, precision, stream);
+        }
+        if (s != DGC_OK) return s;
         if (fuse) {
             const dgc_dev::CombineArgs cmb{stg == 0 ? nullptr : U, stage_out[stg], a[stg], b[stg], dt};
             bool fused = false;
             s = dispatch<double>(dm, 0, 0, [&](auto impl) {
-                return decltype(impl)::surface_fused(dm, ti, stage_in[stg], static_cast<double *>(rhs), cmb, &fused,
-                                                     st);
+                return decltype(impl)::surface_fused(dm, ti, stage_in[stg], static_cast<double *>(rhs), cmb, first,
+                                                     &fused, st);
             });
             if (s != DGC_OK) return s;
             if (fused) continue;
         }
-        if ((s = dgc_surface_rhs(dm, Uin, rhs, variant, precision, sws, sws_bytes, stream)) != DGC_OK) return s;
+        if (first == 0) {
+            s = dgc_surface_rhs(dm, Uin, rhs, variant, precision, sws, sws_bytes, stream);
+        } else if (shadow) {
+            s = dispatch<float>(dm, 0, 0, [&](auto impl) {
+                return decltype(impl)::colors(dm, ti, first, dm->n_colors, shadow, static_cast<float *>(rhs), st);
+            });
+        } else {
+            s = dispatch<double>(dm, 0, 0, [&](auto impl) {
+                return decltype(impl)::colors(dm, ti, first, dm->n_colors, stage_in[stg], static_cast<double *>(rhs),
+                                              st);
+            });
+        }
+        if (s != DGC_OK) return s;
         if (shadow) {
             hipLaunchKernelGGL(dgc_dev::rk_combine_f32_kernel, dim3(grid_for((int64_t)n)), dim3(kBlock), 0, st,
                                (int64_t)n, a[stg], b[stg], dt, x_in[stg], stage_in[stg], static_cast<const float *>(rhs),
@@ -558,7 +637,7 @@ dgc_status dgc_batch_describe(int32_t n_mesh, const dgc_dmesh *meshes, double *c
     const int team = (ti.dim == 3 && ti.n_p == 4) ? 4 : (ti.dim + 2 <= 4 ? 4 : 8);
     const int fpb = kBlock / team;
     // lanes per element of batch_volume_kernel
-    const int vteam = dgc_dev::batch_volume_lanes(ti.dim, ti.n_p);
+    const int vteam = dgc_dev::batch_volume_lanes(ti.dim, ti.n_p, precision == DGC_F32);
     int nc = 0;
     for (int32_t i = 0; i < n_mesh; ++i) nc = meshes[i].n_colors > nc ? meshes[i].n_colors : nc;
     // work-group counts

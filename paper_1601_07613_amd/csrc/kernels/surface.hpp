@@ -22,10 +22,23 @@
 #include <hip/hip_runtime.h>
 
 #include "euler_dev.hpp"
+#include "team.hpp"
+#include "volume_team.hpp"
 
 namespace dgc_dev {
 
-enum { kColored = 0, kAtomic = 1, kGather = 2, kCombine = 3 };
+enum { kColored = 0, kAtomic = 1, kGather = 2, kCombine = 3, kVolume = 4 };
+
+// First color of a stage with the volume term fused in: on a conforming
+// mesh every element has exactly one face of every color, so the first
+// color's face lanes, which read the element records for the traces anyway,
+// also evaluate the volume term of both elements (Eq. (2), first term) and
+// write rhs = volume - delta_L (+ delta_R) without reading rhs.  The tables
+// are the volume tables of the element type (vb[q][j], vd[d][q][j]).
+struct VolArgs {
+    const double *elem_geo;
+    const double *vb, *vd;
+};
 
 // Last color of a colored pass with the SSP-RK3 stage combination fused in:
 // on a conforming mesh every element has exactly one face of every color, so
@@ -181,35 +194,6 @@ __global__ __launch_bounds__(256) void surface_kernel(
     }
 }
 
-// Value of lane k of the caller's team (TEAM consecutive lanes).  Teams of
-// four use a DPP quad broadcast (a register move, no LDS traffic); wider
-// teams use ds_bpermute through __shfl.
-template <int TEAM>
-__device__ __forceinline__ int team_bcast_i(int v, int k) {
-    if constexpr (TEAM == 4) {
-        switch (k) {
-            case 0: return __builtin_amdgcn_mov_dpp(v, 0x00, 0xF, 0xF, false);
-            case 1: return __builtin_amdgcn_mov_dpp(v, 0x55, 0xF, 0xF, false);
-            case 2: return __builtin_amdgcn_mov_dpp(v, 0xAA, 0xF, 0xF, false);
-            default: return __builtin_amdgcn_mov_dpp(v, 0xFF, 0xF, 0xF, false);
-        }
-    } else {
-        return __shfl(v, k, TEAM);
-    }
-}
-
-template <int TEAM>
-__device__ __forceinline__ double team_bcast(double v, int k) {
-    const int lo = team_bcast_i<TEAM>(__double2loint(v), k);
-    const int hi = team_bcast_i<TEAM>(__double2hiint(v), k);
-    return __hiloint2double(hi, lo);
-}
-
-template <int TEAM>
-__device__ __forceinline__ float team_bcast(float v, int k) {
-    return __int_as_float(team_bcast_i<TEAM>(__float_as_int(v), k));
-}
-
 // Team form of the face work: TEAM lanes per face (4 for M = 4, 8 for
 // M = 5); lane r < M owns conserved variable r.  Each lane reads and
 // updates the NP modes of its variable, so one load instruction of a team
@@ -218,12 +202,13 @@ __device__ __forceinline__ float team_bcast(float v, int k) {
 // team and every lane evaluates the flux of the full state; lane r then
 // projects component r.  Same arithmetic and accumulation modes as
 // surface_kernel.
-template <int DIM, int NP, int Q, int MODE, class T, bool PREFETCH>
+template <int DIM, int NP, int Q, int MODE, class T, bool PREFETCH, int QV = 1>
 __device__ __forceinline__ void team_face(
     int64_t k, int r, int64_t n_face, int64_t n_elem,
     const int32_t *__restrict__ face_lr, const uint8_t *__restrict__ face_code,
     const double *__restrict__ face_geo, const T *__restrict__ s_tr, const T *__restrict__ s_pr, int n_codes,
-    const T *__restrict__ U, T *__restrict__ rhs, T *__restrict__ buf, const CombineArgs &cmb = CombineArgs{}) {
+    const T *__restrict__ U, T *__restrict__ rhs, T *__restrict__ buf, const CombineArgs &cmb = CombineArgs{},
+    const VolArgs &va = VolArgs{}) {
     constexpr int M = DIM + 2;
     constexpr int REC = M * NP;
     constexpr int TEAM = M <= 4 ? 4 : 8;
@@ -258,6 +243,20 @@ __device__ __forceinline__ void team_face(
     // my variable's traces on both sides
     T tL[Q], tR[Q];
     T cL_[NP], cR_[NP];
+    // the volume term of both elements, my variable (kVolume)
+    T vL[NP], vR[NP];
+    if constexpr (MODE == kVolume) {
+        const T *uL = U + (size_t)L * REC + r * NP;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) cL_[j] = own ? uL[j] : T(0);
+        if (R >= 0) {
+            const T *uR = U + (size_t)R * REC + r * NP;
+#pragma unroll
+            for (int j = 0; j < NP; ++j) cR_[j] = own ? uR[j] : T(0);
+        }
+        volume_team_core<DIM, NP, QV, T>(L, r, n_elem, va.elem_geo, va.vb, va.vd, cL_, vL);
+        if (R >= 0) volume_team_core<DIM, NP, QV, T>(R, r, n_elem, va.elem_geo, va.vb, va.vd, cR_, vR);
+    }
     {
         const T *uL = U + (size_t)L * REC + r * NP;
 #pragma unroll
@@ -317,6 +316,7 @@ __device__ __forceinline__ void team_face(
             for (int q = 0; q < Q; ++q) a += pl[q * NP + j] * Fm[q];
             a *= sL;
             if (MODE == kColored) dst[j] = (PREFETCH ? pre_L[j] : dst[j]) - a;
+            else if (MODE == kVolume) dst[j] = vL[j] - a;
             else if (MODE == kCombine)
                 combine_store(cmb, (size_t)L * REC + r * NP + j, cL_[j], (PREFETCH ? pre_L[j] : dst[j]) - a);
             else if (MODE == kAtomic) atomic_add<T>(dst + j, -a);
@@ -334,33 +334,13 @@ __device__ __forceinline__ void team_face(
             for (int q = 0; q < Q; ++q) a += pr[q * NP + j] * Fm[q];
             a *= sR;
             if (MODE == kColored) dst[j] = (PREFETCH ? pre_R[j] : dst[j]) + a;
+            else if (MODE == kVolume) dst[j] = vR[j] + a;
             else if (MODE == kCombine)
                 combine_store(cmb, (size_t)R * REC + r * NP + j, cR_[j], (PREFETCH ? pre_R[j] : dst[j]) + a);
             else if (MODE == kAtomic) atomic_add<T>(dst + j, a);
             else dst[j] = a;
         }
     }
-}
-
-// Sum over the 4 lanes of a quad (butterfly with DPP quad permutations);
-// every lane of the quad gets the same, order-independent result
-// ((v0 + v1) + (v2 + v3)).
-__device__ __forceinline__ int quad_xor1_i(int v) { return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false); }
-__device__ __forceinline__ int quad_xor2_i(int v) { return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false); }
-
-__device__ __forceinline__ double quad_xor1(double v) {
-    return __hiloint2double(quad_xor1_i(__double2hiint(v)), quad_xor1_i(__double2loint(v)));
-}
-__device__ __forceinline__ double quad_xor2(double v) {
-    return __hiloint2double(quad_xor2_i(__double2hiint(v)), quad_xor2_i(__double2loint(v)));
-}
-__device__ __forceinline__ float quad_xor1(float v) { return __int_as_float(quad_xor1_i(__float_as_int(v))); }
-__device__ __forceinline__ float quad_xor2(float v) { return __int_as_float(quad_xor2_i(__float_as_int(v))); }
-
-template <class T>
-__device__ __forceinline__ T quad_sum(T v) {
-    v = v + quad_xor1(v);
-    return v + quad_xor2(v);
 }
 
 // Mode-team form of the face work for N_p = 4 (tetrahedra, p = 1): a team
@@ -370,12 +350,13 @@ __device__ __forceinline__ T quad_sum(T v) {
 // j projects onto mode j.  Loads and stores of one record are 4 consecutive
 // values per instruction, and no lane idles (the variable-per-lane team
 // would need 8 lanes for M = 5).
-template <int DIM, int NP, int Q, int MODE, class T, bool PREFETCH>
+template <int DIM, int NP, int Q, int MODE, class T, bool PREFETCH, int QV = 1>
 __device__ __forceinline__ void mode_team_face(
     int64_t k, int j, int64_t n_face, int64_t n_elem,
     const int32_t *__restrict__ face_lr, const uint8_t *__restrict__ face_code,
     const double *__restrict__ face_geo, const T *__restrict__ s_tr, const T *__restrict__ s_pr, int n_codes,
-    const T *__restrict__ U, T *__restrict__ rhs, T *__restrict__ buf, const CombineArgs &cmb = CombineArgs{}) {
+    const T *__restrict__ U, T *__restrict__ rhs, T *__restrict__ buf, const CombineArgs &cmb = CombineArgs{},
+    const T *__restrict__ s_vb = nullptr, const T *__restrict__ s_vd = nullptr, const double *elem_geo = nullptr) {
     static_assert(NP == 4, "mode teams need exactly four modes");
     constexpr int M = DIM + 2;
     constexpr int REC = M * NP;
@@ -403,6 +384,18 @@ __device__ __forceinline__ void mode_team_face(
     }
     T uL[Q][M], uR[Q][M];
     T cL_[M], cR_[M];
+    // the volume term of both elements, my mode (kVolume; tables in LDS)
+    T vL[M], vR[M];
+    if constexpr (MODE == kVolume) {
+#pragma unroll
+        for (int m = 0; m < M; ++m) cL_[m] = U[(size_t)L * REC + m * NP + j];
+        if (R >= 0) {
+#pragma unroll
+            for (int m = 0; m < M; ++m) cR_[m] = U[(size_t)R * REC + m * NP + j];
+        }
+        volume_mode_team_core<DIM, NP, QV, T, T>(L, j, n_elem, elem_geo, s_vb, s_vd, cL_, vL);
+        if (R >= 0) volume_mode_team_core<DIM, NP, QV, T, T>(R, j, n_elem, elem_geo, s_vb, s_vd, cR_, vR);
+    }
     {
 #pragma unroll
         for (int m = 0; m < M; ++m) cL_[m] = U[(size_t)L * REC + m * NP + j];
@@ -439,6 +432,7 @@ __device__ __forceinline__ void mode_team_face(
             for (int q = 0; q < Q; ++q) a += s_pr[(cL * Q + q) * NP + j] * F[q][m];
             a *= sL;
             if (MODE == kColored) dst[m * NP + j] = (PREFETCH ? pre_L[m] : dst[m * NP + j]) - a;
+            else if (MODE == kVolume) dst[m * NP + j] = vL[m] - a;
             else if (MODE == kCombine)
                 combine_store(cmb, (size_t)L * REC + m * NP + j, cL_[m], (PREFETCH ? pre_L[m] : dst[m * NP + j]) - a);
             else if (MODE == kAtomic) atomic_add<T>(dst + m * NP + j, -a);
@@ -455,6 +449,7 @@ __device__ __forceinline__ void mode_team_face(
             for (int q = 0; q < Q; ++q) a += s_pr[(cR * Q + q) * NP + j] * F[q][m];
             a *= sR;
             if (MODE == kColored) dst[m * NP + j] = (PREFETCH ? pre_R[m] : dst[m * NP + j]) + a;
+            else if (MODE == kVolume) dst[m * NP + j] = vR[m] + a;
             else if (MODE == kCombine)
                 combine_store(cmb, (size_t)R * REC + m * NP + j, cR_[m], (PREFETCH ? pre_R[m] : dst[m * NP + j]) + a);
             else if (MODE == kAtomic) atomic_add<T>(dst + m * NP + j, a);
@@ -532,6 +527,41 @@ __global__ __launch_bounds__(256) void surface_combine_kernel(
     else
         team_face<DIM, NP, Q, kCombine, double, true>(k, threadIdx.x % TEAM, n_face, n_elem, face_lr, face_code,
                                                        face_geo, s_tr, s_pr, n_codes, U, rhs, nullptr, cmb);
+}
+
+// First color of a stage with the volume term fused in (see VolArgs): the
+// team form, or the mode team for tetrahedra at p = 1 (volume tables staged
+// in LDS after the face tables).
+template <int DIM, int NP, int Q, int QV, bool MT, class T>
+__global__ __launch_bounds__(256) void surface_volume_kernel(
+    int64_t f_begin, int64_t f_end, int64_t n_face, int64_t n_elem,
+    const int32_t *__restrict__ face_lr, const uint8_t *__restrict__ face_code,
+    const double *__restrict__ face_geo, const double *__restrict__ tab_trace,
+    const double *__restrict__ tab_proj, int n_codes,
+    const T *__restrict__ U, T *__restrict__ rhs, VolArgs va, int remap) {
+    constexpr int TEAM = MT ? 4 : (DIM + 2 <= 4 ? 4 : 8);
+    extern __shared__ unsigned char smem_raw[];
+    T *s_tr = reinterpret_cast<T *>(smem_raw);
+    T *s_pr = s_tr + n_codes * Q * NP;
+    if constexpr (MT) {
+        T *s_vb = s_pr + n_codes * Q * NP;
+        T *s_vd = s_vb + QV * NP;
+        for (int i = threadIdx.x; i < QV * NP; i += blockDim.x) s_vb[i] = T(va.vb[i]);
+        for (int i = threadIdx.x; i < DIM * QV * NP; i += blockDim.x) s_vd[i] = T(va.vd[i]);
+        stage_tables<T>(s_tr, s_pr, tab_trace, tab_proj, n_codes * Q * NP);  // its barrier covers both
+        const int64_t k = f_begin + ((int64_t)logical_block(remap) * blockDim.x + threadIdx.x) / 4;
+        if (k >= f_end) return;  // whole quads leave together
+        mode_team_face<DIM, NP, Q, kVolume, T, false, QV>(k, threadIdx.x % 4, n_face, n_elem, face_lr, face_code,
+                                                          face_geo, s_tr, s_pr, n_codes, U, rhs, nullptr,
+                                                          CombineArgs{}, s_vb, s_vd, va.elem_geo);
+    } else {
+        stage_tables<T>(s_tr, s_pr, tab_trace, tab_proj, n_codes * Q * NP);
+        const int64_t k = f_begin + ((int64_t)logical_block(remap) * blockDim.x + threadIdx.x) / TEAM;
+        if (k >= f_end) return;  // whole teams leave together
+        team_face<DIM, NP, Q, kVolume, T, false, QV>(k, threadIdx.x % TEAM, n_face, n_elem, face_lr, face_code,
+                                                     face_geo, s_tr, s_pr, n_codes, U, rhs, nullptr, CombineArgs{},
+                                                     va);
+    }
 }
 
 // Second pass of the buffered variant: rhs[k] += sum of element k's slots.

@@ -14,7 +14,12 @@
 
 namespace dgc_dev {
 
-template <int DIM, int NP, int QV, class T>
+// Unroll of the point loop of the one-work-item form: full for small
+// records, rolled from 9 modes on, where a fully unrolled loop runs out of
+// registers (measured on 1M-element meshes).
+__host__ __device__ constexpr int valu_volume_unroll(int np, int qv) { return np >= 9 ? 1 : qv; }
+
+template <int DIM, int NP, int QV, class T, int UNR = valu_volume_unroll(NP, QV)>
 __device__ __forceinline__ void volume_elem(int64_t k, int64_t n_elem, const double *__restrict__ elem_geo,
                                             const double *__restrict__ vb, const double *__restrict__ vd,
                                             const T *__restrict__ U, T *__restrict__ rhs) {
@@ -32,7 +37,7 @@ __device__ __forceinline__ void volume_elem(int64_t k, int64_t n_elem, const dou
     T acc[REC];
 #pragma unroll
     for (int i = 0; i < REC; ++i) acc[i] = 0;
-#pragma unroll
+#pragma unroll UNR
     for (int q = 0; q < QV; ++q) {
         T uq[M];
 #pragma unroll

@@ -14,7 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include "euler_dev.hpp"
-#include "surface.hpp"
+#include "team.hpp"
 
 namespace dgc_dev {
 
@@ -25,36 +25,39 @@ constexpr int volume_team_size() {
 
 // Lanes per element of the batched volume term: the team form where it is
 // the faster vector form, one work-item per element where that is faster
-// (tetrahedra; 2D with 9, 10 or 15 modes: quadrilaterals at p = 2, triangles
-// at p = 3, 4; measured on 1M-element meshes).  Host and device share this rule.
-__host__ __device__ constexpr int batch_volume_lanes(int dim, int np) {
-    return (dim == 3 || np == 9 || np == 10 || np == 15) ? 1 : 4;
+// (tetrahedra; f32 triangles and f32 quadrilaterals at p = 3; f64 triangles
+// at p = 3; measured on 1M-element meshes).  Host and device share this rule.
+__host__ __device__ constexpr int batch_volume_lanes(int dim, int np, bool f32) {
+    if (dim == 3) return 1;
+    const bool quad = np == 4 || np == 9 || np == 16;
+    if (f32) return (quad && np != 16) ? 4 : 1;
+    return np == 10 ? 1 : 4;
 }
 
-// element k, lane r of its team (all lanes of the team must call); the
-// tables may live in global memory (f64) or in LDS
-template <int DIM, int NP, int QV, class T, class TAB = double>
-__device__ __forceinline__ void volume_team_elem(int64_t k, int r, int64_t n_elem,
+// Unroll of the point loop of the team form: a rolled loop keeps the
+// registers of one point only (measured faster at every order: 58 instead of
+// 122 registers at N_p = 6; two points per trip at N_p = 21).
+__host__ __device__ constexpr int team_volume_unroll(int np) { return np >= 21 ? 2 : 1; }
+
+// Lane r's share of element k's volume term: c holds the element's modes of
+// variable r (zeros on lanes r >= M), out receives the result for variable r
+// (all lanes of the team must call; the tables may live in global memory
+// (f64) or in LDS).
+template <int DIM, int NP, int QV, class T, class TAB = double, int UNR = team_volume_unroll(NP)>
+__device__ __forceinline__ void volume_team_core(int64_t k, int r, int64_t n_elem,
                                                  const double *__restrict__ elem_geo, const TAB *__restrict__ vb,
-                                                 const TAB *__restrict__ vd, const T *__restrict__ U,
-                                                 T *__restrict__ rhs) {
+                                                 const TAB *__restrict__ vd, const T (&c)[NP], T (&out)[NP]) {
     constexpr int M = DIM + 2;
-    constexpr int REC = M * NP;
     constexpr int TEAM = volume_team_size<DIM>();
-    const bool own = r < M;
     T Ji[DIM * DIM];
 #pragma unroll
     for (int a = 0; a < DIM * DIM; ++a) Ji[a] = T(elem_geo[a * n_elem + k]);
     const double sq = elem_geo[DIM * DIM * n_elem + k];
     const T isq = T(1.0 / sq);
-    T c[NP];
-    const T *u = U + (size_t)k * REC + r * NP;
-#pragma unroll
-    for (int j = 0; j < NP; ++j) c[j] = own ? u[j] : T(0);
     T acc[NP];
 #pragma unroll
     for (int j = 0; j < NP; ++j) acc[j] = 0;
-#pragma unroll
+#pragma unroll UNR
     for (int q = 0; q < QV; ++q) {
         T t = 0;
 #pragma unroll
@@ -88,10 +91,79 @@ __device__ __forceinline__ void volume_team_elem(int64_t k, int r, int64_t n_ele
             acc[j] += a;
         }
     }
+#pragma unroll
+    for (int j = 0; j < NP; ++j) out[j] = acc[j] * T(sq);
+}
+
+// element k, lane r of its team (all lanes of the team must call)
+template <int DIM, int NP, int QV, class T, class TAB = double>
+__device__ __forceinline__ void volume_team_elem(int64_t k, int r, int64_t n_elem,
+                                                 const double *__restrict__ elem_geo, const TAB *__restrict__ vb,
+                                                 const TAB *__restrict__ vd, const T *__restrict__ U,
+                                                 T *__restrict__ rhs) {
+    constexpr int M = DIM + 2;
+    constexpr int REC = M * NP;
+    const bool own = r < M;
+    T c[NP];
+    const T *u = U + (size_t)k * REC + r * NP;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) c[j] = own ? u[j] : T(0);
+    T res[NP];
+    volume_team_core<DIM, NP, QV, T, TAB>(k, r, n_elem, elem_geo, vb, vd, c, res);
     if (!own) return;
     T *o = rhs + (size_t)k * REC + r * NP;
 #pragma unroll
-    for (int j = 0; j < NP; ++j) o[j] = acc[j] * T(sq);
+    for (int j = 0; j < NP; ++j) o[j] = res[j];
+}
+
+// Mode-team share of element k's volume term (N_p = 4, a quad of lanes, lane
+// j owning mode j of every variable; c and out hold that mode of the M
+// variables): the point values are quad sums of the lanes' shares, every
+// lane evaluates the flux of the full state, and lane j projects onto mode j.
+// (Giving each lane a quarter of the points instead avoids repeating the
+// flux, but needs the whole record and all 20 projections in every lane:
+// more than twice the registers.)  All four lanes of the quad must call.
+template <int DIM, int NP, int QV, class T, class TAB = double>
+__device__ __forceinline__ void volume_mode_team_core(int64_t k, int j, int64_t n_elem,
+                                                      const double *__restrict__ elem_geo, const TAB *__restrict__ vb,
+                                                      const TAB *__restrict__ vd, const T (&c)[DIM + 2],
+                                                      T (&out)[DIM + 2]) {
+    static_assert(NP == 4, "mode teams need exactly four modes");
+    constexpr int M = DIM + 2;
+    T Ji[DIM * DIM];
+#pragma unroll
+    for (int a = 0; a < DIM * DIM; ++a) Ji[a] = T(elem_geo[a * n_elem + k]);
+    const double sq = elem_geo[DIM * DIM * n_elem + k];
+    const T isq = T(1.0 / sq);
+    T acc[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) acc[m] = 0;
+#pragma unroll 1
+    for (int q = 0; q < QV; ++q) {
+        const T t = T(vb[q * NP + j]);
+        T uq[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) uq[m] = quad_sum(t * c[m]) * isq;
+        T Fx[M * DIM];
+        phys_flux<DIM, T>(uq, Fx);
+        T w[DIM];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) w[d] = T(vd[(d * QV + q) * NP + j]);
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            T a = 0;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) {
+                T g = 0;
+#pragma unroll
+                for (int e = 0; e < DIM; ++e) g += Ji[d * DIM + e] * Fx[m * DIM + e];
+                a += w[d] * g;
+            }
+            acc[m] += a;
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m) out[m] = acc[m] * T(sq);
 }
 
 template <int DIM, int NP, int QV, class T>

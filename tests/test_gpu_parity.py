@@ -341,10 +341,12 @@ def test_rk3_100_steps_vortex():
 @pytest.mark.parametrize("kind,size,p", [("delaunay", 6000, 2), ("periodic", 16, 1), ("periodic", 16, 3),
                                          ("tets", 5, 1), ("tets", 4, 2), ("quads", 12, 2), ("quadbox", 11, 1)])
 def test_rk3_step_forms_agree(kind, size, p):
-    """The stage combination fused into the last color's face kernel and the
-    whole step in one work-group give the separate-kernel step (same
-    formulas; only the compiler's contraction of a x + b (y + dt r) may
-    differ) over several steps, walls included."""
+    """The stage combination fused into the last color's face kernel, the
+    volume term fused into the first color's, and the whole step in one
+    work-group give the separate-kernel step (same formulas; only the
+    compiler's contraction of a x + b (y + dt r) and, with the fused volume
+    term, the summation order of the volume term may differ) over several
+    steps, walls included."""
     import torch
 
     c = Case(kind, size, 21, p)
@@ -356,7 +358,7 @@ def test_rk3_step_forms_agree(kind, size, p):
     U0 = c.Ug.clone()
     dt = 1e-4
     out = {}
-    for form in ("fused", "block", "separate", "default"):
+    for form in ("fused", "fused_volume", "block", "separate", "default"):
         c.D.set_rk_form(form)
         U = U0.clone()
         ws = c.D.workspace("rk", "colored")
@@ -366,7 +368,7 @@ def test_rk3_step_forms_agree(kind, size, p):
         out[form] = U
     c.D.set_rk_form("default")
     scale = out["separate"].abs().max().item()
-    for form in ("fused", "block", "default"):
+    for form in ("fused", "fused_volume", "block", "default"):
         assert (out[form] - out["separate"]).abs().max().item() <= 1e-14 * scale, form
     assert not torch.equal(out["default"], U0)
     # the single-work-group form needs f64
@@ -374,6 +376,38 @@ def test_rk3_step_forms_agree(kind, size, p):
         c.D.set_rk_form("block")
         c.D.rk_step(U0.clone(), dt, precision="f32", ws=c.D.workspace("rk", "colored", "f32"))
     c.D.set_rk_form("default")
+
+
+@pytest.mark.parametrize("kind,size,p", [("delaunay", 6000, 2), ("periodic", 16, 1), ("tets", 5, 1),
+                                         ("quadbox", 11, 1)])
+def test_rk3_f32_form_fused_volume(kind, size, p):
+    """The f32 form with the volume term fused into the first color's face
+    kernel matches the f32 form with a separate volume kernel: over 5 steps
+    the two states differ by at most 1e-5 of the change the steps made (f32
+    rounding of a differently ordered sum; a missing or doubled volume term
+    would differ by O(1) of it)."""
+    import torch
+
+    c = Case(kind, size, 22, p)
+    if kind != "tets":
+        st = synth.density_wave_states(synth.element_centroid(c.m["elem_xyz"]), vel=(0.5, 0.3))
+        c.Ug = torch.from_numpy(c.D.to_layout(synth.perturbed_dofs(c.O.elem_measure, st, c.d.n_p, eps=0.01,
+                                                                   seed=4))).cuda()
+    U0 = c.Ug.clone()
+    dt = 1e-4
+    out = {}
+    for form in ("separate", "fused_volume"):
+        c.D.set_rk_form(form)
+        U = U0.clone()
+        ws = c.D.workspace("rk", "colored", "f32")
+        for _ in range(5):
+            c.D.rk_step(U, dt, precision="f32", ws=ws)
+        torch.cuda.synchronize()
+        out[form] = U
+    c.D.set_rk_form("default")
+    change = (out["separate"] - U0).abs().max().item()
+    assert change > 0
+    assert (out["fused_volume"] - out["separate"]).abs().max().item() <= 1e-5 * change
 
 
 def test_rk3_quads_vortex_20_steps():
