@@ -338,8 +338,11 @@ def main(argv=None):
     ap.add_argument("--tet-n", type=int, default=64)
     ap.add_argument("--p", type=int, default=None)
     ap.add_argument("--seed", type=int, default=2)
-    ap.add_argument("--only", choices=["all", "colored", "volume"], default="all",
-                    help="'colored' times the colored pass only, 'volume' the volume-term forms only (for profiling)")
+    ap.add_argument("--only", choices=["all", "colored", "volume", "rk"], default="all",
+                    help="'colored' times the colored pass only, 'volume' the volume-term forms only, 'rk' the "
+                         "SSP-RK3 step forms only (for profiling)")
+    ap.add_argument("--rk-form", choices=["default", "fused_volume", "fused", "separate"], default="default",
+                    help="SSP-RK3 step form timed by --only rk")
     ap.add_argument("--form", choices=["auto", "default", "team", "team_prefetch", "thread"], default="auto",
                     help="face-kernel form; 'auto' runs the launch autotuner before timing")
     ap.add_argument("--block", type=int, default=0)
@@ -422,6 +425,16 @@ def main(argv=None):
             res[vf + "_us"] = timed(lambda: D.volume_rhs(Ug, rhs), args.steps, args.warmup, stream)[0] * 1e3
         log("volume forms: %s" % res)
         print(json.dumps({"volume_forms_us": res, "n_elem": K, "p": args.p}))
+        return 0
+
+    if args.only == "rk":
+        # SSP-RK3 steps of one form (for counter runs of the step's kernels)
+        D.set_rk_form(args.rk_form)
+        ws = D.workspace("rk", "colored")
+        Ur = Ug.clone()
+        t_ms = timed(lambda: D.rk_step(Ur, 1e-7, ws=ws), args.steps, args.warmup, stream)[0]
+        log("rk3 step (%s): %.1f us" % (args.rk_form, t_ms * 1e3))
+        print(json.dumps({"rk3_step_us": t_ms * 1e3, "rk_form": args.rk_form, "n_elem": K, "p": args.p}))
         return 0
 
     # clocks up: run the pass for ~0.5 s before any measurement

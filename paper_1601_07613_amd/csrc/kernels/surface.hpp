@@ -45,19 +45,20 @@ struct VolArgs {
 // when its last-color face is done its right-hand side is complete and the
 // face's lanes write out = a x + b (y + dt r) instead of r (y = the stage
 // input the traces were read from, x = the stage-0 state, or y itself when
-// x is null).  f64 only.
+// x is null).  f64 only.  x is read up front with the right-hand side: out
+// may be x itself (the last stage), so reads of x interleaved with the stores
+// would be serialised.
 struct CombineArgs {
     const double *x;
     double *out;
     double a, b, dt;
 };
 
-__device__ __forceinline__ void combine_store(const CombineArgs &cmb, size_t idx, double y, double r) {
-    const double x = cmb.x ? cmb.x[idx] : y;
+__device__ __forceinline__ void combine_store(const CombineArgs &cmb, size_t idx, double x, double y, double r) {
     cmb.out[idx] = cmb.a * x + cmb.b * (y + cmb.dt * r);
 }
 template <class T>
-__device__ __forceinline__ void combine_store(const CombineArgs &, size_t, T, T) {}
+__device__ __forceinline__ void combine_store(const CombineArgs &, size_t, T, T, T) {}
 
 template <class T>
 __device__ __forceinline__ void atomic_add(T *addr, T v) {
@@ -239,6 +240,18 @@ __device__ __forceinline__ void team_face(
             for (int j = 0; j < NP; ++j) pre_R[j] = b[j];
         }
     }
+    // the stage-0 state of a fused combination (kCombine with x set)
+    T xL[NP], xR[NP];
+    if (MODE == kCombine && cmb.x && own) {
+        const double *a = cmb.x + (size_t)L * REC + r * NP;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) xL[j] = T(a[j]);
+        if (R >= 0) {
+            const double *b = cmb.x + (size_t)R * REC + r * NP;
+#pragma unroll
+            for (int j = 0; j < NP; ++j) xR[j] = T(b[j]);
+        }
+    }
 
     // my variable's traces on both sides
     T tL[Q], tR[Q];
@@ -318,7 +331,8 @@ __device__ __forceinline__ void team_face(
             if (MODE == kColored) dst[j] = (PREFETCH ? pre_L[j] : dst[j]) - a;
             else if (MODE == kVolume) dst[j] = vL[j] - a;
             else if (MODE == kCombine)
-                combine_store(cmb, (size_t)L * REC + r * NP + j, cL_[j], (PREFETCH ? pre_L[j] : dst[j]) - a);
+                combine_store(cmb, (size_t)L * REC + r * NP + j, cmb.x ? xL[j] : cL_[j], cL_[j],
+                              (PREFETCH ? pre_L[j] : dst[j]) - a);
             else if (MODE == kAtomic) atomic_add<T>(dst + j, -a);
             else dst[j] = -a;
         }
@@ -336,7 +350,8 @@ __device__ __forceinline__ void team_face(
             if (MODE == kColored) dst[j] = (PREFETCH ? pre_R[j] : dst[j]) + a;
             else if (MODE == kVolume) dst[j] = vR[j] + a;
             else if (MODE == kCombine)
-                combine_store(cmb, (size_t)R * REC + r * NP + j, cR_[j], (PREFETCH ? pre_R[j] : dst[j]) + a);
+                combine_store(cmb, (size_t)R * REC + r * NP + j, cmb.x ? xR[j] : cR_[j], cR_[j],
+                              (PREFETCH ? pre_R[j] : dst[j]) + a);
             else if (MODE == kAtomic) atomic_add<T>(dst + j, a);
             else dst[j] = a;
         }
@@ -380,6 +395,16 @@ __device__ __forceinline__ void mode_team_face(
         if (R >= 0) {
 #pragma unroll
             for (int m = 0; m < M; ++m) pre_R[m] = rhs[(size_t)R * REC + m * NP + j];
+        }
+    }
+    // the stage-0 state of a fused combination (kCombine with x set)
+    T xL[M], xR[M];
+    if (MODE == kCombine && cmb.x) {
+#pragma unroll
+        for (int m = 0; m < M; ++m) xL[m] = T(cmb.x[(size_t)L * REC + m * NP + j]);
+        if (R >= 0) {
+#pragma unroll
+            for (int m = 0; m < M; ++m) xR[m] = T(cmb.x[(size_t)R * REC + m * NP + j]);
         }
     }
     T uL[Q][M], uR[Q][M];
@@ -434,7 +459,8 @@ __device__ __forceinline__ void mode_team_face(
             if (MODE == kColored) dst[m * NP + j] = (PREFETCH ? pre_L[m] : dst[m * NP + j]) - a;
             else if (MODE == kVolume) dst[m * NP + j] = vL[m] - a;
             else if (MODE == kCombine)
-                combine_store(cmb, (size_t)L * REC + m * NP + j, cL_[m], (PREFETCH ? pre_L[m] : dst[m * NP + j]) - a);
+                combine_store(cmb, (size_t)L * REC + m * NP + j, cmb.x ? xL[m] : cL_[m], cL_[m],
+                              (PREFETCH ? pre_L[m] : dst[m * NP + j]) - a);
             else if (MODE == kAtomic) atomic_add<T>(dst + m * NP + j, -a);
             else dst[m * NP + j] = -a;
         }
@@ -451,7 +477,8 @@ __device__ __forceinline__ void mode_team_face(
             if (MODE == kColored) dst[m * NP + j] = (PREFETCH ? pre_R[m] : dst[m * NP + j]) + a;
             else if (MODE == kVolume) dst[m * NP + j] = vR[m] + a;
             else if (MODE == kCombine)
-                combine_store(cmb, (size_t)R * REC + m * NP + j, cR_[m], (PREFETCH ? pre_R[m] : dst[m * NP + j]) + a);
+                combine_store(cmb, (size_t)R * REC + m * NP + j, cmb.x ? xR[m] : cR_[m], cR_[m],
+                              (PREFETCH ? pre_R[m] : dst[m * NP + j]) + a);
             else if (MODE == kAtomic) atomic_add<T>(dst + m * NP + j, a);
             else dst[m * NP + j] = a;
         }
