@@ -307,7 +307,8 @@ typedef struct {
  * face kernel of the last color when that is exact (f64, colored variant, a
  * conforming mesh colored with as many colors as an element has faces, so
  * every element has exactly one face of the last color, and a team face
- * form), else runs it as its own kernel; DGC_RK_SEPARATE always runs the
+ * form; the f32 form keeps its combination kernel, measured faster than a
+ * fused one), else runs it as its own kernel; DGC_RK_SEPARATE always runs the
  * combination as its own kernel; DGC_RK_BLOCK runs the whole step in one
  * work-group of 512 work-items, with barriers between the volume term, the
  * colors and the combinations (f64, colored variant, one element type; an
@@ -463,9 +464,14 @@ dgc_status dgc_surface_rhs_batched(const void *host_desc, const void *dev_desc, 
 dgc_status dgc_volume_rhs_batched(const void *host_desc, const void *dev_desc, int32_t stage, void *stream);
 
 /* One SSP-RK3 step of every mesh of the batch with its own dt: a fixed
- * sequence of 3 x (volume + one launch per color + combine) launches (plus
- * one for the f32 shadow), independent of the number of meshes, so it can be
- * captured once in a graph and replayed. */
+ * sequence of launches (plus one for the f32 shadow), independent of the
+ * number of meshes, so it can be captured once in a graph and replayed.
+ * When every member has exactly one face of each color (conforming meshes
+ * colored with as many colors as an element has faces), each stage is one
+ * launch per color, the first also evaluating the volume term (triangles
+ * p <= 3, quadrilaterals) and, in f64, the last writing the stage
+ * combination, as the single-mesh DGC_RK_DEFAULT step; otherwise 3 x
+ * (volume + one launch per color + combine). */
 dgc_status dgc_rk_step_batched(const void *host_desc, const void *dev_desc, void *stream);
 
 /* Library build identification (static string). */

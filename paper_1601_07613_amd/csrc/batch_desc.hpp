@@ -33,6 +33,10 @@ struct Entry {
 struct Header {
     uint32_t magic;
     int32_t n_mesh, n_colors, elem_type, p, n_p, n_var, n_qf, n_qv, n_codes, precision, block, faces_per_block;
+    // every member has exactly one face of each color: the RK step may fuse
+    // the stage combination into the last color's launch and (fuse_volume)
+    // the volume term into the first color's
+    int32_t fuse_combine, fuse_volume;
     int32_t nblk_face[kMaxColors];
     int32_t nblk_elem, nblk_dof;
     const double *tables;

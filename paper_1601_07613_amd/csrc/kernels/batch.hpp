@@ -46,9 +46,16 @@ constexpr int batch_team() {
     return (DIM == 3 && NP == 4) ? 4 : (DIM + 2 <= 4 ? 4 : 8);
 }
 
-template <int DIM, int NP, int Q, class T>
+// One color of every mesh.  MODE kColored accumulates into the stage
+// right-hand side; kVolume (first color) also evaluates the volume term and
+// writes the right-hand side; kCombine (last color, f64) writes the stage
+// combination instead of the right-hand side.  The fused modes need every
+// member to have exactly one face of each color.
+template <int DIM, int NP, int Q, int QV, int MODE, class T>
 __global__ __launch_bounds__(256) void batch_surface_kernel(const char *__restrict__ desc, int color, int stage) {
     constexpr int TEAM = batch_team<DIM, NP>();
+    constexpr bool kMT = DIM == 3 && NP == 4;
+    static_assert(!(kMT && MODE == kVolume), "the batched fused volume term uses the variable team");
     const Header *h = bh(desc);
     extern __shared__ unsigned char smem_raw[];
     T *s_tr = reinterpret_cast<T *>(smem_raw);
@@ -60,14 +67,25 @@ __global__ __launch_bounds__(256) void batch_surface_kernel(const char *__restri
     const int64_t k = e->color_off[color] + (local * blockDim.x + threadIdx.x) / TEAM;
     if (k >= e->color_off[color + 1]) return;
     const dgc_batch::RkWs w = dgc_batch::rk_ws(e->ws, (size_t)e->n_dof, sizeof(T) == 4);
-    if constexpr (DIM == 3 && NP == 4)
-        mode_team_face<DIM, NP, Q, kColored, T, true>(k, threadIdx.x % TEAM, e->n_face, e->n_elem, e->face_lr,
-                                                      e->face_code, e->face_geo, s_tr, s_pr, h->n_codes,
-                                                      stage_input<T>(e, w, stage), static_cast<T *>(w.rhs), nullptr);
+    const T *in = stage_input<T>(e, w, stage);
+    T *rhs = static_cast<T *>(w.rhs);
+    static_assert(MODE != kCombine || sizeof(T) == 8, "the fused stage combination is f64 only");
+    CombineArgs cmb{};
+    if constexpr (MODE == kCombine) {
+        cmb.x = stage == 0 ? nullptr : e->U;
+        cmb.out = stage == 0 ? w.U1 : (stage == 1 ? w.U2 : e->U);
+        cmb.a = stage == 0 ? 0.0 : (stage == 1 ? 0.75 : 1.0 / 3.0);
+        cmb.b = stage == 0 ? 1.0 : (stage == 1 ? 0.25 : 2.0 / 3.0);
+        cmb.dt = e->dt;
+    }
+    if constexpr (kMT)
+        mode_team_face<DIM, NP, Q, MODE, T, true>(k, threadIdx.x % TEAM, e->n_face, e->n_elem, e->face_lr,
+                                                  e->face_code, e->face_geo, s_tr, s_pr, h->n_codes, in, rhs, nullptr,
+                                                  cmb);
     else
-        team_face<DIM, NP, Q, kColored, T, true>(k, threadIdx.x % TEAM, e->n_face, e->n_elem, e->face_lr,
-                                                 e->face_code, e->face_geo, s_tr, s_pr, h->n_codes,
-                                                 stage_input<T>(e, w, stage), static_cast<T *>(w.rhs), nullptr);
+        team_face<DIM, NP, Q, MODE, T, MODE != kVolume, QV>(
+            k, threadIdx.x % TEAM, e->n_face, e->n_elem, e->face_lr, e->face_code, e->face_geo, s_tr, s_pr,
+            h->n_codes, in, rhs, nullptr, cmb, VolArgs{e->elem_geo, h->tables + h->off_vb, h->tables + h->off_vd});
 }
 
 template <int DIM, int NP, int QV, class T>

@@ -233,8 +233,9 @@ struct Impl {
         return s;
     }
 
-    // colored pass whose last color writes the stage combination (f64); *fused
-    // is false (and nothing is launched) when the last color is empty
+    // colored pass (from first_color on) whose last color writes the stage
+    // combination (f64); *fused is false (and nothing is launched) when the
+    // last color is empty
     static dgc_status surface_fused(const dgc_dmesh *dm, const dgc_table_info &ti, const T *U, T *rhs,
                                     const dgc_dev::CombineArgs &cmb, int first_color, bool *fused, hipStream_t st) {
         *fused = false;
@@ -453,6 +454,8 @@ dgc_status dgc_rk_step(const dgc_dmesh *dm, double *U, double dt, int32_t varian
     const bool one_face_per_color = variant == DGC_SURF_COLORED && dm->elem_type != DGC_MIXED &&
                                     dm->n_colors == faces_per_elem && dm->max_slots == faces_per_elem &&
                                     sform != DGC_FORM_THREAD && dm->color_off[1] > dm->color_off[0];
+    // (the f32 form keeps its combination kernel: measured faster than a fused
+    // one, whose extra f64 reads cost the face kernel registers)
     const bool fuse = !shadow && one_face_per_color && dm->rk_form != DGC_RK_SEPARATE;
     const bool vol_team_face = sform == DGC_FORM_TEAM || sform == DGC_FORM_TEAM_PREFETCH ||
                                (sform == DGC_FORM_MODE_TEAM && dm->elem_type == DGC_TET && dm->p == 1);
@@ -538,15 +541,36 @@ dgc_status read_header(const void *host_desc, dgc_batch::Header *h) {
 
 template <int DIM, int NP, int Q, int QV, class T>
 struct BatchImpl {
-    static dgc_status surface(const dgc_batch::Header &h, const char *dev, int stage, hipStream_t st) {
+    // color c of every mesh in face-kernel mode MODE
+    template <int MODE>
+    static dgc_status color(const dgc_batch::Header &h, const char *dev, int stage, int c, hipStream_t st) {
+        if (h.nblk_face[c] == 0) return DGC_OK;
         const size_t lds = 2 * (size_t)h.n_codes * Q * NP * sizeof(T);
-        for (int c = 0; c < h.n_colors; ++c) {
-            if (h.nblk_face[c] == 0) continue;
-            hipLaunchKernelGGL((dgc_dev::batch_surface_kernel<DIM, NP, Q, T>), dim3(h.nblk_face[c]), dim3(h.block), lds,
-                               st, dev, c, stage);
-            if (dgc_status s = hip_check("batched surface launch"); s != DGC_OK) return s;
+        if constexpr (MODE == dgc_dev::kVolume && DIM == 3 && NP == 4) {
+            return fail(DGC_E_UNSUPPORTED, "the batched fused volume term needs the variable team");
+        } else {
+            hipLaunchKernelGGL((dgc_dev::batch_surface_kernel<DIM, NP, Q, QV, MODE, T>), dim3(h.nblk_face[c]),
+                               dim3(h.block), lds, st, dev, c, stage);
+            return hip_check("batched surface launch");
         }
+    }
+    static dgc_status surface(const dgc_batch::Header &h, const char *dev, int stage, hipStream_t st) {
+        for (int c = 0; c < h.n_colors; ++c)
+            if (dgc_status s = color<dgc_dev::kColored>(h, dev, stage, c, st); s != DGC_OK) return s;
         return DGC_OK;
+    }
+    // the volume and face work of one SSP-RK3 stage, with the volume term in
+    // the first color's launch and (f64) the combination in the last color's
+    // as the header allows
+    static dgc_status stage_fused(const dgc_batch::Header &h, const char *dev, int stage, hipStream_t st) {
+        const int nc = h.n_colors;
+        dgc_status s = h.fuse_volume ? color<dgc_dev::kVolume>(h, dev, stage, 0, st) : volume(h, dev, stage, st);
+        if (s != DGC_OK) return s;
+        for (int c = h.fuse_volume ? 1 : 0; c < nc - 1; ++c)
+            if ((s = color<dgc_dev::kColored>(h, dev, stage, c, st)) != DGC_OK) return s;
+        if constexpr (std::is_same_v<T, double>)
+            if (h.fuse_combine) return color<dgc_dev::kCombine>(h, dev, stage, nc - 1, st);
+        return color<dgc_dev::kColored>(h, dev, stage, nc - 1, st);
     }
     static dgc_status volume(const dgc_batch::Header &h, const char *dev, int stage, hipStream_t st) {
         hipLaunchKernelGGL((dgc_dev::batch_volume_kernel<DIM, NP, QV, T>), dim3(h.nblk_elem), dim3(kBlock), 0, st, dev,
@@ -669,6 +693,18 @@ dgc_status dgc_batch_describe(int32_t n_mesh, const dgc_dmesh *meshes, double *c
     h.precision = precision;
     h.block = kBlock;
     h.faces_per_block = fpb;
+    {
+        // fused stage kernels need exactly one face of each color per element
+        const int fpe = h.elem_type == DGC_TRI ? 3 : 4;
+        bool one = true;
+        for (int32_t i = 0; i < n_mesh; ++i) {
+            const dgc_dmesh &d = meshes[i];
+            one = one && d.n_colors == fpe && d.max_slots == fpe && d.color_off[1] > d.color_off[0] &&
+                  d.color_off[fpe] > d.color_off[fpe - 1];
+        }
+        h.fuse_combine = one && precision == DGC_F64 ? 1 : 0;
+        h.fuse_volume = one && default_fuse_volume(h.elem_type, h.p) ? 1 : 0;
+    }
     h.tables = meshes[0].tables;
     h.off_trace = ti.off_trace;
     h.off_proj = ti.off_proj;
@@ -769,8 +805,17 @@ dgc_status dgc_rk_step_batched(const void *host_desc, const void *dev_desc, void
         if (dgc_status s = hip_check("batched f32 shadow launch"); s != DGC_OK) return s;
     }
     for (int stage = 0; stage < 3; ++stage) {
-        if (dgc_status s = dgc_volume_rhs_batched(host_desc, dev_desc, stage, stream); s != DGC_OK) return s;
-        if (dgc_status s = dgc_surface_rhs_batched(host_desc, dev_desc, stage, stream); s != DGC_OK) return s;
+        if (h.fuse_combine || h.fuse_volume) {
+            dgc_status s = dispatch_type(h.elem_type, h.p, h.precision, [&](auto impl) {
+                using I = decltype(impl);
+                return BatchImpl<I::kDim, I::kNp, I::kQ, I::kQv, typename I::Real>::stage_fused(h, dev, stage, st);
+            });
+            if (s != DGC_OK) return s;
+            if (h.fuse_combine) continue;
+        } else {
+            if (dgc_status s = dgc_volume_rhs_batched(host_desc, dev_desc, stage, stream); s != DGC_OK) return s;
+            if (dgc_status s = dgc_surface_rhs_batched(host_desc, dev_desc, stage, stream); s != DGC_OK) return s;
+        }
         if (f32)
             hipLaunchKernelGGL(dgc_dev::batch_combine_kernel<float>, dim3(h.nblk_dof), dim3(kBlock), 0, st, dev, stage);
         else

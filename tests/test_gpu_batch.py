@@ -98,12 +98,13 @@ def test_batched_rk_steps_match_single(precision):
     members = [_member(k, s, sd, 2, precision, smooth=True) for k, s, sd in TRI]
     ref = [(D, Ug.clone(), D.workspace("rk", "colored", precision), dt) for D, Ug, ws, dt in members]
     B = dgc.Batch(members, precision=precision)
-    # the single-mesh steps with the batch's volume form and a separate volume
-    # kernel, so that both sides round alike (the f32 form rounds a
-    # differently ordered volume sum visibly)
+    # the batched step fuses the volume term and the stage combination into
+    # the first and last colors' launches like the single-mesh default step,
+    # so both round alike (the f32 form would show a differently ordered
+    # volume sum)
     for D, _, _, _ in ref:
-        D.set_volume_form(_batch_volume_form(D, precision))
-        D.set_rk_form("fused")
+        D.set_volume_form("default")
+        D.set_rk_form("default")
     for _ in range(10):
         B.rk_step()
         for D, U, w, dt in ref:
