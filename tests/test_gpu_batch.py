@@ -89,13 +89,22 @@ def test_batched_tets_bitwise_single():
         assert torch.equal(B.stage_rhs(i), r), i
 
 
+TET = [("tets", 4, 1), ("tets", 6, 2), ("tets", 4, 3)]
+
+
+@pytest.mark.parametrize("family,p", [("tri", 2), ("quad", 2), ("quad", 1), ("tet", 1)])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
-def test_batched_rk_steps_match_single(precision):
+def test_batched_rk_steps_match_single(precision, family, p):
+    """Batched SSP-RK3 steps (the first color's launch carrying the volume
+    term for triangles and parallelograms, the last color's the stage
+    combination in f64) equal the single-mesh default steps, walls
+    included."""
     import torch
 
     import paper_1601_07613_amd as dgc
 
-    members = [_member(k, s, sd, 2, precision, smooth=True) for k, s, sd in TRI]
+    fam = {"tri": TRI, "quad": QUAD, "tet": TET}[family]
+    members = [_member(k, s, sd, p, precision, smooth=True) for k, s, sd in fam]
     ref = [(D, Ug.clone(), D.workspace("rk", "colored", precision), dt) for D, Ug, ws, dt in members]
     B = dgc.Batch(members, precision=precision)
     # the batched step fuses the volume term and the stage combination into
