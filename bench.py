@@ -65,6 +65,21 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def host_cpu() -> dict:
+    """The host's CPU model string and logical CPU count (as the OS reports
+    them; a container may be limited to fewer)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count()}
+
+
 def algorithmic_bytes(n_face: int, n_interior: int, rec: int, elt: int, dim: int) -> int:
     """Bytes one colored pass must move: per face side, read the DOF record and
     read + write the RHS record; per face, its geometry (dim + 3 doubles),
@@ -558,7 +573,8 @@ def main(argv=None):
         cpu_s = (time.perf_counter() - t) / reps
         cpu = {"value": dof / cpu_s, "unit": "DOF-updates/s", "cores": 1, "kind": "oracle",
                "sample": "the full surface term of this workload (%d elements, %d faces), %d repetitions, "
-                         "numpy float64, single process" % (K, E, reps)}
+                         "numpy float64, single process" % (K, E, reps),
+               "host": host_cpu()}
         log("cpu oracle: %.2f s per surface term" % cpu_s)
         if not args.no_cpu_pool:
             cpu["pool"] = oracle_pool(m, U, args.p, log)
