@@ -472,6 +472,61 @@ def test_full_size_sampled(full_c1):
     _check(other, got, dg.surface_abs(c.d, c.U), "full-size thread form vs team form")
 
 
+def test_full_size_rk_step(full_c1):
+    """One SSP-RK3 step of the full Delaunay workload in the default form
+    (volume term in the first color's face kernel, stage combination in the
+    last color's) against the oracle's step: the new state at 1e-12 of its
+    largest entry, the change the step made at 1e-10 of the largest change."""
+    import torch
+
+    c = full_c1
+    # a smooth state (the shock tube's noisy traces reach negative pressures
+    # within a step: there is no limiter)
+    st = synth.density_wave_states(synth.element_centroid(c.m["elem_xyz"]), vel=(0.5, 0.3))
+    U0 = synth.perturbed_dofs(c.O.elem_measure, st, c.d.n_p, eps=0.01, seed=5)
+    dt = dg.cfl_dt(c.d, U0, 0.1)
+    ref = dg.rk3_step(c.d, U0, dt)
+    assert np.isfinite(ref).all()
+    U = torch.from_numpy(c.D.to_layout(U0)).cuda()
+    c.D.set_rk_form("default")
+    c.D.rk_step(U, dt, ws=c.D.workspace("rk", "colored"))
+    got = c.to_host(U)
+    assert np.isfinite(got).all()
+    assert np.abs(got - ref).max() <= TOL * np.abs(ref).max()
+    change = np.abs(ref - U0).max()
+    assert np.abs((got - U0) - (ref - U0)).max() <= 1e-10 * change
+
+
+@pytest.fixture(scope="module")
+def full_c2():
+    """The full tetrahedral workload: 64^3 periodic cubes x 6 Kuhn tetrahedra
+    (1,572,864 tetrahedra), p = 1, density wave plus 1 % high-mode noise."""
+    return Case("tets", 64, 3, 1, cseed=0, eps=0.01)
+
+
+def test_full_size_tets_sampled(full_c2):
+    c = full_c2
+    assert c.D.info["n_colors"] == 4
+    c.D.set_launch("default")
+    got = c.to_host(c.surface("colored"))
+    rng = np.random.default_rng(43)
+    S = np.unique(np.concatenate([rng.choice(c.O.K, 3000, replace=False), [0, c.O.K - 1]]))
+    ref = dg.surface_rhs(c.d, c.U, elems=S)
+    scale = dg.surface_abs(c.d, c.U)
+    _check(got[S], ref[S], scale[S], "full-size tets sampled colored")
+    # the f32 form of the same pass at its own bar
+    import torch
+
+    U32 = c.U.astype(np.float32)
+    Ug32 = torch.from_numpy(c.D.to_layout(U32)).cuda()
+    r32 = torch.zeros_like(Ug32)
+    c.D.surface_rhs(Ug32, r32, variant="colored", precision="f32")
+    torch.cuda.synchronize()
+    got32 = c.D.from_layout(r32.cpu().numpy()).astype(np.float64)
+    ref32 = dg.surface_rhs(c.d, U32.astype(np.float64), elems=S)
+    _check_tol(got32[S], ref32[S], scale[S], "full-size tets sampled f32", TOL32)
+
+
 # ---------------------------------------------------------------- FP32 form
 
 TOL32 = 2e-6
