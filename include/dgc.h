@@ -380,9 +380,13 @@ dgc_status dgc_surface_rhs(const dgc_dmesh *dm, const void *U, void *rhs, int32_
                            int32_t precision, void *ws, size_t ws_bytes, void *stream);
 
 /* One SSP-RK3 step (Shu-Osher form) of U (device f64, updated in place):
- * three stages of volume term + surface term (`variant`) + combination.
+ * three stages of volume term + surface term (`variant`) + combination,
+ * launched as dm->rk_form says (the volume term and the combination may
+ * ride on the first and last color's face kernels, see DGC_RK_*).
  * DGC_F32 evaluates both terms on an f32 shadow of the stage state and
- * accumulates the stages in f64.  ws holds the stage states and the RHS. */
+ * accumulates the stages in f64.  ws holds the stage states and the RHS
+ * (DGC_WS_RK_STEP bytes, dgc_rk_workspace_layout).  Errors: DGC_E_ARG,
+ * DGC_E_NOT_COLORED, DGC_E_WORKSPACE, DGC_E_UNSUPPORTED, DGC_E_HIP. */
 dgc_status dgc_rk_step(const dgc_dmesh *dm, double *U, double dt, int32_t variant, int32_t precision,
                        void *ws, size_t ws_bytes, void *stream);
 
