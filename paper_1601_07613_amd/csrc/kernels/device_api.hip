@@ -25,20 +25,25 @@ namespace {
 constexpr int kBlock = 256;
 
 // DGC_FORM_DEFAULT: the face-kernel form measured fastest for each element
-// type and order (f64 colored pass, ~1M elements): the team with
+// type, order and precision (colored pass, ~1M elements): the team with
 // right-hand-side prefetch, except where its registers cost more than the
-// prefetch gains (triangles p = 4, parallelograms p = 1 and 3: the team
-// without prefetch), the mode team for tetrahedra at p = 1, and one
-// work-item per face for tetrahedra at p = 2 (8-lane teams of 10 modes)
-int default_surface_form(int elem_type, int p) {
-    if (elem_type == DGC_TET) return p == 1 ? DGC_FORM_MODE_TEAM : (p == 2 ? DGC_FORM_THREAD : DGC_FORM_TEAM_PREFETCH);
+// prefetch gains (f64 triangles p = 4, parallelograms p = 1 and 3: the team
+// without prefetch), the mode team for tetrahedra at p = 1, and for
+// tetrahedra at p = 2 one work-item per face in f64 (8-lane teams of 10
+// modes), the team with prefetch in f32
+int default_surface_form(int elem_type, int p, bool f32) {
+    if (elem_type == DGC_TET) {
+        if (p == 1) return DGC_FORM_MODE_TEAM;
+        if (p == 2) return f32 ? DGC_FORM_TEAM_PREFETCH : DGC_FORM_THREAD;
+        return DGC_FORM_TEAM_PREFETCH;
+    }
     if (elem_type == DGC_QUAD || elem_type == DGC_MIXED)
         return (p == 1 || p == 3) ? DGC_FORM_TEAM : DGC_FORM_TEAM_PREFETCH;
-    return p == 4 ? DGC_FORM_TEAM : DGC_FORM_TEAM_PREFETCH;
+    return (p == 4 && !f32) ? DGC_FORM_TEAM : DGC_FORM_TEAM_PREFETCH;
 }
 
-int resolved_surface_form(const dgc_dmesh *dm) {
-    return dm->surf_form == DGC_FORM_DEFAULT ? default_surface_form(dm->elem_type, dm->p) : dm->surf_form;
+int resolved_surface_form(const dgc_dmesh *dm, bool f32) {
+    return dm->surf_form == DGC_FORM_DEFAULT ? default_surface_form(dm->elem_type, dm->p, f32) : dm->surf_form;
 }
 
 // DGC_VOL_DEFAULT: the volume form measured fastest for each element type,
@@ -146,7 +151,7 @@ struct Impl {
         if (f1 <= f0) return DGC_OK;
         const size_t lds = 2 * (size_t)ti.n_codes * Q * NP * sizeof(T);
         const int block = dm->block_size ? dm->block_size : kBlock;
-        const int form = resolved_surface_form(dm);
+        const int form = resolved_surface_form(dm, sizeof(T) == 4);
         if constexpr (NP == 4 && DIM == 3) {
             // tetrahedra at p = 1: the mode team (4 lanes, lane = mode)
             if (form == DGC_FORM_MODE_TEAM) {
@@ -201,7 +206,7 @@ struct Impl {
     static dgc_status faces_volume(const dgc_dmesh *dm, const dgc_table_info &ti, int64_t f0, int64_t f1, const T *U,
                                    T *rhs, hipStream_t st) {
         const int block = dm->block_size ? dm->block_size : kBlock;
-        const int form = resolved_surface_form(dm);
+        const int form = resolved_surface_form(dm, sizeof(T) == 4);
         const dgc_dev::VolArgs va{dm->elem_geo, dm->tables + ti.off_vb, dm->tables + ti.off_vd};
         const size_t lds = 2 * (size_t)ti.n_codes * Q * NP * sizeof(T);
         if constexpr (NP == 4 && DIM == 3) {
@@ -251,7 +256,7 @@ struct Impl {
             const size_t lds = 2 * (size_t)ti.n_codes * Q * NP * sizeof(double);
             const int block = dm->block_size ? dm->block_size : kBlock;
             constexpr bool kMT = DIM == 3 && NP == 4;
-            if (kMT && resolved_surface_form(dm) == DGC_FORM_MODE_TEAM) {
+            if (kMT && resolved_surface_form(dm, false) == DGC_FORM_MODE_TEAM) {
                 hipLaunchKernelGGL((dgc_dev::surface_combine_kernel<DIM, NP, Q, kMT>),
                                    dim3(grid_for((f1 - f0) * 4, block)), dim3(block), lds, st, f0, f1, dm->n_face,
                                    dm->n_elem, dm->face_lr, dm->face_code, dm->face_geo, dm->tables + ti.off_trace,
@@ -450,7 +455,7 @@ dgc_status dgc_rk_step(const dgc_dmesh *dm, double *U, double dt, int32_t varian
     // face of each color (see DGC_RK_FUSED and DGC_RK_FUSED_VOLUME)
     if (variant == DGC_SURF_COLORED && (s = check_colors(dm)) != DGC_OK) return s;
     const int faces_per_elem = dm->elem_type == DGC_TRI ? 3 : 4;
-    const int sform = resolved_surface_form(dm);
+    const int sform = resolved_surface_form(dm, shadow != nullptr);
     const bool one_face_per_color = variant == DGC_SURF_COLORED && dm->elem_type != DGC_MIXED &&
                                     dm->n_colors == faces_per_elem && dm->max_slots == faces_per_elem &&
                                     sform != DGC_FORM_THREAD && dm->color_off[1] > dm->color_off[0];
