@@ -493,6 +493,9 @@ def main(argv=None):
         D.set_rk_form("fused_volume")
         extra["rk3_step_fused_volume_us"] = timed(lambda: D.rk_step(Ur, 1e-7, ws=wsr), max(args.steps // 5, 3), 2,
                                                   stream)[0] * 1e3
+        from paper_1601_07613_amd.tune import autotune_rk
+
+        extra["rk3_step_autotuned_form"] = autotune_rk(D, Ur, 1e-7)[0]
         D.set_rk_form("default")
         wsr32 = D.workspace("rk", "colored", "f32")
         for rf in ("separate", "fused_volume"):

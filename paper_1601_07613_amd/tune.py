@@ -1,10 +1,12 @@
-"""Launch autotuner for the colored face kernels.
+"""Launch autotuner for the colored face kernels and the SSP-RK3 step.
 
 Times every candidate launch configuration (kernel form, work-group size,
 XCD remapping) of one device mesh on the caller's data with HIP events and
-installs the fastest one.  All candidates compute the same result; only the
-rounding order of the accumulation could differ between forms, and the
-colored update is bitwise deterministic for a fixed form.
+installs the fastest one; then, optionally, the fastest SSP-RK3 step
+schedule (volume term and stage combination fused into the first and last
+colors' launches, the combination only, or separate launches).  All
+candidates compute the same result; only the rounding order of some sums
+could differ between forms, and every form is bitwise deterministic.
 """
 
 from __future__ import annotations
@@ -49,4 +51,25 @@ def autotune(dmesh, U, rhs, variant: str = "colored", precision: str = "f64", ca
         results.append((dict(c), ms))
     best = min(results, key=lambda r: r[1])[0]
     dmesh.set_launch(best["form"], best["block"], best.get("xcd_remap", False))
+    return best, results
+
+
+RK_FORMS = ("fused_volume", "fused", "separate")
+
+
+def autotune_rk(dmesh, U, dt: float, precision: str = "f64", forms=RK_FORMS, reps: int = 5, warmup: int = 2):
+    """Pick the fastest SSP-RK3 step form of ``dmesh`` (with its installed face
+    launch) for a state shaped like ``U``; the steps run on a copy, ``U`` is
+    left unchanged.  Returns ``(best, [(form, ms), ...])`` and leaves ``best``
+    installed.  A form whose conditions do not hold on this mesh runs as the
+    next simpler one, so timing it is harmless."""
+    work = U.clone()
+    ws = dmesh.workspace("rk", "colored", precision)
+    results = []
+    for f in forms:
+        dmesh.set_rk_form(f)
+        ms = time_call(lambda: dmesh.rk_step(work, dt, precision=precision, ws=ws), reps, warmup)
+        results.append((f, ms))
+    best = min(results, key=lambda r: r[1])[0]
+    dmesh.set_rk_form(best)
     return best, results
