@@ -306,7 +306,7 @@ def extra_workloads(dgc, synth, torch, steps, warmup, log):
                                           ("plain_f64_sequential", "f64", "sequential", 200 << 30, False),
                                           ("batched_f32_saturated", "f32", "batched", 200 << 30, True),
                                           ("plain_f64_saturated", "f64", "sequential", 200 << 30, True)):
-        st = Server(GPUExecutor(precision=prec), budget_bytes=budget, mode=mode, prep_workers=8).run(reqs(sat))
+        st = Server(GPUExecutor(precision=prec), budget_bytes=budget, mode=mode, prep_workers=16).run(reqs(sat))
         serving[name] = st.summary()
         log("c4 %s: %s" % (name, serving[name]))
     out["c4_serving_256"] = serving

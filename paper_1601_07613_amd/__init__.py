@@ -397,14 +397,17 @@ class Batch:
         elt = 8 if self.precision == "f64" else 4
         return ws[off[2]:off[2] + n * elt].view(dt).view(D.K, D.n_var, D.n_p)
 
-    def capture(self, steps: int = 1):
-        """Capture ``steps`` batched RK3 steps in a graph; returns the graph (replay with ``.replay()``)."""
+    def capture(self, steps: int = 1, warm: bool = True):
+        """Capture ``steps`` batched RK3 steps in a graph; returns the graph
+        (replay with ``.replay()``).  ``warm`` first runs a stage-0 volume +
+        surface evaluation, which loads the kernels before the capture (it
+        writes only the stage right-hand side in the workspaces, never a
+        state); a caller that has already stepped this batch may skip it."""
         import torch
 
-        # load the kernels before capturing: stage-0 volume + surface only
-        # write the stage right-hand side (workspace), never the state
-        self.volume(0)
-        self.surface(0)
+        if warm:
+            self.volume(0)
+            self.surface(0)
         torch.cuda.synchronize()
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):

@@ -6,9 +6,12 @@ each request's mesh while the GPU works.  A prepared request is admitted when
 its device footprint fits in the HBM budget (first come, first served; a
 request that can never fit is rejected).  Admitted requests of the same order
 p form one group; every iteration advances every group by one batched SSP-RK3
-step (one graph replay per group, re-captured only when the group's
-membership changes), so requests join and leave between steps and their work
-overlaps on the device.  Finished requests free their memory for the next
+step, so requests join and leave between steps and their work overlaps on
+the device.  A group whose membership changed steps with eager batched
+launches; once its membership has held for a few steps its step is captured
+in a graph and replayed until the next change (a capture costs a warm-up
+and a synchronisation, which a membership that changes every few steps
+would pay over and over).  Finished requests free their memory for the next
 admission.  A request whose result is not finite fails alone.
 
 ``mode="sequential"`` is the plain baseline: one request at a time, each
@@ -66,7 +69,8 @@ class ServeStats:
     makespan: float = 0.0
     dof_steps: float = 0.0
     max_used: int = 0
-    recaptures: int = 0
+    recaptures: int = 0       # membership rebuilds of the batched groups
+    graph_captures: int = 0   # graphs the executor captured
     iterations: int = 0
 
     def summary(self) -> dict:
@@ -77,7 +81,8 @@ class ServeStats:
             "mean_s": float(lat.mean()), "makespan_s": self.makespan,
             "requests_per_s": self.completed / self.makespan if self.makespan > 0 else 0.0,
             "dof_steps_per_s": self.dof_steps / self.makespan if self.makespan > 0 else 0.0,
-            "max_used_bytes": self.max_used, "graph_captures": self.recaptures, "iterations": self.iterations,
+            "max_used_bytes": self.max_used, "membership_rebuilds": self.recaptures,
+            "graph_captures": self.graph_captures, "iterations": self.iterations,
         }
 
 
@@ -189,6 +194,7 @@ class Server:
                         dirty.add(p)
                     active[p] = keep
             st.makespan = clock.now() - (reqs[0].arrival if reqs else 0.0)
+            st.graph_captures = int(getattr(self.ex, "captures", 0))
         finally:
             if pool is not None:
                 pool.shutdown(wait=True)
@@ -219,6 +225,8 @@ class GPUExecutor:
         self.seed = seed
         self.batches = {}
         self.graphs = {}
+        self.eager_steps = {}
+        self.captures = 0
 
     # host work (worker threads): mesh, coloring, layout, initial DOFs, dt
     def prepare(self, r: Request) -> None:
@@ -259,13 +267,26 @@ class GPUExecutor:
         r.host = None
         r.dev = None
 
+    # eager batched steps of a group before its step is captured in a graph
+    STABLE_STEPS = 2
+
     def rebuild(self, p, group) -> None:
-        B = self.dgc.Batch([r.dev for r in group], precision=self.precision)
-        self.batches[p] = B
-        self.graphs[p] = B.capture()
+        self.batches[p] = self.dgc.Batch([r.dev for r in group], precision=self.precision)
+        self.graphs.pop(p, None)
+        self.eager_steps[p] = 0
 
     def step_group(self, p, group) -> None:
-        self.graphs[p].replay()
+        g = self.graphs.get(p)
+        if g is not None:
+            g.replay()
+            return
+        B = self.batches[p]
+        B.rk_step()
+        self.eager_steps[p] += 1
+        if self.eager_steps[p] >= self.STABLE_STEPS:
+            # the kernels are loaded by now: capture without a warm-up stage
+            self.graphs[p] = B.capture(warm=False)
+            self.captures += 1
 
     def step_single(self, r: Request) -> None:
         D, U, ws, dt = r.dev
