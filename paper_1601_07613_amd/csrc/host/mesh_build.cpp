@@ -3,9 +3,13 @@
 //
 // The paper keeps the connectivity face-wise: each face points to its left
 // and right element (Section 5, Table 5a).  Faces are matched here by
-// sorting (sorted vertex-id key, visit index) records, which reproduces the
+// ordering (sorted vertex-id key, visit index) records, which reproduces the
 // "first visit creates the face" numbering without a hash table: the visit
-// index elem * F + local is unique and increasing in scan order.
+// index elem * F + local is unique and increasing in scan order.  The records
+// are bucketed by their smallest vertex id with a stable counting sort (a
+// bucket holds the few faces around one vertex) and each bucket is sorted by
+// the rest of the key; the faces are then numbered by walking the visit
+// indices in order.
 #include <algorithm>
 #include <array>
 #include <cmath>
@@ -143,8 +147,9 @@ dgc_status build_faces(Mesh &m) {
     if (dgc_status g = elem_geometry(m); g != DGC_OK) return g;
 
     // face matching (an element of a mixed mesh has 3 or 4 faces)
-    std::vector<FaceRec> rec;
-    rec.reserve(K * F);
+    std::vector<FaceRec> raw;
+    raw.reserve(K * F);
+    int32_t n_vert = 0;
     for (int64_t i = 0; i < K; ++i) {
         const int Fi = elem_n_faces(m, i);
         for (int k = 0; k < Fi; ++k) {
@@ -152,27 +157,59 @@ dgc_status build_faces(Mesh &m) {
             r.key = {-1, -1, -1};
             for (int a = 0; a < nfv; ++a) r.key[a] = m.elem_vert[i * nv + face_vertex(m, i, k, a)];
             std::sort(r.key.begin(), r.key.begin() + nfv);
+            if (r.key[0] < 0) return fail(DGC_E_MESH, "negative vertex id");
+            n_vert = std::max(n_vert, r.key[nfv - 1] + 1);
             r.visit = i * F + k;
-            rec.push_back(r);
+            raw.push_back(r);
         }
     }
-    std::sort(rec.begin(), rec.end(), [](const FaceRec &a, const FaceRec &b) {
+    // stable counting sort by the smallest vertex id
+    std::vector<int64_t> bstart((size_t)n_vert + 1, 0);
+    for (const FaceRec &r : raw) ++bstart[(size_t)r.key[0] + 1];
+    for (int32_t v = 0; v < n_vert; ++v) bstart[v + 1] += bstart[v];
+    std::vector<FaceRec> rec(raw.size());
+    {
+        std::vector<int64_t> pos(bstart.begin(), bstart.end() - 1);
+        for (const FaceRec &r : raw) rec[pos[r.key[0]]++] = r;
+    }
+    raw.clear();
+    raw.shrink_to_fit();
+    const auto less = [](const FaceRec &a, const FaceRec &b) {
         if (a.key != b.key) return a.key < b.key;
         return a.visit < b.visit;
-    });
+    };
+    for (int32_t v = 0; v < n_vert; ++v) {
+        FaceRec *b = rec.data() + bstart[v], *e = rec.data() + bstart[v + 1];
+        if (e - b <= 32) {
+            for (FaceRec *x = b + 1; x < e; ++x) {  // insertion sort of a small bucket
+                const FaceRec t = *x;
+                FaceRec *y = x;
+                for (; y > b && less(t, y[-1]); --y) *y = y[-1];
+                *y = t;
+            }
+        } else {
+            std::sort(b, e, less);
+        }
+    }
+    // one group per face; walking the first visits in increasing order numbers
+    // the faces as the element scan first meets them
     struct Group { int64_t first, second; };
-    std::vector<Group> groups;
-    groups.reserve(rec.size() / 2 + 16);
+    std::vector<int64_t> partner((size_t)K * F, -2);  // -2: not a first visit
+    int64_t n_groups = 0;
     for (size_t s = 0; s < rec.size();) {
         size_t e = s + 1;
         while (e < rec.size() && rec[e].key == rec[s].key) ++e;
         if (e - s > 2) return fail(DGC_E_MESH, "a face is shared by more than two elements");
-        groups.push_back({rec[s].visit, e - s == 2 ? rec[s + 1].visit : -1});
+        partner[rec[s].visit] = e - s == 2 ? rec[s + 1].visit : -1;
+        ++n_groups;
         s = e;
     }
-    std::sort(groups.begin(), groups.end(), [](const Group &a, const Group &b) { return a.first < b.first; });
     rec.clear();
     rec.shrink_to_fit();
+    std::vector<Group> groups;
+    groups.reserve(n_groups);
+    for (int64_t t = 0; t < K * F; ++t)
+        if (partner[t] != -2) groups.push_back({t, partner[t]});
 
     const int64_t E = (int64_t)groups.size();
     m.E = E;
