@@ -353,11 +353,13 @@ enum { DGC_VOL_DEFAULT = 0, DGC_VOL_VALU = 1, DGC_VOL_MFMA = 2, DGC_VOL_TEAM = 3
  * evaluation; DGC_FORM_THREAD gives each face one work-item;
  * DGC_FORM_MODE_TEAM (tetrahedra, p = 1) gives each face 4 lanes, one per
  * mode, and sums the traces across them.  DGC_FORM_DEFAULT picks the form
- * measured fastest for the element type, order and precision: the team with
- * prefetch, the team without it for f64 triangles at p = 4 and for
- * parallelograms (and mixed meshes) at p = 1, 3, the mode team for
- * tetrahedra at p = 1 and, for tetrahedra at p = 2, one work-item per face
- * in f64. */
+ * measured fastest for the element type, order, precision and size: the
+ * team with prefetch for f64 triangles at p = 1 and at p = 2 from 1M faces
+ * on, for f32 triangles at p >= 3 and for parallelograms (and mixed meshes)
+ * at p = 0, 2; the team without prefetch for the other triangle and
+ * parallelogram cases; the mode team for tetrahedra at p = 1; for
+ * tetrahedra at p = 2 one work-item per face in f64, the team with
+ * prefetch in f32. */
 enum { DGC_FORM_DEFAULT = 0, DGC_FORM_TEAM = 1, DGC_FORM_THREAD = 2, DGC_FORM_TEAM_PREFETCH = 3,
        DGC_FORM_MODE_TEAM = 4 };
 

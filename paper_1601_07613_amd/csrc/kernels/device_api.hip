@@ -25,13 +25,14 @@ namespace {
 constexpr int kBlock = 256;
 
 // DGC_FORM_DEFAULT: the face-kernel form measured fastest for each element
-// type, order and precision (colored pass, ~1M elements): the team with
-// right-hand-side prefetch, except where its registers cost more than the
-// prefetch gains (f64 triangles p = 4, parallelograms p = 1 and 3: the team
-// without prefetch), the mode team for tetrahedra at p = 1, and for
-// tetrahedra at p = 2 one work-item per face in f64 (8-lane teams of 10
-// modes), the team with prefetch in f32
-int default_surface_form(int elem_type, int p, bool f32) {
+// type, order, precision and size (colored pass): the right-hand-side
+// prefetch pays only where the launches are large and the records small
+// (f64 triangles at p = 1, at p = 2 from 1M faces on; f32 triangles from
+// p = 3 on; parallelograms at p = 2); otherwise the team without prefetch
+// (its registers cost more occupancy than the prefetch hides).  Tetrahedra:
+// the mode team at p = 1; at p = 2 one work-item per face in f64 (8-lane
+// teams of 10 modes), the team with prefetch in f32.
+int default_surface_form(int elem_type, int p, bool f32, int64_t n_face) {
     if (elem_type == DGC_TET) {
         if (p == 1) return DGC_FORM_MODE_TEAM;
         if (p == 2) return f32 ? DGC_FORM_TEAM_PREFETCH : DGC_FORM_THREAD;
@@ -39,11 +40,15 @@ int default_surface_form(int elem_type, int p, bool f32) {
     }
     if (elem_type == DGC_QUAD || elem_type == DGC_MIXED)
         return (p == 1 || p == 3) ? DGC_FORM_TEAM : DGC_FORM_TEAM_PREFETCH;
-    return (p == 4 && !f32) ? DGC_FORM_TEAM : DGC_FORM_TEAM_PREFETCH;
+    if (f32) return p >= 3 ? DGC_FORM_TEAM_PREFETCH : DGC_FORM_TEAM;
+    if (p <= 1) return DGC_FORM_TEAM_PREFETCH;
+    if (p == 2) return n_face >= 1000000 ? DGC_FORM_TEAM_PREFETCH : DGC_FORM_TEAM;
+    return DGC_FORM_TEAM;
 }
 
 int resolved_surface_form(const dgc_dmesh *dm, bool f32) {
-    return dm->surf_form == DGC_FORM_DEFAULT ? default_surface_form(dm->elem_type, dm->p, f32) : dm->surf_form;
+    return dm->surf_form == DGC_FORM_DEFAULT ? default_surface_form(dm->elem_type, dm->p, f32, dm->n_face)
+                                             : dm->surf_form;
 }
 
 // DGC_VOL_DEFAULT: the volume form measured fastest for each element type,
