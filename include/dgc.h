@@ -322,12 +322,12 @@ typedef struct {
  * per stage; the volume term is then computed by the face team (lane =
  * variable, or lane = mode for tetrahedra at p = 1) whatever vol_form says.
  * Where its conditions fail it falls back to DGC_RK_FUSED.
- * DGC_RK_DEFAULT is DGC_RK_FUSED_VOLUME for triangles at p <= 3 and for
- * quadrilaterals when vol_form is DGC_VOL_DEFAULT (measured 4-18 % faster
- * per step on ~1M elements), and DGC_RK_FUSED otherwise (triangles at
- * p = 4, 5: the face kernel's registers run out; tetrahedra: no gain, the
- * face team evaluates the flux of the volume term on each of its four
- * lanes). */
+ * DGC_RK_DEFAULT is DGC_RK_FUSED_VOLUME for triangles at p <= 3, for
+ * quadrilaterals and for f64 tetrahedra at p = 1 when vol_form is
+ * DGC_VOL_DEFAULT (measured 2-18 % faster per step on ~1M elements), and
+ * DGC_RK_FUSED otherwise (triangles at p = 4, 5: the face kernel's
+ * registers run out; f32 tetrahedra: no gain, the face team evaluates the
+ * flux of the volume term on each of its four lanes). */
 enum { DGC_RK_DEFAULT = 0, DGC_RK_SEPARATE = 1, DGC_RK_FUSED = 2, DGC_RK_BLOCK = 3, DGC_RK_FUSED_VOLUME = 4 };
 
 /* Volume-kernel forms: DGC_VOL_VALU evaluates each element in one work-item

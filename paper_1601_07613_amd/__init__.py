@@ -198,8 +198,9 @@ class DeviceMesh:
         fused into the first color's face kernel ("fused_volume"); the
         combination as a separate kernel ("separate"); or the whole step in
         one work-group ("block", an alternative for small meshes, measured
-        slower).  "default" is "fused_volume" for triangles at p <= 3 and
-        quadrilaterals (with the default volume form), else "fused"."""
+        slower).  "default" is "fused_volume" for triangles at p <= 3,
+        quadrilaterals and f64 tetrahedra at p = 1 (with the default volume
+        form), else "fused"."""
         self.dm.rk_form = self.RK_FORMS[form]
 
     def set_volume_form(self, form: str = "default") -> None:

@@ -66,8 +66,12 @@ int default_volume_form(int elem_type, int p, bool f32) {
 
 // DGC_RK_DEFAULT fuses the volume term into the first color's face kernel
 // where the face team carries it without slowing the pass down (measured on
-// ~1M-element meshes)
-bool default_fuse_volume(int elem_type, int p) { return (elem_type == DGC_TRI && p <= 3) || elem_type == DGC_QUAD; }
+// ~1M-element meshes; tetrahedra at p = 1 in f64 only, the f32 form gains
+// nothing there)
+bool default_fuse_volume(int elem_type, int p, bool f32) {
+    if (elem_type == DGC_TET) return p == 1 && !f32;
+    return (elem_type == DGC_TRI && p <= 3) || elem_type == DGC_QUAD;
+}
 
 inline unsigned grid_for(int64_t n, int block = kBlock) { return (unsigned)((n + block - 1) / block); }
 
@@ -472,7 +476,7 @@ dgc_status dgc_rk_step(const dgc_dmesh *dm, double *U, double dt, int32_t varian
     const bool fuse_vol = one_face_per_color && vol_team_face &&
                           (dm->rk_form == DGC_RK_FUSED_VOLUME ||
                            (dm->rk_form == DGC_RK_DEFAULT && dm->vol_form == DGC_VOL_DEFAULT &&
-                            default_fuse_volume(dm->elem_type, dm->p)));
+                            default_fuse_volume(dm->elem_type, dm->p, shadow != nullptr)));
     const int first = fuse_vol ? 1 : 0;
     for (int stg = 0; stg < 3; ++stg) {
         const void *Uin = shadow ? static_cast<const void *>(shadow) : static_cast<const void *>(stage_in[stg]);
@@ -713,7 +717,10 @@ dgc_status dgc_batch_describe(int32_t n_mesh, const dgc_dmesh *meshes, double *c
                   d.color_off[fpe] > d.color_off[fpe - 1];
         }
         h.fuse_combine = one && precision == DGC_F64 ? 1 : 0;
-        h.fuse_volume = one && default_fuse_volume(h.elem_type, h.p) ? 1 : 0;
+        // (the batched fused volume term uses the variable team: not for the
+        // mode-team tetrahedra)
+        h.fuse_volume = one && h.elem_type != DGC_TET && default_fuse_volume(h.elem_type, h.p, precision == DGC_F32)
+                            ? 1 : 0;
     }
     h.tables = meshes[0].tables;
     h.off_trace = ti.off_trace;
