@@ -353,9 +353,10 @@ def main(argv=None):
     ap.add_argument("--tet-n", type=int, default=64)
     ap.add_argument("--p", type=int, default=None)
     ap.add_argument("--seed", type=int, default=2)
-    ap.add_argument("--only", choices=["all", "colored", "volume", "rk"], default="all",
+    ap.add_argument("--only", choices=["all", "colored", "volume", "rk", "batch"], default="all",
                     help="'colored' times the colored pass only, 'volume' the volume-term forms only, 'rk' the "
-                         "SSP-RK3 step forms only (for profiling)")
+                         "SSP-RK3 step forms only, 'batch' a batched SSP-RK3 step of 8 periodic meshes of "
+                         "125k triangles (for profiling)")
     ap.add_argument("--rk-form", choices=["default", "fused_volume", "fused", "separate"], default="default",
                     help="SSP-RK3 step form timed by --only rk")
     ap.add_argument("--form", choices=["auto", "default", "team", "team_prefetch", "thread"], default="auto",
@@ -396,6 +397,28 @@ def main(argv=None):
         return 0
 
     from paper_1601_07613_amd.tune import autotune, time_call
+
+    if args.only == "batch":
+        # 8 periodic jittered meshes of 250 x 250 x 2 triangles, one batch
+        p = 2 if args.p is None else args.p
+        prec = "f32"
+        members = []
+        for i in range(8):
+            mb = synth.periodic_tri(250, seed=10 + i)
+            Mb = dgc.Mesh.build(mb["elem_vert"], mb["elem_xyz"])
+            Mb.color(seed=i)
+            Db = dgc.DeviceMesh(Mb, p)
+            st = synth.density_wave_states(synth.element_centroid(mb["elem_xyz"]), vel=(0.5, 0.3))
+            Ub = synth.perturbed_dofs(synth.element_measure(mb["elem_xyz"]), st, Db.n_p, eps=0.01, seed=i)
+            members.append((Db, torch.from_numpy(Db.to_layout(Ub)).cuda(), Db.workspace("rk", "colored", prec),
+                            1e-5))
+        B = dgc.Batch(members, precision=prec)
+        t_ms = timed(B.rk_step, args.steps, args.warmup, torch.cuda.current_stream())[0]
+        K = sum(D.K for D, _, _, _ in members)
+        log("batched %s step, %d meshes, %d triangles, p = %d: %.1f us" % (prec, len(members), K, p, t_ms * 1e3))
+        print(json.dumps({"batched_rk3_step_us": t_ms * 1e3, "precision": prec, "n_mesh": len(members),
+                          "n_elem": K, "p": p}))
+        return 0
 
     t = time.perf_counter()
     if args.workload == "delaunay":
