@@ -6,8 +6,8 @@ each request's mesh while the GPU works.  A prepared request is admitted when
 its device footprint fits in the HBM budget (first come, first served; a
 request that can never fit is rejected).  Admitted requests of the same order
 p form one group; every iteration advances every group by one batched SSP-RK3
-step, so requests join and leave between steps and their work overlaps on
-the device.  A group whose membership changed steps with eager batched
+step (each group on a stream of its own, so groups overlap too), so requests
+join and leave between steps and their work overlaps on the device.  A group whose membership changed steps with eager batched
 launches; once its membership has held for a few steps its step is captured
 in a graph and replayed until the next change (a capture costs a warm-up
 and a synchronisation, which a membership that changes every few steps
@@ -227,6 +227,7 @@ class GPUExecutor:
         self.graphs = {}
         self.eager_steps = {}
         self.captures = 0
+        self.streams = {}  # one stream per group (default priority)
 
     # host work (worker threads): mesh, coloring, layout, initial DOFs, dt
     def prepare(self, r: Request) -> None:
@@ -276,17 +277,26 @@ class GPUExecutor:
         self.eager_steps[p] = 0
 
     def step_group(self, p, group) -> None:
-        g = self.graphs.get(p)
-        if g is not None:
-            g.replay()
-            return
-        B = self.batches[p]
-        B.rk_step()
-        self.eager_steps[p] += 1
-        if self.eager_steps[p] >= self.STABLE_STEPS:
-            # the kernels are loaded by now: capture without a warm-up stage
-            self.graphs[p] = B.capture(warm=False)
-            self.captures += 1
+        # each group steps on a stream of its own, so the groups of one
+        # iteration (different orders p) overlap on the device; the stream
+        # first waits for the uploads of newly admitted requests
+        torch = self.torch
+        s = self.streams.get(p)
+        if s is None:
+            s = self.streams[p] = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            g = self.graphs.get(p)
+            if g is not None:
+                g.replay()
+                return
+            B = self.batches[p]
+            B.rk_step()
+            self.eager_steps[p] += 1
+            if self.eager_steps[p] >= self.STABLE_STEPS:
+                # the kernels are loaded by now: capture without a warm-up stage
+                self.graphs[p] = B.capture(warm=False)
+                self.captures += 1
 
     def step_single(self, r: Request) -> None:
         D, U, ws, dt = r.dev
