@@ -475,10 +475,10 @@ dgc_status dgc_volume_rhs_batched(const void *host_desc, const void *dev_desc, i
  * number of meshes, so it can be captured once in a graph and replayed.
  * When every member has exactly one face of each color (conforming meshes
  * colored with as many colors as an element has faces), each stage is one
- * launch per color, the first also evaluating the volume term (triangles
- * p <= 3, quadrilaterals) and, in f64, the last writing the stage
- * combination, as the single-mesh DGC_RK_DEFAULT step; otherwise 3 x
- * (volume + one launch per color + combine). */
+ * launch per color, the first also evaluating the volume term where the
+ * single-mesh DGC_RK_DEFAULT step does (triangles p <= 3, quadrilaterals,
+ * f64 tetrahedra at p = 1) and, in f64, the last writing the stage
+ * combination; otherwise 3 x (volume + one launch per color + combine). */
 dgc_status dgc_rk_step_batched(const void *host_desc, const void *dev_desc, void *stream);
 
 /* Library build identification (static string). */

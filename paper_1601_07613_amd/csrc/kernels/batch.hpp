@@ -80,12 +80,17 @@ template <int DIM, int NP, int Q, int QV, int MODE, class T>
 __global__ __launch_bounds__(256) void batch_surface_kernel(const char *__restrict__ desc, int color, int stage) {
     constexpr int TEAM = batch_team<DIM, NP>();
     constexpr bool kMT = DIM == 3 && NP == 4;
-    static_assert(!(kMT && MODE == kVolume), "the batched fused volume term uses the variable team");
     const Header *h = bh(desc);
     extern __shared__ unsigned char smem_raw[];
     T *s_tr = reinterpret_cast<T *>(smem_raw);
     T *s_pr = s_tr + h->n_codes * Q * NP;
+    T *s_vb = s_pr + h->n_codes * Q * NP;  // mode team with the volume term: its tables follow
+    T *s_vd = s_vb + QV * NP;
     const double *tables = gptr(h->tables);
+    if constexpr (kMT && MODE == kVolume) {
+        for (int i = threadIdx.x; i < QV * NP; i += blockDim.x) s_vb[i] = T(tables[h->off_vb + i]);
+        for (int i = threadIdx.x; i < DIM * QV * NP; i += blockDim.x) s_vd[i] = T(tables[h->off_vd + i]);
+    }
     stage_tables<T>(s_tr, s_pr, tables + h->off_trace, tables + h->off_proj, h->n_codes * Q * NP);
     const int32_t m = reinterpret_cast<const int32_t *>(desc + h->off_map_face[color])[blockIdx.x];
     const Entry *e = bentry(desc, m);
@@ -105,9 +110,10 @@ __global__ __launch_bounds__(256) void batch_surface_kernel(const char *__restri
         cmb.dt = e->dt;
     }
     if constexpr (kMT)
-        mode_team_face<DIM, NP, Q, MODE, T, true>(k, threadIdx.x % TEAM, e->n_face, e->n_elem, mb.face_lr,
-                                                  mb.face_code, mb.face_geo, s_tr, s_pr, h->n_codes, in, rhs, nullptr,
-                                                  cmb);
+        mode_team_face<DIM, NP, Q, MODE, T, MODE != kVolume, QV>(k, threadIdx.x % TEAM, e->n_face, e->n_elem,
+                                                                 mb.face_lr, mb.face_code, mb.face_geo, s_tr, s_pr,
+                                                                 h->n_codes, in, rhs, nullptr, cmb, s_vb, s_vd,
+                                                                 mb.elem_geo);
     else
         team_face<DIM, NP, Q, MODE, T, MODE != kVolume, QV>(
             k, threadIdx.x % TEAM, e->n_face, e->n_elem, mb.face_lr, mb.face_code, mb.face_geo, s_tr, s_pr,

@@ -559,14 +559,12 @@ struct BatchImpl {
     template <int MODE>
     static dgc_status color(const dgc_batch::Header &h, const char *dev, int stage, int c, hipStream_t st) {
         if (h.nblk_face[c] == 0) return DGC_OK;
-        const size_t lds = 2 * (size_t)h.n_codes * Q * NP * sizeof(T);
-        if constexpr (MODE == dgc_dev::kVolume && DIM == 3 && NP == 4) {
-            return fail(DGC_E_UNSUPPORTED, "the batched fused volume term needs the variable team");
-        } else {
-            hipLaunchKernelGGL((dgc_dev::batch_surface_kernel<DIM, NP, Q, QV, MODE, T>), dim3(h.nblk_face[c]),
-                               dim3(h.block), lds, st, dev, c, stage);
-            return hip_check("batched surface launch");
-        }
+        size_t lds = 2 * (size_t)h.n_codes * Q * NP * sizeof(T);
+        // the mode team's fused volume term stages the volume tables too
+        if (MODE == dgc_dev::kVolume && DIM == 3 && NP == 4) lds += (size_t)(1 + DIM) * QV * NP * sizeof(T);
+        hipLaunchKernelGGL((dgc_dev::batch_surface_kernel<DIM, NP, Q, QV, MODE, T>), dim3(h.nblk_face[c]),
+                           dim3(h.block), lds, st, dev, c, stage);
+        return hip_check("batched surface launch");
     }
     static dgc_status surface(const dgc_batch::Header &h, const char *dev, int stage, hipStream_t st) {
         for (int c = 0; c < h.n_colors; ++c)
@@ -717,10 +715,7 @@ dgc_status dgc_batch_describe(int32_t n_mesh, const dgc_dmesh *meshes, double *c
                   d.color_off[fpe] > d.color_off[fpe - 1];
         }
         h.fuse_combine = one && precision == DGC_F64 ? 1 : 0;
-        // (the batched fused volume term uses the variable team: not for the
-        // mode-team tetrahedra)
-        h.fuse_volume = one && h.elem_type != DGC_TET && default_fuse_volume(h.elem_type, h.p, precision == DGC_F32)
-                            ? 1 : 0;
+        h.fuse_volume = one && default_fuse_volume(h.elem_type, h.p, precision == DGC_F32) ? 1 : 0;
     }
     h.tables = meshes[0].tables;
     h.off_trace = ti.off_trace;
