@@ -323,11 +323,14 @@ typedef struct {
  * variable, or lane = mode for tetrahedra at p = 1) whatever vol_form says.
  * Where its conditions fail it falls back to DGC_RK_FUSED.
  * DGC_RK_DEFAULT is DGC_RK_FUSED_VOLUME for triangles at p <= 3, for
- * quadrilaterals and for f64 tetrahedra at p = 1 when vol_form is
- * DGC_VOL_DEFAULT (measured 2-18 % faster per step on ~1M elements), and
+ * quadrilaterals (f32 only at p = 3) and for f64 tetrahedra at p = 1 when
+ * vol_form is DGC_VOL_DEFAULT (measured 2-18 % faster per step on ~1M
+ * elements), and
  * DGC_RK_FUSED otherwise (triangles at p = 4, 5: the face kernel's
  * registers run out; f32 tetrahedra: no gain, the face team evaluates the
- * flux of the volume term on each of its four lanes). */
+ * flux of the volume term on each of its four lanes), except for
+ * tetrahedra at p = 2, where the combination stays a kernel of its own (the
+ * combining team kernel runs out of registers). */
 enum { DGC_RK_DEFAULT = 0, DGC_RK_SEPARATE = 1, DGC_RK_FUSED = 2, DGC_RK_BLOCK = 3, DGC_RK_FUSED_VOLUME = 4 };
 
 /* Volume-kernel forms: DGC_VOL_VALU evaluates each element in one work-item
@@ -352,16 +355,19 @@ enum { DGC_VOL_DEFAULT = 0, DGC_VOL_VALU = 1, DGC_VOL_MFMA = 2, DGC_VOL_TEAM = 3
  * right-hand-side reads of the colored update issued before the flux
  * evaluation; DGC_FORM_THREAD gives each face one work-item;
  * DGC_FORM_MODE_TEAM (tetrahedra, p = 1) gives each face 4 lanes, one per
- * mode, and sums the traces across them.  DGC_FORM_DEFAULT picks the form
- * measured fastest for the element type, order, precision and size: the
- * team with prefetch for f64 triangles at p = 1 and at p = 2 from 1M faces
- * on, for f32 triangles at p >= 3 and for parallelograms (and mixed meshes)
- * at p = 0, 2; the team without prefetch for the other triangle and
- * parallelogram cases; the mode team for tetrahedra at p = 1; for
- * tetrahedra at p = 2 one work-item per face in f64, the team with
- * prefetch in f32. */
+ * mode, and sums the traces across them; DGC_FORM_TEAM_STREAM is the team
+ * visiting the quadrature points one at a time (trace, flux and projection
+ * per point), for large N_p x Q where the team runs out of registers (the
+ * plain colored, atomic and gather passes; the fused RK stages keep the
+ * team).  DGC_FORM_DEFAULT picks the form measured fastest for the element
+ * type, order, precision and size: the team with prefetch for f64
+ * triangles at p = 1 and at p = 2 from 1M faces on, for f32 triangles at
+ * p = 3, 4 and for parallelograms (and mixed meshes) at p = 0, 2; the
+ * streaming team for tetrahedra at p = 2, f64 triangles at p >= 3, f32
+ * triangles at p = 5 and f64 parallelograms at p = 3; the mode team for
+ * tetrahedra at p = 1; the team without prefetch otherwise. */
 enum { DGC_FORM_DEFAULT = 0, DGC_FORM_TEAM = 1, DGC_FORM_THREAD = 2, DGC_FORM_TEAM_PREFETCH = 3,
-       DGC_FORM_MODE_TEAM = 4 };
+       DGC_FORM_MODE_TEAM = 4, DGC_FORM_TEAM_STREAM = 5 };
 
 /* Volume term of Eq. (2): rhs = int F(U) . grad v (overwrites rhs).
  * U, rhs: device [n_elem][n_var][n_p] (f64, or f32 for DGC_F32). */

@@ -187,7 +187,7 @@ class DeviceMesh:
         dm.elem_kind = self.elem_kind.data_ptr() if self.elem_kind is not None else None
         self.dm = dm
 
-    FORMS = {"default": 0, "team": 1, "thread": 2, "team_prefetch": 3, "mode_team": 4}
+    FORMS = {"default": 0, "team": 1, "thread": 2, "team_prefetch": 3, "mode_team": 4, "team_stream": 5}
     VOL_FORMS = {"default": 0, "valu": 1, "mfma": 2, "team": 3}
 
     RK_FORMS = {"default": 0, "separate": 1, "fused": 2, "block": 3, "fused_volume": 4}
@@ -199,8 +199,9 @@ class DeviceMesh:
         combination as a separate kernel ("separate"); or the whole step in
         one work-group ("block", an alternative for small meshes, measured
         slower).  "default" is "fused_volume" for triangles at p <= 3,
-        quadrilaterals and f64 tetrahedra at p = 1 (with the default volume
-        form), else "fused"."""
+        quadrilaterals (f32 only at p = 3) and f64 tetrahedra at p = 1 (with
+        the default volume form), else "fused" (tetrahedra at p = 2:
+        "separate")."""
         self.dm.rk_form = self.RK_FORMS[form]
 
     def set_volume_form(self, form: str = "default") -> None:
@@ -211,8 +212,11 @@ class DeviceMesh:
         self.dm.vol_form = self.VOL_FORMS[form]
 
     def set_launch(self, form: str = "default", block: int = 0, xcd_remap: bool = False) -> None:
-        """Choose the face-kernel form (team of lanes per face, or one work-item
-        per face), the work-group size (0 = library default) and whether
+        """Choose the face-kernel form ("team" of lanes per face, with the
+        right-hand-side reads issued early "team_prefetch", visiting the
+        quadrature points one at a time "team_stream", lane = mode
+        "mode_team" for tetrahedra at p = 1, or one work-item per face
+        "thread"), the work-group size (0 = library default) and whether
         work-groups are remapped to contiguous face ranges per XCD."""
         self.dm.surf_form = self.FORMS[form]
         self.dm.block_size = int(block)

@@ -13,6 +13,7 @@
 #include "batch.hpp"
 #include "layout_dev.hpp"
 #include "surface.hpp"
+#include "surface_stream.hpp"
 #include "volume.hpp"
 #include "volume_mfma.hpp"
 #include "volume_team.hpp"
@@ -27,23 +28,25 @@ constexpr int kBlock = 256;
 // DGC_FORM_DEFAULT: the face-kernel form measured fastest for each element
 // type, order, precision and size (colored pass): the right-hand-side
 // prefetch pays only where the launches are large and the records small
-// (f64 triangles at p = 1, at p = 2 from 1M faces on; f32 triangles from
-// p = 3 on; parallelograms at p = 2); otherwise the team without prefetch
-// (its registers cost more occupancy than the prefetch hides).  Tetrahedra:
-// the mode team at p = 1; at p = 2 one work-item per face in f64 (8-lane
-// teams of 10 modes), the team with prefetch in f32.
+// (f64 triangles at p = 1, at p = 2 from 1M faces on; f32 triangles at
+// p = 3, 4; parallelograms at p = 2); the streaming team where N_p x Q is
+// large (tetrahedra at p = 2, f64 triangles from p = 3 on, f32 triangles at
+// p = 5, f64 parallelograms at p = 3: 9-35 % faster than the other forms);
+// otherwise the team without prefetch.  Tetrahedra at p = 1: the mode team.
 int default_surface_form(int elem_type, int p, bool f32, int64_t n_face) {
     if (elem_type == DGC_TET) {
         if (p == 1) return DGC_FORM_MODE_TEAM;
-        if (p == 2) return f32 ? DGC_FORM_TEAM_PREFETCH : DGC_FORM_THREAD;
+        if (p == 2) return DGC_FORM_TEAM_STREAM;
         return DGC_FORM_TEAM_PREFETCH;
     }
-    if (elem_type == DGC_QUAD || elem_type == DGC_MIXED)
-        return (p == 1 || p == 3) ? DGC_FORM_TEAM : DGC_FORM_TEAM_PREFETCH;
-    if (f32) return p >= 3 ? DGC_FORM_TEAM_PREFETCH : DGC_FORM_TEAM;
+    if (elem_type == DGC_QUAD || elem_type == DGC_MIXED) {
+        if (p == 3) return f32 ? DGC_FORM_TEAM : DGC_FORM_TEAM_STREAM;
+        return p == 1 ? DGC_FORM_TEAM : DGC_FORM_TEAM_PREFETCH;
+    }
+    if (f32) return p >= 5 ? DGC_FORM_TEAM_STREAM : (p >= 3 ? DGC_FORM_TEAM_PREFETCH : DGC_FORM_TEAM);
     if (p <= 1) return DGC_FORM_TEAM_PREFETCH;
     if (p == 2) return n_face >= 1000000 ? DGC_FORM_TEAM_PREFETCH : DGC_FORM_TEAM;
-    return DGC_FORM_TEAM;
+    return DGC_FORM_TEAM_STREAM;
 }
 
 int resolved_surface_form(const dgc_dmesh *dm, bool f32) {
@@ -65,12 +68,13 @@ int default_volume_form(int elem_type, int p, bool f32) {
 }
 
 // DGC_RK_DEFAULT fuses the volume term into the first color's face kernel
-// where the face team carries it without slowing the pass down (measured on
+// where the face team carries it without slowing the step down (measured on
 // ~1M-element meshes; tetrahedra at p = 1 in f64 only, the f32 form gains
-// nothing there)
+// nothing there; parallelograms at p = 3 in f32 only)
 bool default_fuse_volume(int elem_type, int p, bool f32) {
     if (elem_type == DGC_TET) return p == 1 && !f32;
-    return (elem_type == DGC_TRI && p <= 3) || elem_type == DGC_QUAD;
+    if (elem_type == DGC_QUAD) return p <= 2 || f32;  // f64 p = 3: the streaming colors win
+    return elem_type == DGC_TRI && p <= 3;
 }
 
 inline unsigned grid_for(int64_t n, int block = kBlock) { return (unsigned)((n + block - 1) / block); }
@@ -94,7 +98,7 @@ dgc_status check_dm(const dgc_dmesh *dm, dgc_table_info *ti) {
         return fail(DGC_E_ARG, "dgc_dmesh: bad element / face count");
     if (!dm->face_lr || !dm->face_code || !dm->face_geo || !dm->elem_geo || !dm->tables)
         return fail(DGC_E_ARG, "dgc_dmesh: null device array");
-    if (dm->surf_form < DGC_FORM_DEFAULT || dm->surf_form > DGC_FORM_MODE_TEAM)
+    if (dm->surf_form < DGC_FORM_DEFAULT || dm->surf_form > DGC_FORM_TEAM_STREAM)
         return fail(DGC_E_ARG, "dgc_dmesh: unknown surf_form");
     if (dm->elem_type == DGC_MIXED && !dm->elem_kind)
         return fail(DGC_E_ARG, "dgc_dmesh: a mixed mesh needs elem_kind");
@@ -172,6 +176,14 @@ struct Impl {
             }
         }
         if (form == DGC_FORM_MODE_TEAM) return fail(DGC_E_UNSUPPORTED, "mode teams need N_p = 4 in 3D");
+        if (form == DGC_FORM_TEAM_STREAM) {
+            constexpr int TEAM = DIM + 2 <= 4 ? 4 : 8;
+            hipLaunchKernelGGL((dgc_dev::surface_stream_kernel<DIM, NP, Q, MODE, T>),
+                               dim3(grid_for((f1 - f0) * TEAM, block)), dim3(block), lds, st, f0, f1, dm->n_face,
+                               dm->n_elem, dm->face_lr, dm->face_code, dm->face_geo, dm->tables + ti.off_trace,
+                               dm->tables + ti.off_proj, ti.n_codes, U, rhs, buf, dm->xcd_remap);
+            return hip_check("surface kernel launch");
+        }
         if (form == DGC_FORM_THREAD) {
             hipLaunchKernelGGL((dgc_dev::surface_kernel<DIM, NP, Q, MODE, T>), dim3(grid_for(f1 - f0, block)),
                                dim3(block), lds, st, f0, f1, dm->n_face, dm->n_elem, dm->face_lr, dm->face_code,
@@ -228,7 +240,7 @@ struct Impl {
                 return hip_check("fused volume and surface kernel launch");
             }
         }
-        if (form != DGC_FORM_TEAM && form != DGC_FORM_TEAM_PREFETCH)
+        if (form != DGC_FORM_TEAM && form != DGC_FORM_TEAM_PREFETCH && form != DGC_FORM_TEAM_STREAM)
             return fail(DGC_E_UNSUPPORTED, "the fused volume term needs a team face form");
         constexpr int TEAM = DIM + 2 <= 4 ? 4 : 8;
         hipLaunchKernelGGL((dgc_dev::surface_volume_kernel<DIM, NP, Q, QV, false, T>),
@@ -470,8 +482,12 @@ dgc_status dgc_rk_step(const dgc_dmesh *dm, double *U, double dt, int32_t varian
                                     sform != DGC_FORM_THREAD && dm->color_off[1] > dm->color_off[0];
     // (the f32 form keeps its combination kernel: measured faster than a fused
     // one, whose extra f64 reads cost the face kernel registers)
-    const bool fuse = !shadow && one_face_per_color && dm->rk_form != DGC_RK_SEPARATE;
+    // (not for tetrahedra from p = 2 on: the combining team kernel runs out of
+    // registers there and the separate combination is faster)
+    const bool fuse = !shadow && one_face_per_color && dm->rk_form != DGC_RK_SEPARATE &&
+                      !(dm->elem_type == DGC_TET && dm->p >= 2 && dm->rk_form == DGC_RK_DEFAULT);
     const bool vol_team_face = sform == DGC_FORM_TEAM || sform == DGC_FORM_TEAM_PREFETCH ||
+                               sform == DGC_FORM_TEAM_STREAM ||
                                (sform == DGC_FORM_MODE_TEAM && dm->elem_type == DGC_TET && dm->p == 1);
     const bool fuse_vol = one_face_per_color && vol_team_face &&
                           (dm->rk_form == DGC_RK_FUSED_VOLUME ||

@@ -446,6 +446,36 @@ def test_workspace_errors_on_device():
     assert float(rhs.abs().max()) == 0.0
 
 
+@pytest.mark.parametrize("kind,size,p", [("tets", 4, 2), ("periodic", 9, 4), ("delaunay", 1500, 5),
+                                         ("quadbox", 7, 3), ("delaunay", 2000, 2)])
+@pytest.mark.parametrize("variant", ["colored", "atomic", "gather"])
+def test_surface_stream_form(kind, size, p, variant):
+    """The streaming team form (quadrature points visited one at a time)
+    against the oracle, every variant, walls included."""
+    c = Case(kind, size, 23, p)
+    c.D.set_launch("team_stream")
+    got = c.to_host(c.surface(variant))
+    c.D.set_launch("default")
+    _check(got, dg.surface_rhs(c.d, c.U), dg.surface_abs(c.d, c.U), "stream %s" % variant)
+
+
+def test_surface_stream_form_f32():
+    import torch
+
+    c = Case("tets", 4, 24, 2)
+    U32 = c.U.astype(np.float32)
+    Ug = torch.from_numpy(c.D.to_layout(U32)).cuda()
+    rhs = torch.zeros_like(Ug)
+    c.D.set_launch("team_stream")
+    c.D.surface_rhs(Ug, rhs, variant="colored", precision="f32")
+    c.D.set_launch("default")
+    torch.cuda.synchronize()
+    U = U32.astype(np.float64)
+    tol = TOL32 * max(1.0, (c.D.n_p + c.D.tinfo["n_qf"]) / 9.0)
+    _check_tol(c.D.from_layout(rhs.cpu().numpy()).astype(np.float64), dg.surface_rhs(c.d, U),
+               dg.surface_abs(c.d, U), "stream f32", tol)
+
+
 @pytest.fixture(scope="module")
 def full_c1():
     """The full Delaunay workload (~500 k Poisson-disc points, ~1 M triangles, p = 2)."""
