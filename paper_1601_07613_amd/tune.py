@@ -13,11 +13,12 @@ from __future__ import annotations
 
 import itertools
 
-# "default" is the library's choice for the element type and order (team
-# with right-hand-side prefetch in 2D, mode team for tetrahedra at p = 1)
+# "default" is the library's choice for the element type, order, precision
+# and size; "team" and "team_stream" are the alternatives that can win on a
+# given mesh (the streaming team at large N_p x Q)
 DEFAULT_CANDIDATES = [
     {"form": f, "block": b, "xcd_remap": x}
-    for f, b, x in itertools.product(("default", "team"), (128, 256), (False, True))
+    for f, b, x in itertools.product(("default", "team", "team_stream"), (128, 256), (False, True))
 ]
 
 
