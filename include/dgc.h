@@ -101,7 +101,7 @@ typedef struct {
 } dgc_mesh_info_t;
 
 /* Build the face table and geometry of a conforming mesh (face-wise
- * connectivity, Section 5 "stored as pointers"; left/right elements,
+ * connectivity, Section 5 and Table 5a; left/right elements,
  * Section 3).
  *   elem_type  DGC_TRI (3 vertices, counter-clockwise, 2D), DGC_QUAD (4
  *              vertices, counter-clockwise, a parallelogram: the affine image

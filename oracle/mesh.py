@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE ONLY.
 
 The paper stores the mesh connectivity face-wise: each edge (face) points to
 the two elements that share it, its left and right element (Section 1 and
-Section 5, "Mesh connectivity is stored as pointers", Table 5a).  The
+Section 5, Table 5a).  The
 enumeration below is the reading used by this project (the paper gives
 none):
 

@@ -17,6 +17,7 @@ from .meshes import (  # noqa: F401
     hybrid_grid,
     quad_grid,
     refine_flags,
+    shuffle_elements,
 )
 from .fields import (  # noqa: F401
     shock_tube_states,

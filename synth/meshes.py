@@ -298,6 +298,22 @@ def kuhn_tets(n: int, jitter: float = 0.05, seed: int = 3, length: float = 1.0):
     return {"elem_vert": ev, "elem_xyz": xyz, "n_vert": n ** 3, "h": h, "periodic": True}
 
 
+def shuffle_elements(mesh: dict, seed: int) -> dict:
+    """The same mesh with its elements numbered in a seeded random order.
+
+    A mesh generator hands out element numbers in its own order; structured
+    generators (a grid scanned row by row, Qhull's output) number neighbours
+    close together, which lets a greedy pass in id order leave fewer
+    conflicts than on the paper's unstructured meshes.  A random numbering is
+    the stand-in for that order.  Vertex ids and coordinates are unchanged."""
+    perm = np.random.default_rng(seed).permutation(len(mesh["elem_vert"]))
+    out = dict(mesh)
+    out["elem_vert"] = np.ascontiguousarray(np.asarray(mesh["elem_vert"])[perm])
+    out["elem_xyz"] = np.ascontiguousarray(np.asarray(mesh["elem_xyz"])[perm])
+    out["elem_order"] = perm
+    return out
+
+
 def _tri_rows(elem_xyz, elem_vert):
     """Rows of a 4-slot 2D table that hold triangles (fourth vertex id -1)."""
     if elem_vert is None:

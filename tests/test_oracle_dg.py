@@ -85,6 +85,17 @@ def test_ssp_rk3_amplification():
     assert np.allclose(got, (1 + z + z * z / 2 + z ** 3 / 6) * u, rtol=1e-15, atol=0)
 
 
+def test_ssp_rk3_nonlinear_step_closed_form():
+    """One step of u' = u^2, u(0) = 1, dt = 0.1.  The Shu-Osher stages by hand:
+    u1 = 1.1, u2 = 3/4 + (1.1 + 0.121)/4 = 1.05525,
+    u3 = 1/3 + 2/3 (1.05525 + 0.1 * 1.05525^2) = 1.1110701708333...
+    Every three-stage third-order method has the same linear amplification
+    factor, so only a nonlinear right-hand side tells them apart: Kutta's
+    classical RK3 gives 1.1110920041666..."""
+    got = dg.ssp_rk3(lambda v: v * v, np.array([1.0]), 0.1)
+    assert abs(got[0] - 1.11107017083333333333333333333) < 4e-16
+
+
 def _wave(X, t):
     rho = 1.0 + 0.2 * np.sin(2 * np.pi * (X[:, 0] + X[:, 1] - 2.0 * t))
     return _conservative(rho, np.tile([1.0, 1.0], (len(X), 1)), np.ones(len(X)))
