@@ -24,7 +24,9 @@
  *   framework's caching allocator).  Device entry points only enqueue work on
  *   the given stream (a hipStream_t passed as void*, NULL = the null stream)
  *   and return; asynchronous faults surface at the caller's synchronisation.
- *   The library allocates no device memory and keeps no device state.
+ *   The library allocates no device memory; its only device state is the
+ *   fixed stage storage of dgc_rk_step_noalloc (DGC_NOALLOC_MAX_BYTES per
+ *   GPU, reserved when the library's code is loaded onto that GPU).
  * - Colors are 0-based (the paper's color c is color c-1 here).
  * - Element ids in device arrays are *layout* ids (after the renumbering of
  *   Section 5); DOF and right-hand-side arrays are indexed by layout ids.
@@ -398,6 +400,24 @@ dgc_status dgc_surface_rhs(const dgc_dmesh *dm, const void *U, void *rhs, int32_
  * DGC_E_NOT_COLORED, DGC_E_WORKSPACE, DGC_E_UNSUPPORTED, DGC_E_HIP. */
 dgc_status dgc_rk_step(const dgc_dmesh *dm, double *U, double dt, int32_t variant, int32_t precision,
                        void *ws, size_t ws_bytes, void *stream);
+
+/* dgc_rk_step for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same step, same kernels and same results as dgc_rk_step, with the
+ * stage states and right-hand side held in a device array of
+ * DGC_NOALLOC_MAX_BYTES bytes that the library keeps on every GPU it runs on
+ * until the process ends.  The array of the current device is used; `stream`
+ * must belong to that device.  Nothing in it needs to start at zero (every
+ * part is written before it is read).  Every call on one GPU shares that
+ * GPU's array, so calls that overlap on one GPU (two streams, two host
+ * threads) race: order them on one stream.  Allocates nothing, host or
+ * device.  Errors: as dgc_rk_step, and DGC_E_WORKSPACE when the step needs
+ * more than DGC_NOALLOC_MAX_BYTES (dgc_workspace_bytes, DGC_WS_RK_STEP: at
+ * p = 2 about 116k triangles in f64); DGC_E_HIP when the array's device
+ * address cannot be found. */
+#define DGC_NOALLOC_MAX_BYTES (64u << 20)
+dgc_status dgc_rk_step_noalloc(const dgc_dmesh *dm, double *U, double dt, int32_t variant, int32_t precision,
+                               void *stream);
 
 enum { DGC_WS_SURFACE = 0, DGC_WS_RK_STEP = 1 };
 

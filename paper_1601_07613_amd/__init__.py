@@ -322,6 +322,13 @@ class DeviceMesh:
                                   PRECISIONS[precision], ws.data_ptr(), ws.numel(), _stream_ptr(stream)),
                    "dgc_rk_step")
 
+    def rk_step_noalloc(self, U, dt: float, variant: str = "colored", precision: str = "f64", stream=None):
+        """``rk_step`` with the stage storage held by the library (no
+        workspace, no allocation; at most ``DGC_NOALLOC_MAX_BYTES`` of stage
+        storage; calls that overlap on one GPU race)."""
+        _lib.check(_L.dgc_rk_step_noalloc(C.byref(self.dm), U.data_ptr(), float(dt), VARIANTS[variant],
+                                          PRECISIONS[precision], _stream_ptr(stream)), "dgc_rk_step_noalloc")
+
 
 def child_colors(parent_colors, stream=None):
     """Child-edge colors of split elements computed on the device: parent

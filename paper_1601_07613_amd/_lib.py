@@ -15,6 +15,7 @@ DGC_MAX_COLORS = 8
 DGC_SURF_COLORED, DGC_SURF_ATOMIC, DGC_SURF_GATHER = 0, 1, 2
 DGC_F64, DGC_F32 = 0, 1
 DGC_WS_SURFACE, DGC_WS_RK_STEP = 0, 1
+DGC_NOALLOC_MAX_BYTES = 64 << 20
 DGC_FORM_DEFAULT, DGC_FORM_TEAM, DGC_FORM_THREAD = 0, 1, 2
 
 STATUS = {
@@ -95,6 +96,7 @@ _SIGS = {
                                   C.c_size_t, C.c_void_p]),
     "dgc_rk_step": (C.c_int, [C.POINTER(DMesh), C.c_void_p, C.c_double, C.c_int32, C.c_int32, C.c_void_p,
                               C.c_size_t, C.c_void_p]),
+    "dgc_rk_step_noalloc": (C.c_int, [C.POINTER(DMesh), C.c_void_p, C.c_double, C.c_int32, C.c_int32, C.c_void_p]),
     "dgc_workspace_bytes": (C.c_int, [C.POINTER(DMesh), C.c_int32, C.c_int32, C.c_int32,
                                       C.POINTER(C.c_size_t)]),
     "dgc_permute_records": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_int32,

@@ -7,6 +7,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "../batch_desc.hpp"
 #include "../host/internal.hpp"
@@ -546,6 +547,57 @@ dgc_status dgc_rk_step(const dgc_dmesh *dm, double *U, double dt, int32_t varian
         if ((s = hip_check("rk combine launch")) != DGC_OK) return s;
     }
     return DGC_OK;
+}
+
+// SSP-RK3 step without a caller workspace: the stage states and right-hand
+// side live in `scratch`, a device array of fixed size that every GPU holds
+// once (at its own address) until the process ends.  Host code never passes
+// the array's name to a kernel or a copy: it stands for a host-side shadow
+// there.  The device address is looked up once per device, with that device
+// current, and kept.
+static __device__ __align__(256) unsigned char scratch[DGC_NOALLOC_MAX_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+dgc_status scratch_address(void **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(DGC_E_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return fail(DGC_E_HIP, "device ordinal out of range: " + std::to_string(dev));
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(DGC_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return DGC_OK;
+}
+
+}  // namespace
+
+dgc_status dgc_rk_step_noalloc(const dgc_dmesh *dm, double *U, double dt, int32_t variant, int32_t precision,
+                               void *stream) {
+    dgc_table_info ti;
+    dgc_status s = check_dm(dm, &ti);
+    if (s != DGC_OK) return s;
+    if (!U) return fail(DGC_E_ARG, "dgc_rk_step_noalloc: null U");
+    size_t need = 0;
+    if ((s = dgc_workspace_bytes(dm, DGC_WS_RK_STEP, variant, precision, &need)) != DGC_OK) return s;
+    if (need > (size_t)DGC_NOALLOC_MAX_BYTES)
+        return fail(DGC_E_WORKSPACE, "dgc_rk_step_noalloc: this mesh needs " + std::to_string(need) +
+                                         " bytes of stage storage, more than the " +
+                                         std::to_string((size_t)DGC_NOALLOC_MAX_BYTES) +
+                                         " the library holds; call dgc_rk_step with a workspace");
+    void *ws = nullptr;
+    if ((s = scratch_address(&ws)) != DGC_OK) return s;
+    return dgc_rk_step(dm, U, dt, variant, precision, ws, (size_t)DGC_NOALLOC_MAX_BYTES, stream);
 }
 
 }  // extern "C"
