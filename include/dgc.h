@@ -276,7 +276,7 @@ dgc_status dgc_tables(int32_t elem_type, int32_t p, dgc_table_info *info, double
 /* Device entry points                                                     */
 /* ---------------------------------------------------------------------- */
 
-enum { DGC_SURF_COLORED = 0, DGC_SURF_ATOMIC = 1, DGC_SURF_GATHER = 2 };
+enum { DGC_SURF_COLORED = 0, DGC_SURF_ATOMIC = 1, DGC_SURF_GATHER = 2, DGC_SURF_COMPACT = 3 };
 enum { DGC_F64 = 0, DGC_F32 = 1 };
 
 /* Device view of one laid-out mesh at one order.  Every pointer is a device
@@ -361,7 +361,10 @@ enum { DGC_VOL_DEFAULT = 0, DGC_VOL_VALU = 1, DGC_VOL_MFMA = 2, DGC_VOL_TEAM = 3
  * visiting the quadrature points one at a time (trace, flux and projection
  * per point), for large N_p x Q where the team runs out of registers (the
  * plain colored, atomic and gather passes; the fused RK stages keep the
- * team).  DGC_FORM_DEFAULT picks the form measured fastest for the element
+ * team); DGC_FORM_PAIR_TEAM (tetrahedra, p = 1) gives each face 4 lanes that
+ * own two adjacent modes of two or three variables, so that records move in
+ * 16-byte pieces (the plain passes and the fused combination).
+ * DGC_FORM_DEFAULT picks the form measured fastest for the element
  * type, order, precision and size: the team with prefetch for f64
  * triangles at p = 1 and at p = 2 from 1M faces on, for f32 triangles at
  * p = 3, 4 and for parallelograms (and mixed meshes) at p = 0, 2; the
@@ -369,7 +372,7 @@ enum { DGC_VOL_DEFAULT = 0, DGC_VOL_VALU = 1, DGC_VOL_MFMA = 2, DGC_VOL_TEAM = 3
  * triangles at p = 5 and f64 parallelograms at p = 3; the mode team for
  * tetrahedra at p = 1; the team without prefetch otherwise. */
 enum { DGC_FORM_DEFAULT = 0, DGC_FORM_TEAM = 1, DGC_FORM_THREAD = 2, DGC_FORM_TEAM_PREFETCH = 3,
-       DGC_FORM_MODE_TEAM = 4, DGC_FORM_TEAM_STREAM = 5 };
+       DGC_FORM_MODE_TEAM = 4, DGC_FORM_TEAM_STREAM = 5, DGC_FORM_PAIR_TEAM = 6 };
 
 /* Volume term of Eq. (2): rhs = int F(U) . grad v (overwrites rhs).
  * U, rhs: device [n_elem][n_var][n_p] (f64, or f32 for DGC_F32). */
@@ -385,6 +388,12 @@ dgc_status dgc_volume_rhs(const dgc_dmesh *dm, const void *U, void *rhs, int32_t
  *   left / right contributions to slots 2j, 2j+1 of a workspace of
  *   2 * n_face * n_var * n_p values (the memory of Table 4), then a second
  *   kernel adds each element's slots to rhs.
+ * DGC_SURF_COMPACT: the buffer alternative of Section 1 with one record per
+ *   face instead of two element-sized slots: the face pass writes
+ *   |f| F*_q[m] at the Q face points (n_qf * n_var values) and the two
+ *   table codes, a workspace of n_face * (n_qf * n_var + 1) values; a second
+ *   kernel lets each element project the records of its faces (minus on its
+ *   left faces, plus on its right faces) and update its rhs once.
  * Errors: DGC_E_ARG, DGC_E_NOT_COLORED (COLORED without colors),
  * DGC_E_WORKSPACE, DGC_E_UNSUPPORTED, DGC_E_HIP (launch failure). */
 dgc_status dgc_surface_rhs(const dgc_dmesh *dm, const void *U, void *rhs, int32_t variant,

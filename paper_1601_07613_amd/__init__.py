@@ -16,13 +16,15 @@ import numpy as np
 from . import _lib
 from ._lib import (  # noqa: F401
     DGC_COLOR_GREEDY_STD, DGC_COLOR_PAPER, DGC_F32, DGC_F64, DGC_LAYOUT_NONE, DGC_LAYOUT_PAPER,
-    DGC_LAYOUT_PAPER_SFC, DGC_LAYOUT_RENUMBER, DGC_MIXED, DGC_QUAD, DGC_SURF_ATOMIC, DGC_SURF_COLORED, DGC_SURF_GATHER, DGC_TET,
+    DGC_LAYOUT_PAPER_SFC, DGC_LAYOUT_RENUMBER, DGC_MIXED, DGC_QUAD, DGC_SURF_ATOMIC, DGC_SURF_COLORED, DGC_SURF_COMPACT,
+    DGC_SURF_GATHER, DGC_TET,
     DGC_TRI, DgcError,
 )
 
 _L = _lib.load()
 
-VARIANTS = {"colored": DGC_SURF_COLORED, "atomic": DGC_SURF_ATOMIC, "gather": DGC_SURF_GATHER}
+VARIANTS = {"colored": DGC_SURF_COLORED, "atomic": DGC_SURF_ATOMIC, "gather": DGC_SURF_GATHER,
+            "compact": DGC_SURF_COMPACT}
 PRECISIONS = {"f64": DGC_F64, "f32": DGC_F32}
 LAYOUTS = {"paper": DGC_LAYOUT_PAPER, "renumber": DGC_LAYOUT_RENUMBER, "none": DGC_LAYOUT_NONE,
            "paper_sfc": DGC_LAYOUT_PAPER_SFC}
@@ -187,7 +189,8 @@ class DeviceMesh:
         dm.elem_kind = self.elem_kind.data_ptr() if self.elem_kind is not None else None
         self.dm = dm
 
-    FORMS = {"default": 0, "team": 1, "thread": 2, "team_prefetch": 3, "mode_team": 4, "team_stream": 5}
+    FORMS = {"default": 0, "team": 1, "thread": 2, "team_prefetch": 3, "mode_team": 4, "team_stream": 5,
+             "pair_team": 6}
     VOL_FORMS = {"default": 0, "valu": 1, "mfma": 2, "team": 3}
 
     RK_FORMS = {"default": 0, "separate": 1, "fused": 2, "block": 3, "fused_volume": 4}
@@ -347,6 +350,37 @@ def rk_workspace_layout(n: int, precision: str = "f64"):
     tot = C.c_size_t()
     _lib.check(_L.dgc_rk_workspace_layout(n, PRECISIONS[precision], off, C.byref(tot)), "dgc_rk_workspace_layout")
     return [int(x) for x in off], int(tot.value)
+
+
+def device_footprint(mesh: Mesh, p: int, precision: str = "f64", variant: str = "colored") -> int:
+    """Device bytes that ``DeviceMesh(mesh, p)``, one f64 state and its SSP-RK3
+    workspace (``precision``, ``variant``) occupy: the sizes the library
+    reports for every device array (face and element arrays, tables) and for
+    the stage storage, each rounded up to 512 bytes as device allocations are."""
+    info = mesh.info()
+    tinfo, _ = tables(info["elem_type"], p)
+
+    def rnd(b):
+        return (int(b) + 511) // 512 * 512
+
+    total = 0
+    names = ["dev_face_lr", "dev_face_code", "dev_face_geo", "dev_elem_geo", "dev_elem_slots"]
+    if info["elem_type"] == DGC_MIXED:
+        names.append("dev_elem_kind")
+    need = C.c_size_t()
+    for name in names:
+        _lib.check(_L.dgc_mesh_export(mesh._h, _lib.ARR[name][0], None, 0, C.byref(need)), "dgc_mesh_export")
+        total += rnd(need.value)
+    total += rnd(tinfo["total"] * 8)
+    n = info["n_elem"] * (info["dim"] + 2) * tinfo["n_p"]
+    total += rnd(n * 8)
+    _, ws = rk_workspace_layout(n, precision)
+    elt = 8 if precision == "f64" else 4
+    if variant == "gather":
+        ws += 2 * info["n_face"] * (info["dim"] + 2) * tinfo["n_p"] * elt
+    elif variant == "compact":
+        ws += info["n_face"] * (tinfo["n_qf"] * (info["dim"] + 2) + 1) * elt
+    return total + rnd(ws)
 
 
 class Batch:

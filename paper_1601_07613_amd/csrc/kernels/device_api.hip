@@ -14,6 +14,7 @@
 #include "batch.hpp"
 #include "layout_dev.hpp"
 #include "surface.hpp"
+#include "surface_pair.hpp"
 #include "surface_stream.hpp"
 #include "volume.hpp"
 #include "volume_mfma.hpp"
@@ -99,7 +100,7 @@ dgc_status check_dm(const dgc_dmesh *dm, dgc_table_info *ti) {
         return fail(DGC_E_ARG, "dgc_dmesh: bad element / face count");
     if (!dm->face_lr || !dm->face_code || !dm->face_geo || !dm->elem_geo || !dm->tables)
         return fail(DGC_E_ARG, "dgc_dmesh: null device array");
-    if (dm->surf_form < DGC_FORM_DEFAULT || dm->surf_form > DGC_FORM_TEAM_STREAM)
+    if (dm->surf_form < DGC_FORM_DEFAULT || dm->surf_form > DGC_FORM_PAIR_TEAM)
         return fail(DGC_E_ARG, "dgc_dmesh: unknown surf_form");
     if (dm->elem_type == DGC_MIXED && !dm->elem_kind)
         return fail(DGC_E_ARG, "dgc_dmesh: a mixed mesh needs elem_kind");
@@ -172,17 +173,28 @@ struct Impl {
                 hipLaunchKernelGGL((dgc_dev::surface_mode_team_kernel<DIM, NP, Q, MODE, T>),
                                    dim3(grid_for((f1 - f0) * 4, block)), dim3(block), lds, st, f0, f1, dm->n_face,
                                    dm->n_elem, dm->face_lr, dm->face_code, dm->face_geo, dm->tables + ti.off_trace,
-                                   dm->tables + ti.off_proj, ti.n_codes, U, rhs, buf, dm->xcd_remap);
+                                   dm->tables + ti.off_proj, ti.n_codes, U, rhs, buf, dm->xcd_remap, block);
                 return hip_check("surface kernel launch");
             }
         }
-        if (form == DGC_FORM_MODE_TEAM) return fail(DGC_E_UNSUPPORTED, "mode teams need N_p = 4 in 3D");
+        if constexpr (NP == 4 && DIM == 3 && Q == 3) {
+            // tetrahedra at p = 1: the pair team (4 lanes, 16-byte record pieces)
+            if (form == DGC_FORM_PAIR_TEAM) {
+                hipLaunchKernelGGL((dgc_dev::surface_pair_team_kernel<MODE, T>),
+                                   dim3(grid_for((f1 - f0) * 4, block)), dim3(block), lds, st, f0, f1, dm->n_face,
+                                   dm->n_elem, dm->face_lr, dm->face_code, dm->face_geo, dm->tables + ti.off_trace,
+                                   dm->tables + ti.off_proj, ti.n_codes, U, rhs, buf, dm->xcd_remap, block);
+                return hip_check("surface kernel launch");
+            }
+        }
+        if (form == DGC_FORM_MODE_TEAM || form == DGC_FORM_PAIR_TEAM)
+            return fail(DGC_E_UNSUPPORTED, "mode and pair teams need N_p = 4 in 3D");
         if (form == DGC_FORM_TEAM_STREAM) {
             constexpr int TEAM = DIM + 2 <= 4 ? 4 : 8;
             hipLaunchKernelGGL((dgc_dev::surface_stream_kernel<DIM, NP, Q, MODE, T>),
                                dim3(grid_for((f1 - f0) * TEAM, block)), dim3(block), lds, st, f0, f1, dm->n_face,
                                dm->n_elem, dm->face_lr, dm->face_code, dm->face_geo, dm->tables + ti.off_trace,
-                               dm->tables + ti.off_proj, ti.n_codes, U, rhs, buf, dm->xcd_remap);
+                               dm->tables + ti.off_proj, ti.n_codes, U, rhs, buf, dm->xcd_remap, block);
             return hip_check("surface kernel launch");
         }
         if (form == DGC_FORM_THREAD) {
@@ -196,12 +208,12 @@ struct Impl {
                 hipLaunchKernelGGL((dgc_dev::surface_team_kernel<DIM, NP, Q, MODE, T, true>),
                                    dim3(grid_for((f1 - f0) * TEAM, block)), dim3(block), lds, st, f0, f1, dm->n_face,
                                    dm->n_elem, dm->face_lr, dm->face_code, dm->face_geo, dm->tables + ti.off_trace,
-                                   dm->tables + ti.off_proj, ti.n_codes, U, rhs, buf, dm->xcd_remap);
+                                   dm->tables + ti.off_proj, ti.n_codes, U, rhs, buf, dm->xcd_remap, block);
             else
                 hipLaunchKernelGGL((dgc_dev::surface_team_kernel<DIM, NP, Q, MODE, T, false>),
                                    dim3(grid_for((f1 - f0) * TEAM, block)), dim3(block), lds, st, f0, f1, dm->n_face,
                                    dm->n_elem, dm->face_lr, dm->face_code, dm->face_geo, dm->tables + ti.off_trace,
-                                   dm->tables + ti.off_proj, ti.n_codes, U, rhs, buf, dm->xcd_remap);
+                                   dm->tables + ti.off_proj, ti.n_codes, U, rhs, buf, dm->xcd_remap, block);
         }
         return hip_check("surface kernel launch");
     }
@@ -237,7 +249,7 @@ struct Impl {
                 hipLaunchKernelGGL((dgc_dev::surface_volume_kernel<DIM, NP, Q, QV, true, T>),
                                    dim3(grid_for((f1 - f0) * 4, block)), dim3(block), lds_v, st, f0, f1, dm->n_face,
                                    dm->n_elem, dm->face_lr, dm->face_code, dm->face_geo, dm->tables + ti.off_trace,
-                                   dm->tables + ti.off_proj, ti.n_codes, U, rhs, va, dm->xcd_remap);
+                                   dm->tables + ti.off_proj, ti.n_codes, U, rhs, va, dm->xcd_remap, block);
                 return hip_check("fused volume and surface kernel launch");
             }
         }
@@ -247,7 +259,7 @@ struct Impl {
         hipLaunchKernelGGL((dgc_dev::surface_volume_kernel<DIM, NP, Q, QV, false, T>),
                            dim3(grid_for((f1 - f0) * TEAM, block)), dim3(block), lds, st, f0, f1, dm->n_face,
                            dm->n_elem, dm->face_lr, dm->face_code, dm->face_geo, dm->tables + ti.off_trace,
-                           dm->tables + ti.off_proj, ti.n_codes, U, rhs, va, dm->xcd_remap);
+                           dm->tables + ti.off_proj, ti.n_codes, U, rhs, va, dm->xcd_remap, block);
         return hip_check("fused volume and surface kernel launch");
     }
 
@@ -282,13 +294,13 @@ struct Impl {
                 hipLaunchKernelGGL((dgc_dev::surface_combine_kernel<DIM, NP, Q, kMT>),
                                    dim3(grid_for((f1 - f0) * 4, block)), dim3(block), lds, st, f0, f1, dm->n_face,
                                    dm->n_elem, dm->face_lr, dm->face_code, dm->face_geo, dm->tables + ti.off_trace,
-                                   dm->tables + ti.off_proj, ti.n_codes, U, rhs, cmb);
+                                   dm->tables + ti.off_proj, ti.n_codes, U, rhs, cmb, block);
             } else {
                 constexpr int TEAM = DIM + 2 <= 4 ? 4 : 8;
                 hipLaunchKernelGGL((dgc_dev::surface_combine_kernel<DIM, NP, Q, false>),
                                    dim3(grid_for((f1 - f0) * TEAM, block)), dim3(block), lds, st, f0, f1, dm->n_face,
                                    dm->n_elem, dm->face_lr, dm->face_code, dm->face_geo, dm->tables + ti.off_trace,
-                                   dm->tables + ti.off_proj, ti.n_codes, U, rhs, cmb);
+                                   dm->tables + ti.off_proj, ti.n_codes, U, rhs, cmb, block);
             }
             *fused = true;
             return hip_check("fused surface kernel launch");
@@ -315,6 +327,25 @@ struct Impl {
                 hipLaunchKernelGGL((dgc_dev::gather_kernel<DIM, NP, T>), dim3(grid_for(dm->n_elem)), dim3(kBlock), 0, st,
                                    dm->n_elem, dm->max_slots, 2 * dm->n_face, dm->elem_slots, buf, rhs);
                 return hip_check("gather kernel launch");
+            }
+            case DGC_SURF_COMPACT: {
+                const size_t need = (size_t)dm->n_face * dgc_dev::compact_stride<DIM, Q>() * sizeof(T);
+                if (!ws || ws_bytes < need)
+                    return fail(DGC_E_WORKSPACE, "COMPACT needs a workspace of " + std::to_string(need) + " bytes");
+                if (!dm->elem_slots || dm->max_slots <= 0) return fail(DGC_E_ARG, "COMPACT needs elem_slots");
+                T *buf = static_cast<T *>(ws);
+                constexpr int TEAM = DIM + 2 <= 4 ? 4 : 8;
+                const size_t lds = 2 * (size_t)ti.n_codes * Q * NP * sizeof(T);
+                hipLaunchKernelGGL((dgc_dev::surface_team_kernel<DIM, NP, Q, dgc_dev::kFlux, T, false>),
+                                   dim3(grid_for(dm->n_face * TEAM)), dim3(kBlock), lds, st, (int64_t)0, dm->n_face,
+                                   dm->n_face, dm->n_elem, dm->face_lr, dm->face_code, dm->face_geo,
+                                   dm->tables + ti.off_trace, dm->tables + ti.off_proj, ti.n_codes, U, rhs, buf, 0,
+                                   kBlock);
+                if ((s = hip_check("compact face pass launch")) != DGC_OK) return s;
+                hipLaunchKernelGGL((dgc_dev::compact_gather_kernel<DIM, NP, Q, T>), dim3(grid_for(dm->n_elem * TEAM)),
+                                   dim3(kBlock), lds / 2, st, dm->n_elem, dm->n_face, dm->max_slots, dm->elem_slots,
+                                   dm->elem_geo, dm->tables + ti.off_proj, ti.n_codes, buf, rhs);
+                return hip_check("compact gather launch");
             }
             default: return fail(DGC_E_ARG, "unknown surface variant");
         }
@@ -414,10 +445,12 @@ dgc_status dgc_workspace_bytes(const dgc_dmesh *dm, int32_t what, int32_t varian
     if (s != DGC_OK) return s;
     if (!bytes) return fail(DGC_E_ARG, "null bytes");
     if (precision != DGC_F64 && precision != DGC_F32) return fail(DGC_E_ARG, "unknown precision");
-    if (variant < DGC_SURF_COLORED || variant > DGC_SURF_GATHER) return fail(DGC_E_ARG, "unknown variant");
+    if (variant < DGC_SURF_COLORED || variant > DGC_SURF_COMPACT) return fail(DGC_E_ARG, "unknown variant");
     const size_t elt = precision == DGC_F64 ? 8 : 4;
     const size_t rec = rec_bytes(dm, elt);
-    const size_t surf = variant == DGC_SURF_GATHER ? 2 * (size_t)dm->n_face * rec : 0;
+    const size_t surf = variant == DGC_SURF_GATHER    ? 2 * (size_t)dm->n_face * rec
+                        : variant == DGC_SURF_COMPACT ? (size_t)dm->n_face * (dm->n_qf * dm->n_var + 1) * elt
+                                                      : 0;
     if (what == DGC_WS_SURFACE) {
         *bytes = surf;
         return DGC_OK;

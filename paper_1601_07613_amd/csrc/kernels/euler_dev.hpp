@@ -96,4 +96,53 @@ __device__ __forceinline__ void phys_flux(const T *u, T *Fx /* [M][DIM] */) {
     }
 }
 
+// Component r of the physical flux of the full state u, for the lane that
+// owns variable r (own = u[r]): F_r(u)_e = a u_{1+e} / rho + [r = 1 + e] p
+// with a = u_r, plus p for the energy; sel_e = [r = M - 1] and
+// sel_m[e] = [r = 1 + e] as 0/1 values.  The mass component comes out as
+// rho (u_{1+e} / rho) instead of u_{1+e} itself (a rounding apart).
+template <int DIM, class T>
+__device__ __forceinline__ void flux_component(const T *u, T own, T sel_e, const T *sel_m, T *Fr /* [DIM] */) {
+    constexpr int M = DIM + 2;
+    const T ir = dev_recip<T>(u[0]);
+    T ke = 0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) ke += u[1 + d] * u[1 + d];
+    const T p = T(kGamma - 1.0) * (u[M - 1] - T(0.5) * ke * ir);
+    const T a = own + sel_e * p;
+#pragma unroll
+    for (int e = 0; e < DIM; ++e) Fr[e] = a * (u[1 + e] * ir) + sel_m[e] * p;
+}
+
+// Component r of the Rusanov flux (same formula as rusanov) for the lane
+// that owns variable r: ownL / ownR are u_L[r] / u_R[r], n_r = n[r - 1] for
+// a momentum lane and 0 otherwise, sel_e = [r = M - 1].  Summed in the same
+// order as rusanov.
+template <int DIM, class T>
+__device__ __forceinline__ T rusanov_component(const T *uL, const T *uR, const T *n, T ownL, T ownR, T n_r,
+                                               T sel_e) {
+    constexpr int M = DIM + 2;
+    const T g1 = T(kGamma - 1.0);
+    const T irl = dev_recip<T>(uL[0]), irr = dev_recip<T>(uR[0]);
+    T unl = 0, unr = 0, kel = 0, ker = 0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        unl += uL[1 + d] * n[d];
+        unr += uR[1 + d] * n[d];
+        kel += uL[1 + d] * uL[1 + d];
+        ker += uR[1 + d] * uR[1 + d];
+    }
+    unl *= irl;
+    unr *= irr;
+    const T pl = g1 * (uL[M - 1] - T(0.5) * kel * irl);
+    const T pr = g1 * (uR[M - 1] - T(0.5) * ker * irr);
+    const T cl = dev_sqrt<T>(T(kGamma) * pl * irl);
+    const T cr = dev_sqrt<T>(T(kGamma) * pr * irr);
+    const T al = (unl < 0 ? -unl : unl) + cl;
+    const T ar = (unr < 0 ? -unr : unr) + cr;
+    const T lam = al > ar ? al : ar;
+    const T aL = ownL + sel_e * pl, aR = ownR + sel_e * pr;
+    return T(0.5) * (aL * unl + aR * unr + (pl + pr) * n_r) - T(0.5) * lam * (ownR - ownL);
+}
+
 }  // namespace dgc_dev

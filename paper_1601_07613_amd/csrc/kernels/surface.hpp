@@ -27,7 +27,18 @@
 
 namespace dgc_dev {
 
-enum { kColored = 0, kAtomic = 1, kGather = 2, kCombine = 3, kVolume = 4 };
+enum { kColored = 0, kAtomic = 1, kGather = 2, kCombine = 3, kVolume = 4, kFlux = 5 };
+
+// Compact buffered variant (kFlux): the face pass stores, per face k, the
+// record  |f| F*_q[m]  (q < Q, m < M, point-major) followed by one slot that
+// carries the two table codes (left | right << 8) as raw bits; a second pass
+// lets every element project the records of its faces.
+template <int DIM, int Q>
+constexpr int compact_stride() { return Q * (DIM + 2) + 1; }
+__device__ __forceinline__ double pack_codes(double, int c) { return __hiloint2double(0, c); }
+__device__ __forceinline__ float pack_codes(float, int c) { return __int_as_float(c); }
+__device__ __forceinline__ int unpack_codes(double v) { return __double2loint(v); }
+__device__ __forceinline__ int unpack_codes(float v) { return __float_as_int(v); }
 
 // First color of a stage with the volume term fused in: on a conforming
 // mesh every element has exactly one face of every color, so the first
@@ -195,42 +206,62 @@ __global__ __launch_bounds__(256) void surface_kernel(
     }
 }
 
+// Callback a face routine runs after it has issued every memory read of its
+// face and before it uses the LDS tables: the kernels stage their tables
+// there (and meet at the work-group barrier), so that the table reads, the
+// face's header reads and its record reads are in flight together instead of
+// one after the other.  Every thread of the work-group must reach it.
+struct NoMid {
+    __device__ __forceinline__ void operator()() const {}
+};
+
 // Team form of the face work: TEAM lanes per face (4 for M = 4, 8 for
 // M = 5); lane r < M owns conserved variable r.  Each lane reads and
 // updates the NP modes of its variable, so one load instruction of a team
 // touches one contiguous stretch of the element record instead of one
 // record per lane.  The traces of all variables are exchanged inside the
-// team and every lane evaluates the flux of the full state; lane r then
-// projects component r.  Same arithmetic and accumulation modes as
-// surface_kernel.
-template <int DIM, int NP, int Q, int MODE, class T, bool PREFETCH, int QV = 1>
+// team; every lane evaluates component r of the flux of the full state
+// (rusanov_component: the shared wave speeds and pressures, no selection
+// among the components) and projects it.  Same formulas and accumulation
+// modes as surface_kernel.  A thread whose face is not `active` (beyond the
+// launch's range) or is malformed (ids or codes out of range) reads nothing,
+// takes part in `mid` and returns.
+template <int DIM, int NP, int Q, int MODE, class T, bool PREFETCH, int QV = 1, class Mid = NoMid>
 __device__ __forceinline__ void team_face(
     int64_t k, int r, int64_t n_face, int64_t n_elem,
     const int32_t *__restrict__ face_lr, const uint8_t *__restrict__ face_code,
     const double *__restrict__ face_geo, const T *__restrict__ s_tr, const T *__restrict__ s_pr, int n_codes,
     const T *__restrict__ U, T *__restrict__ rhs, T *__restrict__ buf, const CombineArgs &cmb = CombineArgs{},
-    const VolArgs &va = VolArgs{}) {
+    const VolArgs &va = VolArgs{}, bool active = true, const Mid &mid = Mid{}) {
     constexpr int M = DIM + 2;
     constexpr int REC = M * NP;
     constexpr int TEAM = M <= 4 ? 4 : 8;
     constexpr bool RMW = MODE == kColored || MODE == kCombine;
-    const int32_t L = face_lr[k];
-    const int32_t R = face_lr[n_face + k];
-    const int cL = face_code[k];
-    const int cR = face_code[n_face + k];
-    if (L < 0 || L >= n_elem || R >= n_elem || cL >= n_codes || cR >= n_codes) return;
+    int32_t L = -1, R = -1;
+    int cL = 0, cR = 0;
     T n[DIM];
+    double len = 0, isL = 0, isR = 0;
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) n[d] = T(face_geo[d * n_face + k]);
-    const double len = face_geo[DIM * n_face + k];
-    const double isL = face_geo[(DIM + 1) * n_face + k];
-    const double isR = face_geo[(DIM + 2) * n_face + k];
+    for (int d = 0; d < DIM; ++d) n[d] = 0;
+    if (active) {
+        L = face_lr[k];
+        R = face_lr[n_face + k];
+        cL = face_code[k];
+        cR = face_code[n_face + k];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) n[d] = T(face_geo[d * n_face + k]);
+        len = face_geo[DIM * n_face + k];
+        isL = face_geo[(DIM + 1) * n_face + k];
+        isR = face_geo[(DIM + 2) * n_face + k];
+    }
+    const bool ok = active && L >= 0 && L < n_elem && R < n_elem && cL < n_codes && cR < n_codes;
     const bool own = r < M;
+    const bool rd = ok && own;
 
-    // optionally issue the right-hand-side reads of a colored update up front,
-    // so that they are in flight together with the DOF reads
+    // the right-hand-side reads of a colored update are issued up front with
+    // the DOF reads (PREFETCH)
     T pre_L[NP], pre_R[NP];
-    if (PREFETCH && RMW && own) {
+    if (PREFETCH && RMW && rd) {
         const T *a = rhs + (size_t)L * REC + r * NP;
 #pragma unroll
         for (int j = 0; j < NP; ++j) pre_L[j] = a[j];
@@ -242,7 +273,7 @@ __device__ __forceinline__ void team_face(
     }
     // the stage-0 state of a fused combination (kCombine with x set)
     T xL[NP], xR[NP];
-    if (MODE == kCombine && cmb.x && own) {
+    if (MODE == kCombine && cmb.x && rd) {
         const double *a = cmb.x + (size_t)L * REC + r * NP;
 #pragma unroll
         for (int j = 0; j < NP; ++j) xL[j] = T(a[j]);
@@ -252,28 +283,41 @@ __device__ __forceinline__ void team_face(
             for (int j = 0; j < NP; ++j) xR[j] = T(b[j]);
         }
     }
-
-    // my variable's traces on both sides
-    T tL[Q], tR[Q];
+    // my variable's modes on both sides (zero on lanes that own none)
     T cL_[NP], cR_[NP];
-    // the volume term of both elements, my variable (kVolume)
-    T vL[NP], vR[NP];
-    if constexpr (MODE == kVolume) {
+#pragma unroll
+    for (int j = 0; j < NP; ++j) cL_[j] = cR_[j] = T(0);
+    if (rd) {
         const T *uL = U + (size_t)L * REC + r * NP;
 #pragma unroll
-        for (int j = 0; j < NP; ++j) cL_[j] = own ? uL[j] : T(0);
+        for (int j = 0; j < NP; ++j) cL_[j] = uL[j];
         if (R >= 0) {
             const T *uR = U + (size_t)R * REC + r * NP;
 #pragma unroll
-            for (int j = 0; j < NP; ++j) cR_[j] = own ? uR[j] : T(0);
+            for (int j = 0; j < NP; ++j) cR_[j] = uR[j];
         }
-        volume_team_core<DIM, NP, QV, T>(L, r, n_elem, va.elem_geo, va.vb, va.vd, cL_, vL);
-        if (R >= 0) volume_team_core<DIM, NP, QV, T>(R, r, n_elem, va.elem_geo, va.vb, va.vd, cR_, vR);
     }
+    // the geometry of both elements for the fused volume term (kVolume)
+    T JiL[DIM * DIM], JiR[DIM * DIM];
+    double sqL = 1, sqR = 1;
+    if constexpr (MODE == kVolume) {
+        if (ok) {
+            load_elem_geo<DIM, T>(L, n_elem, va.elem_geo, JiL, sqL);
+            if (R >= 0) load_elem_geo<DIM, T>(R, n_elem, va.elem_geo, JiR, sqR);
+        }
+    }
+    mid();
+    if (!ok) return;
+
+    // the volume term of both elements, my variable (kVolume)
+    T vL[NP], vR[NP];
+    if constexpr (MODE == kVolume) {
+        volume_team_core_geo<DIM, NP, QV, T>(r, JiL, sqL, va.vb, va.vd, cL_, vL);
+        if (R >= 0) volume_team_core_geo<DIM, NP, QV, T>(r, JiR, sqR, va.vb, va.vd, cR_, vR);
+    }
+    // my variable's traces on both sides
+    T tL[Q], tR[Q];
     {
-        const T *uL = U + (size_t)L * REC + r * NP;
-#pragma unroll
-        for (int j = 0; j < NP; ++j) cL_[j] = own ? uL[j] : T(0);
         const T *tl = s_tr + cL * Q * NP;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
@@ -284,9 +328,6 @@ __device__ __forceinline__ void team_face(
         }
     }
     if (R >= 0) {
-        const T *uR = U + (size_t)R * REC + r * NP;
-#pragma unroll
-        for (int j = 0; j < NP; ++j) cR_[j] = own ? uR[j] : T(0);
         const T *tr = s_tr + cR * Q * NP;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
@@ -297,26 +338,38 @@ __device__ __forceinline__ void team_face(
         }
     }
 
-    // full states at every point, flux of the full state, my component
+    // full states at every point, my component of their flux
+    T n_r = 0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) n_r = r == 1 + d ? n[d] : n_r;
+    const T sel_e = r == M - 1 ? T(1) : T(0);
     T Fm[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        T uLq[M], uRq[M], F[M];
+        T uLq[M], uRq[M];
 #pragma unroll
         for (int m = 0; m < M; ++m) uLq[m] = team_bcast<TEAM>(tL[q], m);
+        T ownR;
         if (R >= 0) {
 #pragma unroll
             for (int m = 0; m < M; ++m) uRq[m] = team_bcast<TEAM>(tR[q], m);
+            ownR = tR[q];
         } else {
             wall_ghost<DIM, T>(uLq, n, uRq);
-        }
-        rusanov<DIM, T>(uLq, uRq, n, F);
-        T f = F[0];
+            ownR = uRq[0];
 #pragma unroll
-        for (int m = 1; m < M; ++m) f = r == m ? F[m] : f;
-        Fm[q] = f;
+            for (int m = 1; m < M; ++m) ownR = r == m ? uRq[m] : ownR;
+        }
+        Fm[q] = rusanov_component<DIM, T>(uLq, uRq, n, tL[q], ownR, n_r, sel_e);
     }
     if (!own) return;
+    if constexpr (MODE == kFlux) {
+        T *rec = buf + (size_t)k * compact_stride<DIM, Q>();
+#pragma unroll
+        for (int q = 0; q < Q; ++q) rec[q * M + r] = Fm[q] * T(len);
+        if (r == 0) rec[Q * M] = pack_codes(T(0), cL | (R >= 0 ? cR : 0xFF) << 8);
+        return;
+    }
 
     {
         const T sL = T(len * isL);
@@ -365,31 +418,39 @@ __device__ __forceinline__ void team_face(
 // j projects onto mode j.  Loads and stores of one record are 4 consecutive
 // values per instruction, and no lane idles (the variable-per-lane team
 // would need 8 lanes for M = 5).
-template <int DIM, int NP, int Q, int MODE, class T, bool PREFETCH, int QV = 1>
+template <int DIM, int NP, int Q, int MODE, class T, bool PREFETCH, int QV = 1, class Mid = NoMid>
 __device__ __forceinline__ void mode_team_face(
     int64_t k, int j, int64_t n_face, int64_t n_elem,
     const int32_t *__restrict__ face_lr, const uint8_t *__restrict__ face_code,
     const double *__restrict__ face_geo, const T *__restrict__ s_tr, const T *__restrict__ s_pr, int n_codes,
     const T *__restrict__ U, T *__restrict__ rhs, T *__restrict__ buf, const CombineArgs &cmb = CombineArgs{},
-    const T *__restrict__ s_vb = nullptr, const T *__restrict__ s_vd = nullptr, const double *elem_geo = nullptr) {
+    const T *__restrict__ s_vb = nullptr, const T *__restrict__ s_vd = nullptr, const double *elem_geo = nullptr,
+    bool active = true, const Mid &mid = Mid{}) {
     static_assert(NP == 4, "mode teams need exactly four modes");
     constexpr int M = DIM + 2;
     constexpr int REC = M * NP;
     constexpr bool RMW = MODE == kColored || MODE == kCombine;
-    const int32_t L = face_lr[k];
-    const int32_t R = face_lr[n_face + k];
-    const int cL = face_code[k];
-    const int cR = face_code[n_face + k];
-    if (L < 0 || L >= n_elem || R >= n_elem || cL >= n_codes || cR >= n_codes) return;
+    int32_t L = -1, R = -1;
+    int cL = 0, cR = 0;
     T n[DIM];
+    double len = 0, isL = 0, isR = 0;
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) n[d] = T(face_geo[d * n_face + k]);
-    const double len = face_geo[DIM * n_face + k];
-    const double isL = face_geo[(DIM + 1) * n_face + k];
-    const double isR = face_geo[(DIM + 2) * n_face + k];
+    for (int d = 0; d < DIM; ++d) n[d] = 0;
+    if (active) {
+        L = face_lr[k];
+        R = face_lr[n_face + k];
+        cL = face_code[k];
+        cR = face_code[n_face + k];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) n[d] = T(face_geo[d * n_face + k]);
+        len = face_geo[DIM * n_face + k];
+        isL = face_geo[(DIM + 1) * n_face + k];
+        isR = face_geo[(DIM + 2) * n_face + k];
+    }
+    const bool ok = active && L >= 0 && L < n_elem && R < n_elem && cL < n_codes && cR < n_codes;
 
     T pre_L[M], pre_R[M];
-    if (PREFETCH && RMW) {
+    if (PREFETCH && RMW && ok) {
 #pragma unroll
         for (int m = 0; m < M; ++m) pre_L[m] = rhs[(size_t)L * REC + m * NP + j];
         if (R >= 0) {
@@ -399,7 +460,7 @@ __device__ __forceinline__ void mode_team_face(
     }
     // the stage-0 state of a fused combination (kCombine with x set)
     T xL[M], xR[M];
-    if (MODE == kCombine && cmb.x) {
+    if (MODE == kCombine && cmb.x && ok) {
 #pragma unroll
         for (int m = 0; m < M; ++m) xL[m] = T(cmb.x[(size_t)L * REC + m * NP + j]);
         if (R >= 0) {
@@ -407,23 +468,38 @@ __device__ __forceinline__ void mode_team_face(
             for (int m = 0; m < M; ++m) xR[m] = T(cmb.x[(size_t)R * REC + m * NP + j]);
         }
     }
-    T uL[Q][M], uR[Q][M];
+    // my mode of every variable on both sides
     T cL_[M], cR_[M];
-    // the volume term of both elements, my mode (kVolume; tables in LDS)
-    T vL[M], vR[M];
-    if constexpr (MODE == kVolume) {
+#pragma unroll
+    for (int m = 0; m < M; ++m) cL_[m] = cR_[m] = T(0);
+    if (ok) {
 #pragma unroll
         for (int m = 0; m < M; ++m) cL_[m] = U[(size_t)L * REC + m * NP + j];
         if (R >= 0) {
 #pragma unroll
             for (int m = 0; m < M; ++m) cR_[m] = U[(size_t)R * REC + m * NP + j];
         }
-        volume_mode_team_core<DIM, NP, QV, T, T>(L, j, n_elem, elem_geo, s_vb, s_vd, cL_, vL);
-        if (R >= 0) volume_mode_team_core<DIM, NP, QV, T, T>(R, j, n_elem, elem_geo, s_vb, s_vd, cR_, vR);
+    }
+    // the geometry of both elements for the fused volume term (kVolume)
+    T JiL[DIM * DIM], JiR[DIM * DIM];
+    double sqL = 1, sqR = 1;
+    if constexpr (MODE == kVolume) {
+        if (ok) {
+            load_elem_geo<DIM, T>(L, n_elem, elem_geo, JiL, sqL);
+            if (R >= 0) load_elem_geo<DIM, T>(R, n_elem, elem_geo, JiR, sqR);
+        }
+    }
+    mid();
+    if (!ok) return;
+
+    T uL[Q][M], uR[Q][M];
+    // the volume term of both elements, my mode (kVolume; tables in LDS)
+    T vL[M], vR[M];
+    if constexpr (MODE == kVolume) {
+        volume_mode_team_core_geo<DIM, NP, QV, T, T>(j, JiL, sqL, s_vb, s_vd, cL_, vL);
+        if (R >= 0) volume_mode_team_core_geo<DIM, NP, QV, T, T>(j, JiR, sqR, s_vb, s_vd, cR_, vR);
     }
     {
-#pragma unroll
-        for (int m = 0; m < M; ++m) cL_[m] = U[(size_t)L * REC + m * NP + j];
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const T t = s_tr[(cL * Q + q) * NP + j];
@@ -432,8 +508,6 @@ __device__ __forceinline__ void mode_team_face(
         }
     }
     if (R >= 0) {
-#pragma unroll
-        for (int m = 0; m < M; ++m) cR_[m] = U[(size_t)R * REC + m * NP + j];
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const T t = s_tr[(cR * Q + q) * NP + j];
@@ -496,23 +570,73 @@ __device__ __forceinline__ void stage_tables(T *s_tr, T *s_pr, const double *__r
     __syncthreads();
 }
 
+// The same staging in two halves, for kernels that issue their face reads
+// in between: issue() reads this thread's share of the tables into
+// registers (when both tables fit in KT values per thread of a work-group
+// of `block` threads), store() writes them to LDS (or copies the tables
+// there itself when they did not fit) and meets the work-group barrier.
+// Issuing the table reads first keeps them ahead of the face reads, so the
+// wait for the tables does not wait for the records too.  s_pr must follow
+// s_tr directly in LDS.
+template <class T, int KT = 4>
+struct TableStage {
+    double v[KT];
+    int ntab, block;
+    bool fits;
+
+    __device__ __forceinline__ void issue(const double *__restrict__ tab_trace, const double *__restrict__ tab_proj,
+                                          int ntab_, int block_) {
+        ntab = ntab_;
+        block = block_;
+        fits = 2 * ntab <= KT * block;
+        if (fits) {
+#pragma unroll
+            for (int i = 0; i < KT; ++i) {
+                const int idx = (int)threadIdx.x + i * block;
+                if (idx < 2 * ntab) v[i] = idx < ntab ? tab_trace[idx] : tab_proj[idx - ntab];
+            }
+        }
+    }
+    __device__ __forceinline__ void store(T *s_tr, const double *__restrict__ tab_trace,
+                                          const double *__restrict__ tab_proj) const {
+        if (fits) {
+#pragma unroll
+            for (int i = 0; i < KT; ++i) {
+                const int idx = (int)threadIdx.x + i * block;
+                if (idx < 2 * ntab) s_tr[idx] = T(v[i]);
+            }
+        } else {
+            for (int i = threadIdx.x; i < ntab; i += block) {
+                s_tr[i] = T(tab_trace[i]);
+                s_tr[ntab + i] = T(tab_proj[i]);
+            }
+        }
+        __syncthreads();
+    }
+};
+
+// One launch of the team form over faces [f_begin, f_end) in work-groups of
+// `block` threads (the launch's block size): the table reads, then the face
+// reads are issued, the tables are staged in LDS while the face's records
+// are in flight, and the teams beyond f_end only take part in the barrier.
 template <int DIM, int NP, int Q, int MODE, class T, bool PREFETCH>
 __global__ __launch_bounds__(256) void surface_team_kernel(
     int64_t f_begin, int64_t f_end, int64_t n_face, int64_t n_elem,
     const int32_t *__restrict__ face_lr, const uint8_t *__restrict__ face_code,
     const double *__restrict__ face_geo, const double *__restrict__ tab_trace,
     const double *__restrict__ tab_proj, int n_codes,
-    const T *__restrict__ U, T *__restrict__ rhs, T *__restrict__ buf, int remap) {
+    const T *__restrict__ U, T *__restrict__ rhs, T *__restrict__ buf, int remap, int block) {
     constexpr int TEAM = DIM + 2 <= 4 ? 4 : 8;
     extern __shared__ unsigned char smem_raw[];
     T *s_tr = reinterpret_cast<T *>(smem_raw);
     T *s_pr = s_tr + n_codes * Q * NP;
-    stage_tables<T>(s_tr, s_pr, tab_trace, tab_proj, n_codes * Q * NP);
+    TableStage<T> tabs;
+    tabs.issue(tab_trace, tab_proj, n_codes * Q * NP, block);
     const int r = threadIdx.x % TEAM;
-    const int64_t k = f_begin + ((int64_t)logical_block(remap) * blockDim.x + threadIdx.x) / TEAM;
-    if (k >= f_end) return;  // whole teams leave together
+    const int64_t k = f_begin + ((int64_t)logical_block(remap) * block + threadIdx.x) / TEAM;
     team_face<DIM, NP, Q, MODE, T, PREFETCH>(k, r, n_face, n_elem, face_lr, face_code, face_geo, s_tr, s_pr, n_codes,
-                                             U, rhs, buf);
+                                             U, rhs, buf, CombineArgs{}, VolArgs{}, k < f_end,
+                                             [&] { tabs.store(s_tr, tab_trace, tab_proj); });
 }
 
 template <int DIM, int NP, int Q, int MODE, class T>
@@ -521,15 +645,16 @@ __global__ __launch_bounds__(256) void surface_mode_team_kernel(
     const int32_t *__restrict__ face_lr, const uint8_t *__restrict__ face_code,
     const double *__restrict__ face_geo, const double *__restrict__ tab_trace,
     const double *__restrict__ tab_proj, int n_codes,
-    const T *__restrict__ U, T *__restrict__ rhs, T *__restrict__ buf, int remap) {
+    const T *__restrict__ U, T *__restrict__ rhs, T *__restrict__ buf, int remap, int block) {
     extern __shared__ unsigned char smem_raw[];
     T *s_tr = reinterpret_cast<T *>(smem_raw);
     T *s_pr = s_tr + n_codes * Q * NP;
-    stage_tables<T>(s_tr, s_pr, tab_trace, tab_proj, n_codes * Q * NP);
-    const int64_t k = f_begin + ((int64_t)logical_block(remap) * blockDim.x + threadIdx.x) / 4;
-    if (k >= f_end) return;  // whole quads leave together
+    TableStage<T> tabs;
+    tabs.issue(tab_trace, tab_proj, n_codes * Q * NP, block);
+    const int64_t k = f_begin + ((int64_t)logical_block(remap) * block + threadIdx.x) / 4;
     mode_team_face<DIM, NP, Q, MODE, T, true>(k, threadIdx.x % 4, n_face, n_elem, face_lr, face_code, face_geo,
-                                              s_tr, s_pr, n_codes, U, rhs, buf);
+                                              s_tr, s_pr, n_codes, U, rhs, buf, CombineArgs{}, nullptr, nullptr,
+                                              nullptr, k < f_end, [&] { tabs.store(s_tr, tab_trace, tab_proj); });
 }
 
 // Last color of an SSP-RK3 stage with the stage combination fused in (see
@@ -540,20 +665,23 @@ __global__ __launch_bounds__(256) void surface_combine_kernel(
     const int32_t *__restrict__ face_lr, const uint8_t *__restrict__ face_code,
     const double *__restrict__ face_geo, const double *__restrict__ tab_trace,
     const double *__restrict__ tab_proj, int n_codes,
-    const double *__restrict__ U, double *__restrict__ rhs, CombineArgs cmb) {
+    const double *__restrict__ U, double *__restrict__ rhs, CombineArgs cmb, int block) {
     constexpr int TEAM = MT ? 4 : (DIM + 2 <= 4 ? 4 : 8);
     extern __shared__ unsigned char smem_raw[];
     double *s_tr = reinterpret_cast<double *>(smem_raw);
     double *s_pr = s_tr + n_codes * Q * NP;
-    stage_tables<double>(s_tr, s_pr, tab_trace, tab_proj, n_codes * Q * NP);
-    const int64_t k = f_begin + ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / TEAM;
-    if (k >= f_end) return;  // whole teams leave together
+    TableStage<double> tabs;
+    tabs.issue(tab_trace, tab_proj, n_codes * Q * NP, block);
+    const int64_t k = f_begin + ((int64_t)blockIdx.x * block + threadIdx.x) / TEAM;
+    auto mid = [&] { tabs.store(s_tr, tab_trace, tab_proj); };
     if constexpr (MT)
         mode_team_face<DIM, NP, Q, kCombine, double, true>(k, threadIdx.x % 4, n_face, n_elem, face_lr, face_code,
-                                                            face_geo, s_tr, s_pr, n_codes, U, rhs, nullptr, cmb);
+                                                            face_geo, s_tr, s_pr, n_codes, U, rhs, nullptr, cmb,
+                                                            nullptr, nullptr, nullptr, k < f_end, mid);
     else
         team_face<DIM, NP, Q, kCombine, double, true>(k, threadIdx.x % TEAM, n_face, n_elem, face_lr, face_code,
-                                                       face_geo, s_tr, s_pr, n_codes, U, rhs, nullptr, cmb);
+                                                       face_geo, s_tr, s_pr, n_codes, U, rhs, nullptr, cmb,
+                                                       VolArgs{}, k < f_end, mid);
 }
 
 // First color of a stage with the volume term fused in (see VolArgs): the
@@ -565,30 +693,81 @@ __global__ __launch_bounds__(256) void surface_volume_kernel(
     const int32_t *__restrict__ face_lr, const uint8_t *__restrict__ face_code,
     const double *__restrict__ face_geo, const double *__restrict__ tab_trace,
     const double *__restrict__ tab_proj, int n_codes,
-    const T *__restrict__ U, T *__restrict__ rhs, VolArgs va, int remap) {
+    const T *__restrict__ U, T *__restrict__ rhs, VolArgs va, int remap, int block) {
     constexpr int TEAM = MT ? 4 : (DIM + 2 <= 4 ? 4 : 8);
     extern __shared__ unsigned char smem_raw[];
     T *s_tr = reinterpret_cast<T *>(smem_raw);
     T *s_pr = s_tr + n_codes * Q * NP;
+    TableStage<T> tabs;
+    tabs.issue(tab_trace, tab_proj, n_codes * Q * NP, block);
+    const int64_t k = f_begin + ((int64_t)logical_block(remap) * block + threadIdx.x) / TEAM;
     if constexpr (MT) {
         T *s_vb = s_pr + n_codes * Q * NP;
         T *s_vd = s_vb + QV * NP;
-        for (int i = threadIdx.x; i < QV * NP; i += blockDim.x) s_vb[i] = T(va.vb[i]);
-        for (int i = threadIdx.x; i < DIM * QV * NP; i += blockDim.x) s_vd[i] = T(va.vd[i]);
-        stage_tables<T>(s_tr, s_pr, tab_trace, tab_proj, n_codes * Q * NP);  // its barrier covers both
-        const int64_t k = f_begin + ((int64_t)logical_block(remap) * blockDim.x + threadIdx.x) / 4;
-        if (k >= f_end) return;  // whole quads leave together
-        mode_team_face<DIM, NP, Q, kVolume, T, false, QV>(k, threadIdx.x % 4, n_face, n_elem, face_lr, face_code,
-                                                          face_geo, s_tr, s_pr, n_codes, U, rhs, nullptr,
-                                                          CombineArgs{}, s_vb, s_vd, va.elem_geo);
+        mode_team_face<DIM, NP, Q, kVolume, T, false, QV>(
+            k, threadIdx.x % 4, n_face, n_elem, face_lr, face_code, face_geo, s_tr, s_pr, n_codes, U, rhs, nullptr,
+            CombineArgs{}, s_vb, s_vd, va.elem_geo, k < f_end, [&] {
+                for (int i = threadIdx.x; i < QV * NP; i += block) s_vb[i] = T(va.vb[i]);
+                for (int i = threadIdx.x; i < DIM * QV * NP; i += block) s_vd[i] = T(va.vd[i]);
+                tabs.store(s_tr, tab_trace, tab_proj);  // its barrier covers the volume tables too
+            });
     } else {
-        stage_tables<T>(s_tr, s_pr, tab_trace, tab_proj, n_codes * Q * NP);
-        const int64_t k = f_begin + ((int64_t)logical_block(remap) * blockDim.x + threadIdx.x) / TEAM;
-        if (k >= f_end) return;  // whole teams leave together
         team_face<DIM, NP, Q, kVolume, T, false, QV>(k, threadIdx.x % TEAM, n_face, n_elem, face_lr, face_code,
                                                      face_geo, s_tr, s_pr, n_codes, U, rhs, nullptr, CombineArgs{},
-                                                     va);
+                                                     va, k < f_end, [&] { tabs.store(s_tr, tab_trace, tab_proj); });
     }
+}
+
+// Second pass of the compact buffered variant: element k (a team of lanes,
+// lane r < M owning variable r) visits its faces through elem_slots
+// (2 * face + side), reads the face's record (|f| F*_q of its variable and
+// the side's table code) and adds  -/+ (1/sqrt(det J_k)) sum_q proj[code][q][j] |f| F*_q
+// (minus on the left side, plus on the right) to its right-hand side, which
+// it reads and writes once.  The projection tables are staged in LDS.
+template <int DIM, int NP, int Q, class T>
+__global__ __launch_bounds__(256) void compact_gather_kernel(
+    int64_t n_elem, int64_t n_face, int max_slots, const int32_t *__restrict__ elem_slots,
+    const double *__restrict__ elem_geo, const double *__restrict__ tab_proj, int n_codes,
+    const T *__restrict__ flux, T *__restrict__ rhs) {
+    constexpr int M = DIM + 2;
+    constexpr int REC = M * NP;
+    constexpr int TEAM = M <= 4 ? 4 : 8;
+    constexpr int RS = compact_stride<DIM, Q>();
+    extern __shared__ unsigned char smem_raw[];
+    T *s_pr = reinterpret_cast<T *>(smem_raw);
+    for (int i = threadIdx.x; i < n_codes * Q * NP; i += blockDim.x) s_pr[i] = T(tab_proj[i]);
+    __syncthreads();
+    const int r = threadIdx.x % TEAM;
+    const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / TEAM;
+    if (k >= n_elem || r >= M) return;
+    const T isq = T(1.0 / elem_geo[(size_t)DIM * DIM * n_elem + k]);
+    T *dst = rhs + (size_t)k * REC + r * NP;
+    T acc[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) acc[j] = dst[j];
+    for (int s = 0; s < max_slots; ++s) {
+        const int32_t slot = elem_slots[(int64_t)s * n_elem + k];
+        if (slot < 0 || slot >= 2 * n_face) continue;
+        const int64_t f = slot >> 1;
+        const int side = slot & 1;
+        const T *rec = flux + (size_t)f * RS;
+        T F[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) F[q] = rec[q * M + r];
+        const int code = (unpack_codes(rec[Q * M]) >> (8 * side)) & 0xFF;
+        if (code >= n_codes) continue;
+        const T *pr = s_pr + code * Q * NP;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            T a = 0;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) a += pr[q * NP + j] * F[q];
+            a *= isq;
+            acc[j] = side ? acc[j] + a : acc[j] - a;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NP; ++j) dst[j] = acc[j];
 }
 
 // Second pass of the buffered variant: rhs[k] += sum of element k's slots.

@@ -5,10 +5,12 @@
 // record as one contiguous stretch), forms its variable's value at every
 // volume point, and the team exchanges the values (DPP quad broadcasts, or
 // ds_bpermute for 8-lane teams) so that every lane holds the full state.
-// Every lane evaluates the flux of the full state and keeps its own
-// component; the contravariant flux and the projection onto the modes are
-// then lane-local, and lane r writes its variable's N_p modes of the result.
-// Same arithmetic as volume_elem, in the same order.
+// Every lane evaluates only its own component of the flux (the shared
+// pressure and velocity, then one product per direction, no selection among
+// the components); the contravariant flux and the projection onto the modes
+// are lane-local (fused multiply-adds into the accumulators), and lane r
+// writes its variable's N_p modes of the result.  Same formulas as
+// volume_elem; the products are rounded in a different order.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -39,21 +41,32 @@ __host__ __device__ constexpr int batch_volume_lanes(int dim, int np, bool f32) 
 // 122 registers at N_p = 6; two points per trip at N_p = 21).
 __host__ __device__ constexpr int team_volume_unroll(int np) { return np >= 21 ? 2 : 1; }
 
-// Lane r's share of element k's volume term: c holds the element's modes of
-// variable r (zeros on lanes r >= M), out receives the result for variable r
-// (all lanes of the team must call; the tables may live in global memory
-// (f64) or in LDS).
-template <int DIM, int NP, int QV, class T, class TAB = double, int UNR = team_volume_unroll(NP)>
-__device__ __forceinline__ void volume_team_core(int64_t k, int r, int64_t n_elem,
-                                                 const double *__restrict__ elem_geo, const TAB *__restrict__ vb,
-                                                 const TAB *__restrict__ vd, const T (&c)[NP], T (&out)[NP]) {
-    constexpr int M = DIM + 2;
-    constexpr int TEAM = volume_team_size<DIM>();
-    T Ji[DIM * DIM];
+// Element k's inverse Jacobian (row-major) and sqrt(det J).
+template <int DIM, class T>
+__device__ __forceinline__ void load_elem_geo(int64_t k, int64_t n_elem, const double *__restrict__ elem_geo,
+                                              T (&Ji)[DIM * DIM], double &sq) {
 #pragma unroll
     for (int a = 0; a < DIM * DIM; ++a) Ji[a] = T(elem_geo[a * n_elem + k]);
-    const double sq = elem_geo[DIM * DIM * n_elem + k];
+    sq = elem_geo[DIM * DIM * n_elem + k];
+}
+
+// Lane r's share of an element's volume term from its geometry (Ji, sq): c
+// holds the element's modes of variable r (zeros on lanes r >= M), out
+// receives the result for variable r (all lanes of the team must call; the
+// tables may live in global memory (f64) or in LDS).
+template <int DIM, int NP, int QV, class T, class TAB = double, int UNR = team_volume_unroll(NP)>
+__device__ __forceinline__ void volume_team_core_geo(int r, const T (&Ji)[DIM * DIM], double sq,
+                                                     const TAB *__restrict__ vb, const TAB *__restrict__ vd,
+                                                     const T (&c)[NP], T (&out)[NP]) {
+    constexpr int M = DIM + 2;
+    constexpr int TEAM = volume_team_size<DIM>();
     const T isq = T(1.0 / sq);
+    // this lane's share of the physical flux F_r(u) = a u_e / rho + [r = 1 + e] p,
+    // a = u_r (+ p for the energy): 0/1 selectors fixed per lane
+    const T sel_e = r == M - 1 ? T(1) : T(0);
+    T sel_m[DIM];
+#pragma unroll
+    for (int e = 0; e < DIM; ++e) sel_m[e] = r == 1 + e ? T(1) : T(0);
     T acc[NP];
 #pragma unroll
     for (int j = 0; j < NP; ++j) acc[j] = 0;
@@ -62,19 +75,12 @@ __device__ __forceinline__ void volume_team_core(int64_t k, int r, int64_t n_ele
         T t = 0;
 #pragma unroll
         for (int j = 0; j < NP; ++j) t += T(vb[q * NP + j]) * c[j];
+        const T own = t * isq;
         T uq[M];
 #pragma unroll
-        for (int m = 0; m < M; ++m) uq[m] = team_bcast<TEAM>(t * isq, m);
-        T Fx[M * DIM];
-        phys_flux<DIM, T>(uq, Fx);
+        for (int m = 0; m < M; ++m) uq[m] = team_bcast<TEAM>(own, m);
         T Fm[DIM];
-#pragma unroll
-        for (int e = 0; e < DIM; ++e) {
-            T f = Fx[e];
-#pragma unroll
-            for (int m = 1; m < M; ++m) f = r == m ? Fx[m * DIM + e] : f;
-            Fm[e] = f;
-        }
+        flux_component<DIM, T>(uq, own, sel_e, sel_m, Fm);
         T G[DIM];
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
@@ -85,14 +91,23 @@ __device__ __forceinline__ void volume_team_core(int64_t k, int r, int64_t n_ele
         }
 #pragma unroll
         for (int j = 0; j < NP; ++j) {
-            T a = 0;
 #pragma unroll
-            for (int d = 0; d < DIM; ++d) a += T(vd[(d * QV + q) * NP + j]) * G[d];
-            acc[j] += a;
+            for (int d = 0; d < DIM; ++d) acc[j] = __builtin_fma(T(vd[(d * QV + q) * NP + j]), G[d], acc[j]);
         }
     }
 #pragma unroll
     for (int j = 0; j < NP; ++j) out[j] = acc[j] * T(sq);
+}
+
+// the same for element k, its geometry read here
+template <int DIM, int NP, int QV, class T, class TAB = double, int UNR = team_volume_unroll(NP)>
+__device__ __forceinline__ void volume_team_core(int64_t k, int r, int64_t n_elem,
+                                                 const double *__restrict__ elem_geo, const TAB *__restrict__ vb,
+                                                 const TAB *__restrict__ vd, const T (&c)[NP], T (&out)[NP]) {
+    T Ji[DIM * DIM];
+    double sq;
+    load_elem_geo<DIM, T>(k, n_elem, elem_geo, Ji, sq);
+    volume_team_core_geo<DIM, NP, QV, T, TAB, UNR>(r, Ji, sq, vb, vd, c, out);
 }
 
 // element k, lane r of its team (all lanes of the team must call)
@@ -124,16 +139,11 @@ __device__ __forceinline__ void volume_team_elem(int64_t k, int r, int64_t n_ele
 // flux, but needs the whole record and all 20 projections in every lane:
 // more than twice the registers.)  All four lanes of the quad must call.
 template <int DIM, int NP, int QV, class T, class TAB = double>
-__device__ __forceinline__ void volume_mode_team_core(int64_t k, int j, int64_t n_elem,
-                                                      const double *__restrict__ elem_geo, const TAB *__restrict__ vb,
-                                                      const TAB *__restrict__ vd, const T (&c)[DIM + 2],
-                                                      T (&out)[DIM + 2]) {
+__device__ __forceinline__ void volume_mode_team_core_geo(int j, const T (&Ji)[DIM * DIM], double sq,
+                                                          const TAB *__restrict__ vb, const TAB *__restrict__ vd,
+                                                          const T (&c)[DIM + 2], T (&out)[DIM + 2]) {
     static_assert(NP == 4, "mode teams need exactly four modes");
     constexpr int M = DIM + 2;
-    T Ji[DIM * DIM];
-#pragma unroll
-    for (int a = 0; a < DIM * DIM; ++a) Ji[a] = T(elem_geo[a * n_elem + k]);
-    const double sq = elem_geo[DIM * DIM * n_elem + k];
     const T isq = T(1.0 / sq);
     T acc[M];
 #pragma unroll
@@ -164,6 +174,18 @@ __device__ __forceinline__ void volume_mode_team_core(int64_t k, int j, int64_t 
     }
 #pragma unroll
     for (int m = 0; m < M; ++m) out[m] = acc[m] * T(sq);
+}
+
+// the same for element k, its geometry read here
+template <int DIM, int NP, int QV, class T, class TAB = double>
+__device__ __forceinline__ void volume_mode_team_core(int64_t k, int j, int64_t n_elem,
+                                                      const double *__restrict__ elem_geo, const TAB *__restrict__ vb,
+                                                      const TAB *__restrict__ vd, const T (&c)[DIM + 2],
+                                                      T (&out)[DIM + 2]) {
+    T Ji[DIM * DIM];
+    double sq;
+    load_elem_geo<DIM, T>(k, n_elem, elem_geo, Ji, sq);
+    volume_mode_team_core_geo<DIM, NP, QV, T, TAB>(j, Ji, sq, vb, vd, c, out);
 }
 
 template <int DIM, int NP, int QV, class T>

@@ -22,6 +22,17 @@ DEFAULT_CANDIDATES = [
 ]
 
 
+def candidates_for(dmesh):
+    """The launch candidates for this mesh: the common ones, and for
+    tetrahedra at p = 1 the pair team too (the default there is the mode
+    team)."""
+    cands = list(DEFAULT_CANDIDATES)
+    if dmesh.dim == 3 and dmesh.p == 1:
+        cands += [{"form": "pair_team", "block": b, "xcd_remap": x}
+                  for b, x in itertools.product((128, 256), (False, True))]
+    return cands
+
+
 def time_call(fn, reps: int = 20, warmup: int = 3) -> float:
     """Average milliseconds of ``fn()`` over ``reps`` calls on the current stream."""
     import torch
@@ -43,8 +54,8 @@ def autotune(dmesh, U, rhs, variant: str = "colored", precision: str = "f64", ca
              warmup: int = 3):
     """Pick the fastest launch configuration of ``dmesh.surface_rhs`` for these
     arrays; returns ``(best, [(config, ms), ...])`` and leaves ``best`` installed."""
-    cands = candidates or DEFAULT_CANDIDATES
-    ws = dmesh.workspace("surface", variant, precision) if variant == "gather" else None
+    cands = candidates or candidates_for(dmesh)
+    ws = dmesh.workspace("surface", variant, precision) if variant in ("gather", "compact") else None
     results = []
     for c in cands:
         dmesh.set_launch(c["form"], c["block"], c.get("xcd_remap", False))

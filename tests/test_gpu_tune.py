@@ -28,22 +28,25 @@ def _mesh(kind, size, seed, p):
 def test_autotune_surface_launch(kind, size, p):
     import torch
 
-    from paper_1601_07613_amd.tune import DEFAULT_CANDIDATES, autotune
+    from paper_1601_07613_amd.tune import DEFAULT_CANDIDATES, autotune, candidates_for
 
     D, Ug = _mesh(kind, size, 31, p)
+    cands = candidates_for(D)
+    # tetrahedra at p = 1 also try the pair team
+    assert len(cands) == len(DEFAULT_CANDIDATES) + (4 if kind == "tets" else 0)
     ref = torch.zeros_like(Ug)
     D.set_launch("default")
     D.surface_rhs(Ug, ref)
     rhs = torch.zeros_like(Ug)
     best, results = autotune(D, Ug, rhs, reps=3, warmup=1)
-    assert best in DEFAULT_CANDIDATES and len(results) == len(DEFAULT_CANDIDATES)
+    assert best in cands and len(results) == len(cands)
     assert all(ms > 0 for _, ms in results)
     assert best == min(results, key=lambda r: r[1])[0]
     got = torch.zeros_like(Ug)
     D.surface_rhs(Ug, got)  # the installed launch
     torch.cuda.synchronize()
-    # the same arithmetic up to the order of the trace sums (mode team vs
-    # variable team for tetrahedra)
+    # the same arithmetic up to the order of the trace sums (mode, pair and
+    # variable teams for tetrahedra)
     scale = ref.abs().max().item()
     assert (got - ref).abs().max().item() <= 1e-12 * scale
     D.set_launch("default")
