@@ -12,7 +12,9 @@ launches; once its membership has held for a few steps its step is captured
 in a graph and replayed until the next change (a capture costs a warm-up
 and a synchronisation, which a membership that changes every few steps
 would pay over and over).  Finished requests free their memory for the next
-admission.  A request whose result is not finite fails alone.
+admission: their group's batch and graph, which reference every member's
+arrays, are dropped before the next admission and rebuilt for the members
+that remain.  A request whose result is not finite fails alone.
 
 ``mode="sequential"`` is the plain baseline: one request at a time, each
 advanced by the single-mesh f64 step without batching or graphs.
@@ -193,6 +195,13 @@ class Server:
                             st.failed += 1
                         dirty.add(p)
                     active[p] = keep
+                    if p in dirty and self.mode == "batched":
+                        # the group's batch and graph still reference the
+                        # finished members' arrays: free them before the next
+                        # admission counts their bytes as available
+                        drop = getattr(self.ex, "drop_group", None)
+                        if drop is not None:
+                            drop(p)
             st.makespan = clock.now() - (reqs[0].arrival if reqs else 0.0)
             st.graph_captures = int(getattr(self.ex, "captures", 0))
         finally:
@@ -229,31 +238,17 @@ class GPUExecutor:
         self.captures = 0
         self.streams = {}  # one stream per group (default priority)
 
-    # host work (worker threads): mesh, coloring, layout, initial DOFs, dt
+    # host work (worker threads): mesh, coloring, layout, initial DOFs; the
+    # request supplies its time step, the library the device footprint
     def prepare(self, r: Request) -> None:
         import synth.requests as sreq
 
         m, U0 = sreq.request_input(r.spec)
+        dt = sreq.request_dt(r.spec, m, cfl=self.cfl)
         M = self.dgc.Mesh.build(m["elem_vert"], m["elem_xyz"])
         M.color(seed=self.seed)
-        xyz = m["elem_xyz"]
-        area = 0.5 * np.abs((xyz[:, 1, 0] - xyz[:, 0, 0]) * (xyz[:, 2, 1] - xyz[:, 0, 1])
-                            - (xyz[:, 2, 0] - xyz[:, 0, 0]) * (xyz[:, 1, 1] - xyz[:, 0, 1]))
-        per = sum(np.linalg.norm(xyz[:, (k + 1) % 3] - xyz[:, k], axis=1) for k in range(3))
-        mean = U0[:, :, 0] / np.sqrt(area)[:, None]
-        rho = mean[:, 0]
-        vel = mean[:, 1:3] / rho[:, None]
-        pres = 0.4 * (mean[:, 3] - 0.5 * rho * (vel ** 2).sum(axis=1))
-        smax = float((np.linalg.norm(vel, axis=1) + np.sqrt(1.4 * pres / rho)).max())
-        dt = self.cfl * float((4.0 * area / per).min()) / smax
-        K = U0.shape[0]
-        n_p = U0.shape[2]
-        E = 3 * K // 2
-        # state U (f64) + workspace: U1, U2 (f64), stage rhs (f64 / f32), f32 shadow
-        ws_elt = 16 + (4 if self.precision == "f32" else 8) + (4 if self.precision == "f32" else 0)
-        # + face arrays (ids, codes, geometry) + element arrays (geometry, slots) + tables
-        r.footprint = int(K * 4 * n_p * (8 + ws_elt) + E * (8 + 2 + 40) + K * (5 * 8 + 12) + 64 * 1024)
-        r.dofs = K * 4 * n_p
+        r.footprint = self.dgc.device_footprint(M, r.p, self.precision)
+        r.dofs = U0.size
         r.host = (M, U0, dt)
 
     def admit(self, r: Request) -> None:
@@ -270,6 +265,12 @@ class GPUExecutor:
 
     # eager batched steps of a group before its step is captured in a graph
     STABLE_STEPS = 2
+
+    def drop_group(self, p) -> None:
+        """Let go of group p's batch descriptor and captured graph, which hold
+        the device arrays of every member, finished ones included."""
+        self.batches.pop(p, None)
+        self.graphs.pop(p, None)
 
     def rebuild(self, p, group) -> None:
         self.batches[p] = self.dgc.Batch([r.dev for r in group], precision=self.precision)

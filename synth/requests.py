@@ -53,15 +53,35 @@ def front_state(points, normal, offset, width, gamma=GAMMA):
     return _conservative(rho, vel, p, gamma)
 
 
+def request_dt(req, m=None, cfl: float = 0.1, gamma=GAMMA) -> float:
+    """Time step supplied with a request: ``cfl * min(2 r_in) / max(|u| + c)``
+    over the initial state at the element centroids (``r_in`` the inradius,
+    ``c`` the sound speed of the ideal gas)."""
+    if m is None:
+        m, _ = request_input(req)
+    xyz = m["elem_xyz"]
+    st = _initial_states(req, element_centroid(xyz))
+    rho = st[:, 0]
+    vel = st[:, 1:3] / rho[:, None]
+    pres = (gamma - 1.0) * (st[:, 3] - 0.5 * rho * (vel ** 2).sum(axis=1))
+    smax = float((np.linalg.norm(vel, axis=1) + np.sqrt(gamma * pres / rho)).max())
+    per = sum(np.linalg.norm(xyz[:, (k + 1) % 3] - xyz[:, k], axis=1) for k in range(3))
+    two_rin = 4.0 * element_measure(xyz) / per
+    return cfl * float(two_rin.min()) / smax
+
+
+def _initial_states(req, cen):
+    ic = req["ic"]
+    if ic["kind"] == "vortex":
+        return isentropic_vortex(cen, 0.0, center=ic["center"], beta=ic["beta"], radius=0.1)
+    return front_state(cen, ic["normal"], ic["offset"], 3.0 / req["n"])
+
+
 def request_input(req):
     """Mesh arrays and constant-mode initial DOFs ``[K, 4, N_p]`` of one request."""
     m = periodic_tri(req["n"], jitter=0.1, seed=req["mesh_seed"])
     cen = element_centroid(m["elem_xyz"])
-    ic = req["ic"]
-    if ic["kind"] == "vortex":
-        st = isentropic_vortex(cen, 0.0, center=ic["center"], beta=ic["beta"], radius=0.1)
-    else:
-        st = front_state(cen, ic["normal"], ic["offset"], 3.0 / req["n"])
+    st = _initial_states(req, cen)
     p = req["p"]
     n_p = (p + 1) * (p + 2) // 2
     U = np.zeros((len(cen), 4, n_p))
