@@ -9,6 +9,7 @@ native library can consume its output without sharing any computation.
 
 from .meshes import (  # noqa: F401
     periodic_tri,
+    lattice_delaunay,
     poisson_delaunay,
     kuhn_tets,
     element_measure,

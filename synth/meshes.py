@@ -240,7 +240,38 @@ def poisson_delaunay(n_points: int = 500_000, seed: int = 2, radius: float | Non
             "points": pts}
 
 
-def kuhn_tets(n: int, jitter: float = 0.05, seed: int = 3, length: float = 1.0):
+def lattice_delaunay(n_points: int, seed: int = 7, jitter: float = 0.3):
+    """Delaunay triangulation of about ``n_points`` points of a jittered
+    square lattice in the unit square (interior points moved by
+    U(-jitter h, jitter h) per coordinate, boundary points on the sides):
+    a fast stand-in for the Poisson-disc mesh at sizes where the dart
+    throwing would dominate (used for the coloring-time sweep).  Walls, no
+    periodicity; counter-clockwise triangles in Qhull's order."""
+    from scipy.spatial import Delaunay  # generator-only dependency
+
+    n = max(3, int(round(np.sqrt(n_points))))
+    h = 1.0 / (n - 1)
+    rng = np.random.default_rng(seed)
+    g = np.linspace(0.0, 1.0, n)
+    X, Y = np.meshgrid(g, g, indexing="ij")
+    pts = np.stack([X.ravel(), Y.ravel()], axis=1)
+    inner = (pts[:, 0] > 0) & (pts[:, 0] < 1) & (pts[:, 1] > 0) & (pts[:, 1] < 1)
+    pts[inner] += rng.uniform(-jitter * h, jitter * h, size=(int(inner.sum()), 2))
+    tri = Delaunay(pts)
+    ev = tri.simplices.astype(np.int32).copy()
+    xyz = pts[ev]
+    area2 = (xyz[:, 1, 0] - xyz[:, 0, 0]) * (xyz[:, 2, 1] - xyz[:, 0, 1]) - (
+        xyz[:, 2, 0] - xyz[:, 0, 0]
+    ) * (xyz[:, 1, 1] - xyz[:, 0, 1])
+    neg = area2 < 0
+    ev[neg, 1], ev[neg, 2] = ev[neg, 2].copy(), ev[neg, 1].copy()
+    keep = np.abs(area2) > 1e-14 * h * h
+    ev = np.ascontiguousarray(ev[keep])
+    return {"elem_vert": ev, "elem_xyz": np.ascontiguousarray(pts[ev]), "n_vert": len(pts), "h": h,
+            "periodic": False}
+
+
+def kuhn_tets(n: int, jitter: float = 0.05, seed: int = 3, length: float = 1.0, periodic: bool = True):
     """``n^3`` periodic cubes, each split into the six Kuhn tetrahedra.
 
     Every tetrahedron of cube ``(i, j, k)`` runs from the cube's corner
@@ -250,13 +281,20 @@ def kuhn_tets(n: int, jitter: float = 0.05, seed: int = 3, length: float = 1.0):
     images.  Odd permutations list their vertices with the middle two
     swapped so that every tetrahedron has positive volume.
     Element ``6 (i + n j + n^2 k) + s`` uses the ``s``-th permutation of
-    ``itertools.permutations(range(3))``.
+    ``itertools.permutations(range(3))``.  With ``periodic=False`` the cube
+    is closed by reflective walls: the ``(n+1)^3`` lattice vertices are all
+    distinct and only the interior ones are displaced.
     """
     if n < 2:
         raise ValueError("kuhn_tets needs n >= 2")
     h = length / n
     rng = np.random.default_rng(seed)
-    disp = rng.uniform(-jitter * h, jitter * h, size=(n, n, n, 3))
+    nv = n if periodic else n + 1
+    disp = rng.uniform(-jitter * h, jitter * h, size=(nv, nv, nv, 3))
+    if not periodic:
+        disp[[0, -1], :, :] = 0.0
+        disp[:, [0, -1], :] = 0.0
+        disp[:, :, [0, -1]] = 0.0
     idx = np.arange(n)
     I, J, Kc = np.meshgrid(idx, idx, idx, indexing="ij")
     # cube order: i fastest, then j, then k
@@ -269,11 +307,11 @@ def kuhn_tets(n: int, jitter: float = 0.05, seed: int = 3, length: float = 1.0):
     xyz = np.empty((6 * ncube, 4, 3), dtype=np.float64)
 
     def vid(a, b, c):
-        return (a % n) + n * (b % n) + n * n * (c % n)
+        return (a % nv) + nv * (b % nv) + nv * nv * (c % nv)
 
     def pos(a, b, c):
         base = np.stack([a * h, b * h, c * h], axis=-1).astype(np.float64)
-        return base + disp[a % n, b % n, c % n]
+        return base + disp[a % nv, b % nv, c % nv]
 
     for s, perm in enumerate(perms):
         corner = [np.zeros(3, dtype=np.int64)]
@@ -295,7 +333,7 @@ def kuhn_tets(n: int, jitter: float = 0.05, seed: int = 3, length: float = 1.0):
         flip = vol <= 0
         ev[flip, 1], ev[flip, 2] = ev[flip, 2].copy(), ev[flip, 1].copy()
         xyz[flip, 1], xyz[flip, 2] = xyz[flip, 2].copy(), xyz[flip, 1].copy()
-    return {"elem_vert": ev, "elem_xyz": xyz, "n_vert": n ** 3, "h": h, "periodic": True}
+    return {"elem_vert": ev, "elem_xyz": xyz, "n_vert": nv ** 3, "h": h, "periodic": periodic}
 
 
 def shuffle_elements(mesh: dict, seed: int) -> dict:

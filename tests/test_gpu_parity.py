@@ -37,7 +37,7 @@ def _states(m, K):
 def _eps(kind, p):
     """Noise level of the higher modes that keeps every trace state physical
     (orthonormal modes grow towards the vertices with the order)."""
-    if kind == "tets":
+    if kind in ("tets", "tetbox"):
         return 0.02 if p <= 1 else 0.005
     if kind in ("quads", "quadbox", "hybrid", "hybridbox"):
         return 0.02 if p <= 2 else 0.005
@@ -66,7 +66,7 @@ class Case:
 
         D = D or self.D
         rhs = torch.zeros_like(self.Ug) if rhs0 is None else rhs0.clone()
-        ws = D.workspace("surface", variant) if variant == "gather" else None
+        ws = D.workspace("surface", variant) if variant in ("gather", "compact") else None
         D.surface_rhs(self.Ug, rhs, variant=variant, ws=ws)
         torch.cuda.synchronize()
         return rhs
@@ -101,7 +101,7 @@ def _volume_abs(d, U):
 
 @pytest.mark.parametrize("form", ["team", "team_prefetch", "thread"])
 @pytest.mark.parametrize("p", [0, 1, 2, 3, 4, 5])
-@pytest.mark.parametrize("variant", ["colored", "atomic", "gather"])
+@pytest.mark.parametrize("variant", ["colored", "atomic", "gather", "compact"])
 def test_surface_periodic_triangles(p, variant, form):
     c = Case("periodic", 16, 1, p)
     c.D.set_launch(form)
@@ -112,7 +112,7 @@ def test_surface_periodic_triangles(p, variant, form):
 @pytest.mark.parametrize("form,block,xcd", [("team", 256, False), ("team", 64, False), ("team", 256, True),
                                             ("team_prefetch", 256, False), ("team_prefetch", 128, True),
                                             ("thread", 256, False), ("thread", 128, True)])
-@pytest.mark.parametrize("variant", ["colored", "atomic", "gather"])
+@pytest.mark.parametrize("variant", ["colored", "atomic", "gather", "compact"])
 def test_surface_delaunay_walls_ragged(variant, form, block, xcd):
     c = Case("delaunay", 12000, 2, 2)
     assert c.O.E % 256 != 0 and c.O.n_boundary > 0
@@ -124,7 +124,7 @@ def test_surface_delaunay_walls_ragged(variant, form, block, xcd):
 @pytest.mark.parametrize("kind,size", [("quads", 12), ("quadbox", 11)])
 @pytest.mark.parametrize("form", ["default", "team", "thread"])
 @pytest.mark.parametrize("p", [0, 1, 2, 3])
-@pytest.mark.parametrize("variant", ["colored", "atomic", "gather"])
+@pytest.mark.parametrize("variant", ["colored", "atomic", "gather", "compact"])
 def test_surface_quads(p, variant, form, kind, size):
     """Parallelogram meshes (periodic, and walled with a ragged face count),
     four colors, tensor Legendre basis."""
@@ -138,7 +138,7 @@ def test_surface_quads(p, variant, form, kind, size):
 @pytest.mark.parametrize("kind,size", [("hybrid", 14), ("hybridbox", 13)])
 @pytest.mark.parametrize("form", ["default", "thread"])
 @pytest.mark.parametrize("p", [0, 1, 2, 3])
-@pytest.mark.parametrize("variant", ["colored", "atomic", "gather"])
+@pytest.mark.parametrize("variant", ["colored", "atomic", "gather", "compact"])
 def test_surface_mixed(p, variant, form, kind, size):
     """Mixed triangle / parallelogram meshes (four colors; every element has
     (p+1)^2 slots, a triangle's tables are zero beyond its own modes)."""
@@ -180,12 +180,25 @@ def test_rk3_mixed_vortex_20_steps():
     assert np.abs(got - U).max() / np.abs(U).max() <= TOL
 
 
-@pytest.mark.parametrize("form", ["default", "team", "thread", "mode_team"])
-@pytest.mark.parametrize("p", [0, 1, 2])
-@pytest.mark.parametrize("variant", ["colored", "atomic", "gather"])
+@pytest.mark.parametrize("form,p", [("default", 0), ("default", 1), ("default", 2), ("team", 1), ("thread", 2),
+                                    ("mode_team", 1), ("pair_team", 1)])
+@pytest.mark.parametrize("variant", ["colored", "atomic", "gather", "compact"])
+def test_surface_tets_walls(p, variant, form):
+    """Tetrahedra in a closed box (reflective walls on all six sides)."""
+    c = Case("tetbox", 4, 5, p)
+    assert c.O.n_boundary > 0 and c.stats["n_colors"] == 4
+    c.D.set_launch(form)
+    got = c.to_host(c.surface(variant))
+    _check(got, dg.surface_rhs(c.d, c.U), dg.surface_abs(c.d, c.U), "surface walled tets %s p=%d" % (variant, p))
+
+
+# the mode and pair teams exist for N_p = 4 only (tetrahedra at p = 1)
+TET_FORMS = [(f, p) for p in (0, 1, 2) for f in ("default", "team", "thread")] + [("mode_team", 1), ("pair_team", 1)]
+
+
+@pytest.mark.parametrize("form,p", TET_FORMS)
+@pytest.mark.parametrize("variant", ["colored", "atomic", "gather", "compact"])
 def test_surface_tets(p, variant, form):
-    if form == "mode_team" and p != 1:
-        pytest.skip("mode teams need N_p = 4 (tetrahedra, p = 1)")
     c = Case("tets", 6, 3, p)
     c.D.set_launch(form)
     assert c.stats["n_colors"] == 4
@@ -235,13 +248,21 @@ def test_volume_forms(kind, size, p):
     assert np.abs(out["team"] - out["valu"]).max() <= 1e-13 * max(scale, 1e-300)
 
 
-@pytest.mark.parametrize("layout", ["paper_sfc", "renumber", "none"])
-def test_surface_other_layouts(layout):
+@pytest.mark.parametrize("algorithm", ["paper", "greedy"])
+@pytest.mark.parametrize("layout", ["paper", "paper_sfc", "renumber", "none"])
+def test_surface_other_layouts(layout, algorithm):
+    """Every layout of the paper's coloring and of the standard greedy
+    coloring (up to five colors on triangles, Section 1; the Table 7
+    comparison): the colored pass gives the oracle's uncolored face sum."""
     import torch
 
     dgc = _dgc()
     c = Case("delaunay", 9000, 3, 2)
-    c.M.set_colors(c.M.export("color"), layout=layout)
+    if algorithm == "greedy":
+        st = c.M.color(algorithm="greedy", layout=layout)
+        assert 3 <= st["n_colors"] <= 5
+    else:
+        c.M.set_colors(c.M.export("color"), layout=layout)
     D = dgc.DeviceMesh(c.M, 2)
     D.set_launch("team", 256, True)
     Ug = torch.from_numpy(D.to_layout(c.U)).cuda()
@@ -339,7 +360,8 @@ def test_rk3_100_steps_vortex():
 
 
 @pytest.mark.parametrize("kind,size,p", [("delaunay", 6000, 2), ("periodic", 16, 1), ("periodic", 16, 3),
-                                         ("tets", 5, 1), ("tets", 4, 2), ("quads", 12, 2), ("quadbox", 11, 1)])
+                                         ("tets", 5, 1), ("tets", 4, 2), ("tetbox", 4, 1), ("quads", 12, 2),
+                                         ("quadbox", 11, 1)])
 def test_rk3_step_forms_agree(kind, size, p):
     """The stage combination fused into the last color's face kernel, the
     volume term fused into the first color's, and the whole step in one
@@ -350,7 +372,7 @@ def test_rk3_step_forms_agree(kind, size, p):
     import torch
 
     c = Case(kind, size, 21, p)
-    if kind != "tets":
+    if c.D.dim == 2:
         # a smooth state: the shock tube has no limiter to survive several steps at p >= 1
         st = synth.density_wave_states(synth.element_centroid(c.m["elem_xyz"]), vel=(0.5, 0.3))
         c.Ug = torch.from_numpy(c.D.to_layout(synth.perturbed_dofs(c.O.elem_measure, st, c.d.n_p, eps=0.01,
@@ -436,9 +458,10 @@ def test_workspace_errors_on_device():
     c = Case("periodic", 8, 9, 1)
     rhs = torch.zeros_like(c.Ug)
     small = torch.empty(16, dtype=torch.uint8, device="cuda")
-    with pytest.raises(dgc.DgcError) as e:
-        c.D.surface_rhs(c.Ug, rhs, variant="gather", ws=small)
-    assert e.value.name == "DGC_E_WORKSPACE"
+    for variant in ("gather", "compact"):
+        with pytest.raises(dgc.DgcError) as e:
+            c.D.surface_rhs(c.Ug, rhs, variant=variant, ws=small)
+        assert e.value.name == "DGC_E_WORKSPACE"
     with pytest.raises(dgc.DgcError) as e:
         c.D.rk_step(c.Ug, 1e-3, ws=small)
     assert e.value.name == "DGC_E_WORKSPACE"
@@ -448,7 +471,7 @@ def test_workspace_errors_on_device():
 
 @pytest.mark.parametrize("kind,size,p", [("tets", 4, 2), ("periodic", 9, 4), ("delaunay", 1500, 5),
                                          ("quadbox", 7, 3), ("delaunay", 2000, 2)])
-@pytest.mark.parametrize("variant", ["colored", "atomic", "gather"])
+@pytest.mark.parametrize("variant", ["colored", "atomic", "gather", "compact"])
 def test_surface_stream_form(kind, size, p, variant):
     """The streaming team form (quadrature points visited one at a time)
     against the oracle, every variant, walls included."""
@@ -483,17 +506,16 @@ def full_c1():
     return c
 
 
-def test_full_size_sampled(full_c1):
+def test_full_size_every_element(full_c1):
+    """The colored pass of the whole Delaunay workload in the launch the bench
+    times, against the oracle's face sum on every one of its ~1M elements."""
     c = full_c1
     c.D.set_launch("default")
     got = c.to_host(c.surface("colored"))
-    rng = np.random.default_rng(42)
-    S = np.unique(np.concatenate([rng.choice(c.O.K, 3000, replace=False), [0, c.O.K - 1]]))
-    ref = dg.surface_rhs(c.d, c.U, elems=S)
-    scale = dg.surface_abs(c.d, c.U)[S]
-    _check(got[S], ref[S], scale, "full-size sampled colored")
+    ref = dg.surface_rhs(c.d, c.U)
+    _check(got, ref, dg.surface_abs(c.d, c.U), "full-size colored, every element")
     # the other variants agree with the colored one on every entry
-    for v in ("atomic", "gather"):
+    for v in ("atomic", "gather", "compact"):
         other = c.to_host(c.surface(v))
         _check(other, got, dg.surface_abs(c.d, c.U), "full-size %s vs colored" % v)
     c.D.set_launch("thread")
@@ -534,16 +556,17 @@ def full_c2():
     return Case("tets", 64, 3, 1, cseed=0, eps=0.01)
 
 
-def test_full_size_tets_sampled(full_c2):
+def test_full_size_tets_every_element(full_c2):
+    """The whole tetrahedral workload: every element against the oracle (f64);
+    the f32 form on 3,002 sampled elements at its own bar."""
     c = full_c2
     assert c.D.info["n_colors"] == 4
     c.D.set_launch("default")
     got = c.to_host(c.surface("colored"))
+    scale = dg.surface_abs(c.d, c.U)
+    _check(got, dg.surface_rhs(c.d, c.U), scale, "full-size tets colored, every element")
     rng = np.random.default_rng(43)
     S = np.unique(np.concatenate([rng.choice(c.O.K, 3000, replace=False), [0, c.O.K - 1]]))
-    ref = dg.surface_rhs(c.d, c.U, elems=S)
-    scale = dg.surface_abs(c.d, c.U)
-    _check(got[S], ref[S], scale[S], "full-size tets sampled colored")
     # the f32 form of the same pass at its own bar
     import torch
 
@@ -564,7 +587,7 @@ TOL32 = 2e-6
 
 @pytest.mark.parametrize("kind,size,p", [("periodic", 16, 2), ("periodic", 16, 5), ("delaunay", 6000, 2),
                                          ("tets", 5, 1), ("tets", 5, 2), ("quads", 12, 2), ("hybrid", 14, 2)])
-@pytest.mark.parametrize("variant", ["colored", "atomic", "gather"])
+@pytest.mark.parametrize("variant", ["colored", "atomic", "gather", "compact"])
 def test_surface_and_volume_f32(kind, size, p, variant):
     """f32 storage and arithmetic (geometry stored in f64) against the f64
     oracle evaluated on the same f32-rounded DOFs.  The worst-case rounding
@@ -578,7 +601,7 @@ def test_surface_and_volume_f32(kind, size, p, variant):
     U = U32.astype(np.float64)
     Ug = torch.from_numpy(c.D.to_layout(U32)).cuda()
     rhs = torch.zeros_like(Ug)
-    ws = c.D.workspace("surface", variant, "f32") if variant == "gather" else None
+    ws = c.D.workspace("surface", variant, "f32") if variant in ("gather", "compact") else None
     c.D.surface_rhs(Ug, rhs, variant=variant, precision="f32", ws=ws)
     vol = torch.zeros_like(Ug)
     c.D.volume_rhs(Ug, vol, precision="f32")
@@ -652,7 +675,27 @@ def _refined(n=24, levels=3, radius=0.15, p=2, cseed=0):
     return mesh, d, D
 
 
-@pytest.mark.parametrize("variant", ["colored", "atomic", "gather"])
+def test_surface_refined_configured_size():
+    """The refined workload at its configured size: 128 x 128 x 2 base, three
+    refinement passes within 0.15 of the center (178,724 leaves, six colors,
+    hanging faces), every variant against the oracle on every element."""
+    import torch
+
+    mesh, d, D = _refined(n=128)
+    assert D.info["n_colors"] == 6 and mesh.K == 178_724
+    U = synth.perturbed_dofs(mesh.elem_measure, synth.shock_tube_states(mesh.elem_xyz.mean(axis=1)), d.n_p,
+                             eps=0.02, seed=21)
+    Ug = torch.from_numpy(D.to_layout(U)).cuda()
+    ref, scale = dg.surface_rhs(d, U), dg.surface_abs(d, U)
+    for variant in ("colored", "atomic", "gather", "compact"):
+        rhs = torch.zeros_like(Ug)
+        ws = D.workspace("surface", variant) if variant in ("gather", "compact") else None
+        D.surface_rhs(Ug, rhs, variant=variant, ws=ws)
+        torch.cuda.synchronize()
+        _check(D.from_layout(rhs.cpu().numpy()), ref, scale, "refined 128 base " + variant)
+
+
+@pytest.mark.parametrize("variant", ["colored", "atomic", "gather", "compact"])
 @pytest.mark.parametrize("form", ["default", "thread"])
 def test_surface_refined_six_colors(variant, form):
     import torch
@@ -664,7 +707,7 @@ def test_surface_refined_six_colors(variant, form):
                              eps=0.02, seed=21)
     Ug = torch.from_numpy(D.to_layout(U)).cuda()
     rhs = torch.zeros_like(Ug)
-    ws = D.workspace("surface", variant) if variant == "gather" else None
+    ws = D.workspace("surface", variant) if variant in ("gather", "compact") else None
     D.surface_rhs(Ug, rhs, variant=variant, ws=ws)
     torch.cuda.synchronize()
     _check(D.from_layout(rhs.cpu().numpy()), dg.surface_rhs(d, U), dg.surface_abs(d, U), "refined " + variant)

@@ -22,7 +22,7 @@ from paper_1601_07613_amd import _lib  # noqa: E402
 GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_tables.json")))
 HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "dgc.h")
 
-CASES = [("periodic", 16, 1), ("periodic", 37, 4), ("delaunay", 8000, 2), ("tets", 5, 3), ("quads", 20, 2),
+CASES = [("periodic", 16, 1), ("periodic", 37, 4), ("delaunay", 8000, 2), ("tets", 5, 3), ("tetbox", 4, 2), ("quads", 20, 2),
          ("quadbox", 23, 5), ("hybrid", 16, 3), ("hybridbox", 15, 6)]
 
 
@@ -229,6 +229,26 @@ def test_gather_workspace_is_table4_memory():
         assert b.value == 2 * info["n_p"] * 4 * t4["sides"] * 8
 
 
+def test_compact_workspace_is_one_record_per_face():
+    """The compact buffered variant keeps one record of n_qf * n_var + 1
+    values per face (the Q-point fluxes and the two table codes), against the
+    two element-sized slots of the buffered variant of Table 4."""
+    for et, p, nvar in ((0, 2, 4), (2, 1, 5), (1, 3, 4)):
+        info, _ = dgc.tables(et, p)
+        dm = _lib.DMesh()
+        dm.elem_type, dm.p, dm.n_p, dm.n_var = et, p, info["n_p"], nvar
+        dm.n_qf, dm.n_qv, dm.n_codes, dm.n_orient = info["n_qf"], info["n_qv"], info["n_codes"], info["n_orient"]
+        dm.n_elem, dm.n_face = 1000, 1700
+        dm.face_lr = dm.face_code = dm.face_geo = dm.elem_geo = dm.tables = 0x1000  # never dereferenced
+        b = C.c_size_t()
+        for prec, elt in ((0, 8), (1, 4)):
+            _lib.check(_lib.load().dgc_workspace_bytes(C.byref(dm), 0, 3, prec, C.byref(b)), "ws")
+            assert b.value == 1700 * (info["n_qf"] * nvar + 1) * elt
+            g = C.c_size_t()
+            _lib.check(_lib.load().dgc_workspace_bytes(C.byref(dm), 0, 2, prec, C.byref(g)), "ws")
+            assert b.value < g.value
+
+
 def test_surface_entry_rejects_missing_workspace_without_launching():
     info, _ = dgc.tables(0, 1)
     dm = _lib.DMesh()
@@ -238,6 +258,8 @@ def test_surface_entry_rejects_missing_workspace_without_launching():
     dm.face_lr = dm.face_code = dm.face_geo = dm.elem_geo = dm.tables = dm.elem_slots = 0x1000
     L = _lib.load()
     assert L.dgc_surface_rhs(C.byref(dm), 0x1000, 0x1000, 2, 0, None, 0, None) == -7  # DGC_E_WORKSPACE
+    assert L.dgc_surface_rhs(C.byref(dm), 0x1000, 0x1000, 3, 0, None, 0, None) == -7  # compact, no workspace
+    assert L.dgc_surface_rhs(C.byref(dm), 0x1000, 0x1000, 4, 0, None, 0, None) == -1  # unknown variant
     assert L.dgc_surface_rhs(C.byref(dm), 0x1000, 0x1000, 0, 0, None, 0, None) == -3  # no colors
     dm.p = 7
     assert L.dgc_surface_rhs(C.byref(dm), 0x1000, 0x1000, 1, 0, None, 0, None) == -6  # unsupported order

@@ -63,6 +63,15 @@ def test_refine_periodic_three_levels_bit_exact():
     assert M.info()["n_colors"] == 6
 
 
+def test_refine_configured_size_bit_exact():
+    """The refined workload at its configured size (128 x 128 x 2 base, three
+    passes within 0.15 of the center): 178,724 leaves, bit-exact."""
+    m = synth.periodic_tri(128, jitter=0.0, seed=4)
+    st, M = _run(m, 3, 0.15, 0)
+    mesh, color = _compare(st, M)
+    assert mesh.K == 178_724 and M.info()["n_colors"] == 6
+
+
 def test_refine_delaunay_walls_bit_exact():
     m = synth.poisson_delaunay(1500, seed=7)
     st, M = _run(m, 2, 0.3, 3)
