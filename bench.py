@@ -27,12 +27,13 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+ABLATION_ROUNDS = 5
 PROFILES = {
     "delaunay": os.path.join(ROOT, "profiles", "surface_colored_team_prefetch_delaunay996k_p2_f64.md"),
     "tets": os.path.join(ROOT, "profiles", "surface_colored_mode_team_kuhn64_tets_p1_f64.md"),
 }
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1601_07613_amd", "csrc", "kernels", f)
-                  for f in ("surface.hpp", "euler_dev.hpp", "team.hpp")]
+                  for f in ("surface.hpp", "euler_dev.hpp", "team.hpp", "device_api.hip")]
 
 
 def profiled_traffic(args, launch):
@@ -88,6 +89,19 @@ def algorithmic_bytes(n_face: int, n_interior: int, rec: int, elt: int, dim: int
     return sides * 3 * rec * elt + n_face * ((dim + 3) * 8 + 8 + 2)
 
 
+def compact_bytes(n_face: int, n_interior: int, n_elem: int, nvar: int, n_p: int, max_slots: int, n_qf: int,
+                  elt: int, dim: int) -> int:
+    """Bytes the compact buffered variant must move: the face pass reads both
+    DOF records, the face geometry, ids and codes and writes one record of
+    n_qf * nvar + 1 values; the element pass reads the element's slots and
+    sqrt(det J), the records of its faces, and reads + writes its RHS."""
+    rec = nvar * n_p * elt
+    frec = (n_qf * nvar + 1) * elt
+    face = (n_face + n_interior) * rec + n_face * ((dim + 3) * 8 + 8 + 2 + frec)
+    elem = n_elem * (max_slots * 4 + 8 + 2 * rec) + (n_face + n_interior) * frec
+    return face + elem
+
+
 def timed(fn, steps, warmup, stream):
     import torch
 
@@ -115,15 +129,22 @@ def extra_workloads(dgc, synth, torch, steps, warmup, log):
     out = {}
     stream = torch.cuda.current_stream()
 
-    def surf_stats(D, K, E, nb, elt, precision):
+    def surf_stats(D, K, E, nb, elt, precision, variants=()):
         U = torch.zeros((K, D.n_var, D.n_p), dtype=torch.float64 if elt == 8 else torch.float32, device="cuda")
         U[:, 0, 0] = 1.0
         U[:, -1, 0] = 2.5
         rhs = torch.zeros_like(U)
         ms = time_call(lambda: D.surface_rhs(U, rhs, "colored", precision), reps=steps, warmup=warmup)
         ab = algorithmic_bytes(E, E - nb, D.n_var * D.n_p, elt, D.dim)
-        return {"colored_us": ms * 1e3, "dof_updates_per_s": K * D.n_var * D.n_p / (ms * 1e-3),
-                "algorithmic_GBs": ab / (ms * 1e-3) / 1e9, "frac_of_8TBs": ab / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        res = {"colored_us": ms * 1e3, "dof_updates_per_s": K * D.n_var * D.n_p / (ms * 1e-3),
+               "algorithmic_GBs": ab / (ms * 1e-3) / 1e9, "frac_of_8TBs": ab / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        # the other variants of the same pass (Section 1's alternatives)
+        for v in variants:
+            ws = D.workspace("surface", v, precision) if v in ("gather", "compact") else None
+            res[v + "_us"] = time_call(lambda: D.surface_rhs(U, rhs, v, precision, ws=ws), reps=steps,
+                                       warmup=warmup) * 1e3
+            del ws
+        return res
 
     # c0: 16 x 16 x 2 periodic triangles, p = 1 (latency-bound)
     m = synth.periodic_tri(16, seed=1)
@@ -157,7 +178,8 @@ def extra_workloads(dgc, synth, torch, steps, warmup, log):
     cs = T.color(seed=0)
     DT = dgc.DeviceMesh(T, 1)
     info = DT.info
-    r64 = surf_stats(DT, info["n_elem"], info["n_face"], info["n_boundary"], 8, "f64")
+    r64 = surf_stats(DT, info["n_elem"], info["n_face"], info["n_boundary"], 8, "f64",
+                     variants=("atomic", "gather", "compact"))
     r32 = surf_stats(DT, info["n_elem"], info["n_face"], info["n_boundary"], 4, "f32")
     DT.set_launch("thread")
     r64t = surf_stats(DT, info["n_elem"], info["n_face"], info["n_boundary"], 8, "f64")
@@ -301,15 +323,66 @@ def extra_workloads(dgc, synth, torch, steps, warmup, log):
                         spec=r) for r in rs]
 
     serving = {}
+    results = {}
     for name, prec, mode, budget, sat in (("batched_f32_budget512MB", "f32", "batched", 512 << 20, False),
                                           ("batched_f32_full", "f32", "batched", 200 << 30, False),
                                           ("plain_f64_sequential", "f64", "sequential", 200 << 30, False),
                                           ("batched_f32_saturated", "f32", "batched", 200 << 30, True),
                                           ("plain_f64_saturated", "f64", "sequential", 200 << 30, True)):
-        st = Server(GPUExecutor(precision=prec), budget_bytes=budget, mode=mode, prep_workers=16).run(reqs(sat))
+        rs = reqs(sat)
+        st = Server(GPUExecutor(precision=prec), budget_bytes=budget, mode=mode, prep_workers=16).run(rs)
         serving[name] = st.summary()
+        results[name] = {r.rid: r.result for r in rs if r.status == "done"}
         log("c4 %s: %s" % (name, serving[name]))
+    # error of the served f32 bulk form against the plain f64 path, per request
+    a, b = results["batched_f32_budget512MB"], results["plain_f64_sequential"]
+    rel = np.array([np.sqrt(((a[i] - b[i]) ** 2).sum() / (b[i] ** 2).sum()) for i in sorted(set(a) & set(b))])
+    serving["f32_served_rel_L2_vs_f64"] = {"requests": int(rel.size), "max": float(rel.max()),
+                                           "median": float(np.median(rel)), "budget": 1e-6}
+    log("c4 f32 served error: %s" % serving["f32_served_rel_L2_vs_f64"])
     out["c4_serving_256"] = serving
+    return out
+
+
+SWEEP_SIDES = {
+    # side counts of the paper's meshes A-E (Table 1, Table 2, Table 3)
+    "triangles": (14775, 59547, 236372, 942162, 3774165),
+    "quadrilaterals": (8888, 35396, 141076, 563108, 2249162),
+    "tetrahedra": (14937, 102438, 720736),
+}
+
+
+def coloring_sweep(dgc, synth, log):
+    """Host coloring at sizes like the paper's meshes A-E (Figure 9, Table 8):
+    for each element family and size, the conflicts left by the greedy stage,
+    the coloring time and the renumbering + reordering time, against the
+    number of sides.  Meshes: jittered-lattice Delaunay triangles, periodic
+    parallelograms and periodic Kuhn tetrahedra (even grids, which have
+    four-colorings), each numbered in a seeded random order (an unstructured
+    generator's numbering; see shuffle_elements)."""
+    out = {}
+    for fam, sizes in SWEEP_SIDES.items():
+        rows = []
+        for sides in sizes:
+            if fam == "triangles":
+                m = synth.lattice_delaunay(sides // 3, seed=7)
+            elif fam == "quadrilaterals":
+                # an even periodic grid: an odd one has no four-coloring
+                m = synth.quad_grid(2 * max(2, int(round((sides / 8) ** 0.5))), seed=6)
+            else:
+                m = synth.kuhn_tets(2 * max(1, int(round((sides / 96) ** (1 / 3)))), seed=3)
+            m = synth.shuffle_elements(m, seed=1)
+            t = time.perf_counter()
+            Mx = dgc.Mesh.build(m["elem_vert"], m["elem_xyz"])
+            build_ms = (time.perf_counter() - t) * 1e3
+            st = Mx.color(seed=0)
+            E = Mx.info()["n_face"]
+            rows.append({"sides": E, "elements": len(m["elem_vert"]), "conflicts_after_greedy": st["conflicts_after_greedy"],
+                         "conflict_fraction": st["conflicts_after_greedy"] / E, "color_ms": st["color_ms"],
+                         "layout_ms": st["layout_ms"], "build_ms": build_ms, "n_colors": st["n_colors"]})
+            log("sweep %s: %s" % (fam, rows[-1]))
+            del Mx, m
+        out[fam] = rows
     return out
 
 
@@ -353,13 +426,14 @@ def main(argv=None):
     ap.add_argument("--tet-n", type=int, default=64)
     ap.add_argument("--p", type=int, default=None)
     ap.add_argument("--seed", type=int, default=2)
-    ap.add_argument("--only", choices=["all", "colored", "volume", "rk", "batch"], default="all",
+    ap.add_argument("--only", choices=["all", "colored", "volume", "rk", "batch", "sweep"], default="all",
                     help="'colored' times the colored pass only, 'volume' the volume-term forms only, 'rk' the "
                          "SSP-RK3 step forms only, 'batch' a batched SSP-RK3 step of 8 periodic meshes of "
-                         "125k triangles (for profiling)")
+                         "125k triangles (for profiling), 'sweep' the host coloring sweep only")
     ap.add_argument("--rk-form", choices=["default", "fused_volume", "fused", "separate"], default="default",
                     help="SSP-RK3 step form timed by --only rk")
-    ap.add_argument("--form", choices=["auto", "default", "team", "team_prefetch", "thread"], default="auto",
+    ap.add_argument("--form", choices=["auto", "default", "team", "team_prefetch", "thread", "team_stream", "mode_team",
+                                       "pair_team"], default="auto",
                     help="face-kernel form; 'auto' runs the launch autotuner before timing")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--xcd-remap", action="store_true")
@@ -384,6 +458,10 @@ def main(argv=None):
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
+
+    if args.only == "sweep":
+        print(json.dumps({"coloring_sweep": coloring_sweep(dgc, synth, log)}))
+        return 0
 
     if args.calibrate_copy:
         # 1 GiB read + 1 GiB written per launch: the reference for FETCH_SIZE / WRITE_SIZE
@@ -497,6 +575,13 @@ def main(argv=None):
         extra["atomic_us"] = timed(lambda: D.surface_rhs(Ug, rhs, "atomic"), args.steps, args.warmup, stream)[0] * 1e3
         extra["gather_us"] = timed(lambda: D.surface_rhs(Ug, rhs, "gather", ws=ws), args.steps, args.warmup,
                                    stream)[0] * 1e3
+        del ws
+        wsc = D.workspace("surface", "compact")
+        extra["compact_us"] = timed(lambda: D.surface_rhs(Ug, rhs, "compact", ws=wsc), args.steps, args.warmup,
+                                    stream)[0] * 1e3
+        extra["compact_algorithmic_bytes"] = compact_bytes(E, E - nb, K, D.n_var, D.n_p, info["max_slots"],
+                                                           D.tinfo["n_qf"], 8, D.dim)
+        del wsc
         extra["volume_us"] = timed(lambda: D.volume_rhs(Ug, rhs), args.steps, args.warmup, stream)[0] * 1e3
         if D.dim == 2:
             for vf in ("valu", "mfma", "team"):
@@ -533,6 +618,7 @@ def main(argv=None):
         D.set_launch(best["form"], best["block"], best["xcd_remap"])
         extra["colored_over_atomic"] = extra["atomic_us"] / (ms * 1e3)
         extra["colored_over_gather"] = extra["gather_us"] / (ms * 1e3)
+        extra["colored_over_compact"] = extra["compact_us"] / (ms * 1e3)
         # the other layouts of the same coloring, same launch
         for lay in ("paper", "paper_sfc", "renumber", "none"):
             if lay == args.layout:
@@ -544,22 +630,29 @@ def main(argv=None):
             del D2, Ug2, rhs2
         M.set_colors(colors, layout=args.layout)
         # Table 7 shape: standard greedy (more colors) vs the paper's coloring,
-        # each with no renumbering / renumbering / renumbering + reordering
-        ablation = {}
+        # each with no renumbering / renumbering / renumbering + reordering,
+        # plus the headline pass itself; the seven passes are timed in turn,
+        # round after round, so that slow drifts of the clock hit all alike
         G = dgc.Mesh.build(m["elem_vert"], m["elem_xyz"])
         gst = G.color(algorithm="greedy")
         gcol = G.export("color")
+        cfgs = {"headline": (D, Ug, rhs)}
         for cname, Mx, col in (("greedy_%dcolors" % gst["n_colors"], G, gcol), ("paper_3colors", M, colors)):
             for lay in ("none", "renumber", "paper"):
                 Mx.set_colors(col, layout=lay)
                 Dx = dgc.DeviceMesh(Mx, p)
                 Dx.set_launch(best["form"], best["block"], best["xcd_remap"])
                 Ux = torch.from_numpy(Dx.to_layout(U)).cuda()
-                rx = torch.zeros_like(Ux)
-                ablation["%s_%s" % (cname, lay)] = time_call(lambda: Dx.surface_rhs(Ux, rx, "colored"),
-                                                             reps=args.steps, warmup=args.warmup) * 1e3
-                del Dx, Ux, rx
-        extra["table7_ablation_us"] = ablation
+                cfgs["%s_%s" % (cname, lay)] = (Dx, Ux, torch.zeros_like(Ux))
+        samples = {k: [] for k in cfgs}
+        for _ in range(ABLATION_ROUNDS):
+            for k, (Dx, Ux, rx) in cfgs.items():
+                samples[k].append(time_call(lambda: Dx.surface_rhs(Ux, rx, "colored"), reps=args.steps,
+                                            warmup=2) * 1e3)
+        extra["table7_ablation_us"] = {
+            k: {"median": float(np.median(v)), "min": float(min(v)), "max": float(max(v))} for k, v in samples.items()}
+        extra["table7_ablation_us"]["rounds"] = ABLATION_ROUNDS
+        del cfgs, samples
         M.set_colors(colors, layout=args.layout)
         del G
         # the f32 form of the same pass (f32 records, f64 geometry)
@@ -582,6 +675,7 @@ def main(argv=None):
     workloads = None
     if args.only == "all" and args.workload == "delaunay":
         workloads = extra_workloads(dgc, synth, torch, args.steps, args.warmup, log)
+        workloads["coloring_sweep"] = coloring_sweep(dgc, synth, log)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -642,7 +736,25 @@ def main(argv=None):
         "other_workloads": workloads,
     }
     print(json.dumps(out))
+    reap_children(log)
     return 0
+
+
+def reap_children(log):
+    """Join every process this run started that is still alive (names it in
+    the log first), so that nothing outlives the benchmark."""
+    try:
+        import psutil
+    except ImportError:
+        return
+    kids = psutil.Process().children(recursive=True)
+    for k in kids:
+        try:
+            log("child process still running at exit: pid %d %s" % (k.pid, " ".join(k.cmdline())))
+            k.terminate()
+        except psutil.Error:
+            pass
+    psutil.wait_procs(kids, timeout=10)
 
 
 if __name__ == "__main__":
