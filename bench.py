@@ -124,20 +124,25 @@ def extra_workloads(dgc, synth, torch, steps, warmup, log):
     """The other configurations, reported beside the headline: small periodic
     mesh latency (c0), periodic Kuhn tetrahedra in f64 and f32 with the f32
     form's error (c2), the adaptively refined nonconforming mesh (c3)."""
-    from paper_1601_07613_amd.tune import time_call
+    from paper_1601_07613_amd.tune import autotune, time_call
 
     out = {}
     stream = torch.cuda.current_stream()
 
-    def surf_stats(D, K, E, nb, elt, precision, variants=()):
+    def surf_stats(D, K, E, nb, elt, precision, variants=(), tune=False):
         U = torch.zeros((K, D.n_var, D.n_p), dtype=torch.float64 if elt == 8 else torch.float32, device="cuda")
         U[:, 0, 0] = 1.0
         U[:, -1, 0] = 2.5
         rhs = torch.zeros_like(U)
+        launch = None
+        if tune:
+            # the launch autotuner on this mesh, as for the headline
+            launch, _ = autotune(D, U, rhs, precision=precision)
         ms = time_call(lambda: D.surface_rhs(U, rhs, "colored", precision), reps=steps, warmup=warmup)
         ab = algorithmic_bytes(E, E - nb, D.n_var * D.n_p, elt, D.dim)
         res = {"colored_us": ms * 1e3, "dof_updates_per_s": K * D.n_var * D.n_p / (ms * 1e-3),
-               "algorithmic_GBs": ab / (ms * 1e-3) / 1e9, "frac_of_8TBs": ab / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+               "algorithmic_GBs": ab / (ms * 1e-3) / 1e9, "frac_of_8TBs": ab / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+               "launch": launch or "default"}
         # the other variants of the same pass (Section 1's alternatives)
         for v in variants:
             ws = D.workspace("surface", v, precision) if v in ("gather", "compact") else None
@@ -178,9 +183,13 @@ def extra_workloads(dgc, synth, torch, steps, warmup, log):
     cs = T.color(seed=0)
     DT = dgc.DeviceMesh(T, 1)
     info = DT.info
-    r64 = surf_stats(DT, info["n_elem"], info["n_face"], info["n_boundary"], 8, "f64",
-                     variants=("atomic", "gather", "compact"))
-    r32 = surf_stats(DT, info["n_elem"], info["n_face"], info["n_boundary"], 4, "f32")
+    # the variants in the default launch; then the colored pass autotuned
+    r64d = surf_stats(DT, info["n_elem"], info["n_face"], info["n_boundary"], 8, "f64",
+                      variants=("atomic", "gather", "compact"))
+    r64 = surf_stats(DT, info["n_elem"], info["n_face"], info["n_boundary"], 8, "f64", tune=True)
+    r32 = surf_stats(DT, info["n_elem"], info["n_face"], info["n_boundary"], 4, "f32", tune=True)
+    DT.set_launch("pair_team")
+    r64p = surf_stats(DT, info["n_elem"], info["n_face"], info["n_boundary"], 8, "f64")
     DT.set_launch("thread")
     r64t = surf_stats(DT, info["n_elem"], info["n_face"], info["n_boundary"], 8, "f64")
     DT.set_launch("team_prefetch")
@@ -212,7 +221,8 @@ def extra_workloads(dgc, synth, torch, steps, warmup, log):
     DT.set_rk_form("default")
     out["c2_kuhn64_tets_p1"] = {
         "n_elem": info["n_elem"], "n_face": info["n_face"], "n_colors": info["n_colors"],
-        "color_ms": cs["color_ms"], "f64": r64, "f32": r32, "f64_thread_form": r64t, "f64_variable_team_form": r64v,
+        "color_ms": cs["color_ms"], "f64": r64, "f32": r32, "f64_default_launch": r64d, "f64_pair_team_form": r64p,
+        "f64_thread_form": r64t, "f64_variable_team_form": r64v,
         "rk3_step_us": {"f64": rk64 * 1e3, "f32_form": rk32 * 1e3},
         "rk3_step_by_form_us": rk_forms,
         "f32_form_rel_L2_after_10_steps": [float(x) for x in diff.cpu()],
@@ -226,8 +236,8 @@ def extra_workloads(dgc, synth, torch, steps, warmup, log):
     qs = Qm.color(seed=0)
     DQ = dgc.DeviceMesh(Qm, 2)
     info = DQ.info
-    rq = surf_stats(DQ, info["n_elem"], info["n_face"], info["n_boundary"], 8, "f64")
-    rq32 = surf_stats(DQ, info["n_elem"], info["n_face"], info["n_boundary"], 4, "f32")
+    rq = surf_stats(DQ, info["n_elem"], info["n_face"], info["n_boundary"], 8, "f64", tune=True)
+    rq32 = surf_stats(DQ, info["n_elem"], info["n_face"], info["n_boundary"], 4, "f32", tune=True)
     Uq = torch.zeros((DQ.K, 4, DQ.n_p), dtype=torch.float64, device="cuda")
     Uq[:, 0, 0] = 1.0
     Uq[:, 3, 0] = 2.5
@@ -252,7 +262,7 @@ def extra_workloads(dgc, synth, torch, steps, warmup, log):
     hs = Hm.color(seed=0)
     DH = dgc.DeviceMesh(Hm, 2)
     info = DH.info
-    rh = surf_stats(DH, info["n_elem"], info["n_face"], info["n_boundary"], 8, "f64")
+    rh = surf_stats(DH, info["n_elem"], info["n_face"], info["n_boundary"], 8, "f64", tune=True)
     out["mixed_1024sq_p2"] = {"n_elem": info["n_elem"], "n_tri": g["n_tri"], "n_quad": g["n_quad"],
                               "n_face": info["n_face"], "n_colors": info["n_colors"], "color_ms": hs["color_ms"],
                               "conflicts_after_greedy": hs["conflicts_after_greedy"], "f64": rh}
@@ -271,7 +281,7 @@ def extra_workloads(dgc, synth, torch, steps, warmup, log):
     refine_s = time.perf_counter() - t0
     DA = dgc.DeviceMesh(A, 2)
     info = DA.info
-    r = surf_stats(DA, info["n_elem"], info["n_face"], info["n_boundary"], 8, "f64")
+    r = surf_stats(DA, info["n_elem"], info["n_face"], info["n_boundary"], 8, "f64", tune=True)
     out["c3_amr_level3_p2"] = {"n_elem": info["n_elem"], "n_face": info["n_face"], "n_colors": info["n_colors"],
                                "refine_s": refine_s, "f64": r}
     log("c3: %s" % out["c3_amr_level3_p2"])
@@ -430,6 +440,8 @@ def main(argv=None):
                     help="'colored' times the colored pass only, 'volume' the volume-term forms only, 'rk' the "
                          "SSP-RK3 step forms only, 'batch' a batched SSP-RK3 step of 8 periodic meshes of "
                          "125k triangles (for profiling), 'sweep' the host coloring sweep only")
+    ap.add_argument("--variant", choices=["colored", "atomic", "gather", "compact"], default="colored",
+                    help="with --only colored: time this variant of the surface pass instead")
     ap.add_argument("--rk-form", choices=["default", "fused_volume", "fused", "separate"], default="default",
                     help="SSP-RK3 step form timed by --only rk")
     ap.add_argument("--form", choices=["auto", "default", "team", "team_prefetch", "thread", "team_stream", "mode_team",
@@ -562,6 +574,13 @@ def main(argv=None):
         D.set_launch(args.form, args.block, args.xcd_remap)
         best, sweep = {"form": args.form, "block": args.block, "xcd_remap": args.xcd_remap}, []
 
+    if args.variant != "colored":
+        # another variant of the same pass (for counter runs of its kernels)
+        wsv = D.workspace("surface", args.variant) if args.variant in ("gather", "compact") else None
+        t_ms = timed(lambda: D.surface_rhs(Ug, rhs, args.variant, ws=wsv), args.steps, args.warmup, stream)[0]
+        log("%s pass: %.1f us" % (args.variant, t_ms * 1e3))
+        print(json.dumps({"variant": args.variant, "pass_us": t_ms * 1e3, "n_elem": K, "p": args.p}))
+        return 0
     ms, wall = timed(lambda: D.surface_rhs(Ug, rhs, "colored"), args.steps, args.warmup, stream)
     log("colored pass: %.1f us (wall %.2fs for %d steps)" % (ms * 1e3, wall, args.steps))
     value = dof / (ms * 1e-3)

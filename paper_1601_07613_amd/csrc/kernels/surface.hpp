@@ -572,20 +572,21 @@ __device__ __forceinline__ void stage_tables(T *s_tr, T *s_pr, const double *__r
 
 // The same staging in two halves, for kernels that issue their face reads
 // in between: issue() reads this thread's share of the tables into
-// registers (when both tables fit in KT values per thread of a work-group
-// of `block` threads), store() writes them to LDS (or copies the tables
-// there itself when they did not fit) and meets the work-group barrier.
-// Issuing the table reads first keeps them ahead of the face reads, so the
-// wait for the tables does not wait for the records too.  s_pr must follow
-// s_tr directly in LDS.
+// registers when both tables fit in KT values per thread of a work-group of
+// `block` threads (larger tables are copied to LDS right there, before the
+// face reads: a copy loop behind the face reads would wait for them once per
+// trip); store() writes the registers to LDS and meets the work-group
+// barrier.  Issuing the table reads first keeps them ahead of the face
+// reads, so the wait for the tables does not wait for the records too.
+// s_pr must follow s_tr directly in LDS.
 template <class T, int KT = 4>
 struct TableStage {
     double v[KT];
     int ntab, block;
     bool fits;
 
-    __device__ __forceinline__ void issue(const double *__restrict__ tab_trace, const double *__restrict__ tab_proj,
-                                          int ntab_, int block_) {
+    __device__ __forceinline__ void issue(T *s_tr, const double *__restrict__ tab_trace,
+                                          const double *__restrict__ tab_proj, int ntab_, int block_) {
         ntab = ntab_;
         block = block_;
         fits = 2 * ntab <= KT * block;
@@ -595,30 +596,25 @@ struct TableStage {
                 const int idx = (int)threadIdx.x + i * block;
                 if (idx < 2 * ntab) v[i] = idx < ntab ? tab_trace[idx] : tab_proj[idx - ntab];
             }
-        }
-    }
-    __device__ __forceinline__ void store(T *s_tr, const double *__restrict__ tab_trace,
-                                          const double *__restrict__ tab_proj) const {
-        if (fits) {
-#pragma unroll
-            for (int i = 0; i < KT; ++i) {
-                const int idx = (int)threadIdx.x + i * block;
-                if (idx < 2 * ntab) s_tr[idx] = T(v[i]);
-            }
         } else {
             for (int i = threadIdx.x; i < ntab; i += block) {
                 s_tr[i] = T(tab_trace[i]);
                 s_tr[ntab + i] = T(tab_proj[i]);
             }
         }
+    }
+    __device__ __forceinline__ void store(T *s_tr) const {
+        if (fits) {
+#pragma unroll
+            for (int i = 0; i < KT; ++i) {
+                const int idx = (int)threadIdx.x + i * block;
+                if (idx < 2 * ntab) s_tr[idx] = T(v[i]);
+            }
+        }
         __syncthreads();
     }
 };
 
-// One launch of the team form over faces [f_begin, f_end) in work-groups of
-// `block` threads (the launch's block size): the table reads, then the face
-// reads are issued, the tables are staged in LDS while the face's records
-// are in flight, and the teams beyond f_end only take part in the barrier.
 template <int DIM, int NP, int Q, int MODE, class T, bool PREFETCH>
 __global__ __launch_bounds__(256) void surface_team_kernel(
     int64_t f_begin, int64_t f_end, int64_t n_face, int64_t n_elem,
@@ -631,12 +627,12 @@ __global__ __launch_bounds__(256) void surface_team_kernel(
     T *s_tr = reinterpret_cast<T *>(smem_raw);
     T *s_pr = s_tr + n_codes * Q * NP;
     TableStage<T> tabs;
-    tabs.issue(tab_trace, tab_proj, n_codes * Q * NP, block);
+    tabs.issue(s_tr, tab_trace, tab_proj, n_codes * Q * NP, block);
     const int r = threadIdx.x % TEAM;
     const int64_t k = f_begin + ((int64_t)logical_block(remap) * block + threadIdx.x) / TEAM;
     team_face<DIM, NP, Q, MODE, T, PREFETCH>(k, r, n_face, n_elem, face_lr, face_code, face_geo, s_tr, s_pr, n_codes,
                                              U, rhs, buf, CombineArgs{}, VolArgs{}, k < f_end,
-                                             [&] { tabs.store(s_tr, tab_trace, tab_proj); });
+                                             [&] { tabs.store(s_tr); });
 }
 
 template <int DIM, int NP, int Q, int MODE, class T>
@@ -650,11 +646,11 @@ __global__ __launch_bounds__(256) void surface_mode_team_kernel(
     T *s_tr = reinterpret_cast<T *>(smem_raw);
     T *s_pr = s_tr + n_codes * Q * NP;
     TableStage<T> tabs;
-    tabs.issue(tab_trace, tab_proj, n_codes * Q * NP, block);
+    tabs.issue(s_tr, tab_trace, tab_proj, n_codes * Q * NP, block);
     const int64_t k = f_begin + ((int64_t)logical_block(remap) * block + threadIdx.x) / 4;
     mode_team_face<DIM, NP, Q, MODE, T, true>(k, threadIdx.x % 4, n_face, n_elem, face_lr, face_code, face_geo,
                                               s_tr, s_pr, n_codes, U, rhs, buf, CombineArgs{}, nullptr, nullptr,
-                                              nullptr, k < f_end, [&] { tabs.store(s_tr, tab_trace, tab_proj); });
+                                              nullptr, k < f_end, [&] { tabs.store(s_tr); });
 }
 
 // Last color of an SSP-RK3 stage with the stage combination fused in (see
@@ -671,9 +667,9 @@ __global__ __launch_bounds__(256) void surface_combine_kernel(
     double *s_tr = reinterpret_cast<double *>(smem_raw);
     double *s_pr = s_tr + n_codes * Q * NP;
     TableStage<double> tabs;
-    tabs.issue(tab_trace, tab_proj, n_codes * Q * NP, block);
+    tabs.issue(s_tr, tab_trace, tab_proj, n_codes * Q * NP, block);
     const int64_t k = f_begin + ((int64_t)blockIdx.x * block + threadIdx.x) / TEAM;
-    auto mid = [&] { tabs.store(s_tr, tab_trace, tab_proj); };
+    auto mid = [&] { tabs.store(s_tr); };
     if constexpr (MT)
         mode_team_face<DIM, NP, Q, kCombine, double, true>(k, threadIdx.x % 4, n_face, n_elem, face_lr, face_code,
                                                             face_geo, s_tr, s_pr, n_codes, U, rhs, nullptr, cmb,
@@ -699,7 +695,7 @@ __global__ __launch_bounds__(256) void surface_volume_kernel(
     T *s_tr = reinterpret_cast<T *>(smem_raw);
     T *s_pr = s_tr + n_codes * Q * NP;
     TableStage<T> tabs;
-    tabs.issue(tab_trace, tab_proj, n_codes * Q * NP, block);
+    tabs.issue(s_tr, tab_trace, tab_proj, n_codes * Q * NP, block);
     const int64_t k = f_begin + ((int64_t)logical_block(remap) * block + threadIdx.x) / TEAM;
     if constexpr (MT) {
         T *s_vb = s_pr + n_codes * Q * NP;
@@ -709,12 +705,12 @@ __global__ __launch_bounds__(256) void surface_volume_kernel(
             CombineArgs{}, s_vb, s_vd, va.elem_geo, k < f_end, [&] {
                 for (int i = threadIdx.x; i < QV * NP; i += block) s_vb[i] = T(va.vb[i]);
                 for (int i = threadIdx.x; i < DIM * QV * NP; i += block) s_vd[i] = T(va.vd[i]);
-                tabs.store(s_tr, tab_trace, tab_proj);  // its barrier covers the volume tables too
+                tabs.store(s_tr);  // its barrier covers the volume tables too
             });
     } else {
         team_face<DIM, NP, Q, kVolume, T, false, QV>(k, threadIdx.x % TEAM, n_face, n_elem, face_lr, face_code,
                                                      face_geo, s_tr, s_pr, n_codes, U, rhs, nullptr, CombineArgs{},
-                                                     va, k < f_end, [&] { tabs.store(s_tr, tab_trace, tab_proj); });
+                                                     va, k < f_end, [&] { tabs.store(s_tr); });
     }
 }
 

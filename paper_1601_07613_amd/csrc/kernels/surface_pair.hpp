@@ -208,11 +208,11 @@ __global__ __launch_bounds__(256) void surface_pair_team_kernel(
     T *s_tr = reinterpret_cast<T *>(smem_raw);
     T *s_pr = s_tr + n_codes * 3 * 4;
     TableStage<T> tabs;
-    tabs.issue(tab_trace, tab_proj, n_codes * 3 * 4, block);
+    tabs.issue(s_tr, tab_trace, tab_proj, n_codes * 3 * 4, block);
     const int64_t k = f_begin + ((int64_t)logical_block(remap) * block + threadIdx.x) / 4;
     pair_team_face<MODE, T, true>(k, threadIdx.x % 4, n_face, n_elem, face_lr, face_code, face_geo, s_tr, s_pr,
                                   n_codes, U, rhs, buf, CombineArgs{}, k < f_end,
-                                  [&] { tabs.store(s_tr, tab_trace, tab_proj); });
+                                  [&] { tabs.store(s_tr); });
 }
 
 }  // namespace dgc_dev

@@ -145,11 +145,11 @@ __global__ __launch_bounds__(256) void surface_stream_kernel(
     T *s_tr = reinterpret_cast<T *>(smem_raw);
     T *s_pr = s_tr + n_codes * Q * NP;
     TableStage<T> tabs;
-    tabs.issue(tab_trace, tab_proj, n_codes * Q * NP, block);
+    tabs.issue(s_tr, tab_trace, tab_proj, n_codes * Q * NP, block);
     const int64_t k = f_begin + ((int64_t)logical_block(remap) * block + threadIdx.x) / TEAM;
     team_face_stream<DIM, NP, Q, MODE, T>(k, threadIdx.x % TEAM, n_face, n_elem, face_lr, face_code, face_geo, s_tr,
                                           s_pr, n_codes, U, rhs, buf, k < f_end,
-                                          [&] { tabs.store(s_tr, tab_trace, tab_proj); });
+                                          [&] { tabs.store(s_tr); });
 }
 
 }  // namespace dgc_dev
