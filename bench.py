@@ -256,6 +256,24 @@ def extra_workloads(dgc, synth, torch, steps, warmup, log):
     log("quads: %s" % out["quads_1024sq_p2"])
     del DQ, Qm, Uq, wq
 
+    # the same grid numbered in a random order (an unstructured generator's
+    # numbering, Table 2's conflict fraction), paper layout and its Morton extension
+    gs = synth.shuffle_elements(g, seed=7)
+    Qs = dgc.Mesh.build(gs["elem_vert"], gs["elem_xyz"])
+    qss = Qs.color(seed=0)
+    res = {"color_ms": qss["color_ms"], "conflicts_after_greedy": qss["conflicts_after_greedy"],
+           "conflict_fraction": qss["conflicts_after_greedy"] / Qs.info()["n_face"], "swaps": qss["swaps"],
+           "loop_breaks": qss["loop_breaks"]}
+    for lay in ("paper", "paper_sfc"):
+        Qs.set_colors(Qs.export("color"), layout=lay)
+        DS = dgc.DeviceMesh(Qs, 2)
+        info = DS.info
+        res["f64_" + lay] = surf_stats(DS, info["n_elem"], info["n_face"], info["n_boundary"], 8, "f64", tune=True)
+        del DS
+    out["quads_1024sq_random_numbering_p2"] = res
+    log("quads, random numbering: %s" % res)
+    del Qs, gs
+
     # mixed: the same grid with the cells within 0.3 of the center split into triangles, p = 2
     g = synth.hybrid_grid(1024, jitter=0.1, seed=6, radius=0.3)
     Hm = dgc.Mesh.build(g["elem_vert"], g["elem_xyz"])

@@ -19,6 +19,9 @@ def make_input(kind: str, size: int, seed: int):
         return synth.quad_grid(size, seed=seed)
     if kind == "quadbox":
         return synth.quad_grid(size, seed=seed, periodic=False)
+    if kind == "quadshuf":
+        # the grid numbered in a random order, as an unstructured generator would
+        return synth.shuffle_elements(synth.quad_grid(size, seed=seed), seed=seed + 7)
     if kind == "hybrid":
         return synth.hybrid_grid(size, seed=seed)
     if kind == "hybridbox":

@@ -39,7 +39,7 @@ def _eps(kind, p):
     (orthonormal modes grow towards the vertices with the order)."""
     if kind in ("tets", "tetbox"):
         return 0.02 if p <= 1 else 0.005
-    if kind in ("quads", "quadbox", "hybrid", "hybridbox"):
+    if kind in ("quads", "quadbox", "quadshuf", "hybrid", "hybridbox"):
         return 0.02 if p <= 2 else 0.005
     return 0.02 if p <= 3 else 0.004
 
@@ -121,7 +121,7 @@ def test_surface_delaunay_walls_ragged(variant, form, block, xcd):
     _check(got, dg.surface_rhs(c.d, c.U), dg.surface_abs(c.d, c.U), "surface delaunay " + variant)
 
 
-@pytest.mark.parametrize("kind,size", [("quads", 12), ("quadbox", 11)])
+@pytest.mark.parametrize("kind,size", [("quads", 12), ("quadbox", 11), ("quadshuf", 14)])
 @pytest.mark.parametrize("form", ["default", "team", "thread"])
 @pytest.mark.parametrize("p", [0, 1, 2, 3])
 @pytest.mark.parametrize("variant", ["colored", "atomic", "gather", "compact"])

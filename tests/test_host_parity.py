@@ -22,7 +22,8 @@ from paper_1601_07613_amd import _lib  # noqa: E402
 GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_tables.json")))
 HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "dgc.h")
 
-CASES = [("periodic", 16, 1), ("periodic", 37, 4), ("delaunay", 8000, 2), ("tets", 5, 3), ("tetbox", 4, 2), ("quads", 20, 2),
+CASES = [("periodic", 16, 1), ("periodic", 37, 4), ("delaunay", 8000, 2), ("tets", 5, 3), ("tetbox", 4, 2),
+         ("quadshuf", 20, 3), ("quads", 20, 2),
          ("quadbox", 23, 5), ("hybrid", 16, 3), ("hybridbox", 15, 6)]
 
 
