@@ -77,7 +77,8 @@ constexpr int batch_team() {
 // combination instead of the right-hand side.  The fused modes need every
 // member to have exactly one face of each color.
 template <int DIM, int NP, int Q, int QV, int MODE, class T>
-__global__ __launch_bounds__(256) void batch_surface_kernel(const char *__restrict__ desc, int color, int stage) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == kVolume ? f32_min_waves<T>(DIM, NP) : 1, 8)))
+void batch_surface_kernel(const char *__restrict__ desc, int color, int stage) {
     constexpr int TEAM = batch_team<DIM, NP>();
     constexpr bool kMT = DIM == 3 && NP == 4;
     const Header *h = bh(desc);

@@ -16,6 +16,10 @@ __device__ __forceinline__ double dev_sqrt<double>(double x) { return __builtin_
 template <>
 __device__ __forceinline__ float dev_sqrt<float>(float x) { return __builtin_sqrtf(x); }
 
+// a * b + c with one rounding, in the precision of the operands
+__device__ __forceinline__ double dev_fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float dev_fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 // 1/x: the hardware reciprocal refined by one Newton-Raphson step,
 // r <- r + r (1 - x r), which leaves it within about an ulp of the rounded
 // quotient (3 instructions instead of the ~10 of an IEEE division; the

@@ -559,6 +559,14 @@ __device__ __forceinline__ void mode_team_face(
     }
 }
 
+// Occupancy asked of the f32 fused first-color kernels for 2D triangles at
+// p = 2 (N_p = 6): six waves per SIMD fit their registers without spills
+// (the compiler's own choice leaves them at five); 1 (no request) otherwise.
+template <class T>
+constexpr int f32_min_waves(int dim, int np) {
+    return (sizeof(T) == 4 && dim == 2 && np == 6) ? 6 : 1;
+}
+
 // Basis tables of every face code, copied once per work-group into LDS.
 template <class T>
 __device__ __forceinline__ void stage_tables(T *s_tr, T *s_pr, const double *__restrict__ tab_trace,
@@ -666,9 +674,19 @@ __global__ __launch_bounds__(256) void surface_combine_kernel(
     extern __shared__ unsigned char smem_raw[];
     double *s_tr = reinterpret_cast<double *>(smem_raw);
     double *s_pr = s_tr + n_codes * Q * NP;
+    const int64_t k = f_begin + ((int64_t)blockIdx.x * block + threadIdx.x) / TEAM;
+    if constexpr (NP >= 15) {
+        // at p >= 4 the stage-0 state, the right-hand side and the records of
+        // both sides held across the barrier would spill: stage the tables
+        // first, then read the face
+        stage_tables<double>(s_tr, s_pr, tab_trace, tab_proj, n_codes * Q * NP);
+        team_face<DIM, NP, Q, kCombine, double, true>(k, threadIdx.x % TEAM, n_face, n_elem, face_lr, face_code,
+                                                       face_geo, s_tr, s_pr, n_codes, U, rhs, nullptr, cmb,
+                                                       VolArgs{}, k < f_end);
+        return;
+    }
     TableStage<double> tabs;
     tabs.issue(s_tr, tab_trace, tab_proj, n_codes * Q * NP, block);
-    const int64_t k = f_begin + ((int64_t)blockIdx.x * block + threadIdx.x) / TEAM;
     auto mid = [&] { tabs.store(s_tr); };
     if constexpr (MT)
         mode_team_face<DIM, NP, Q, kCombine, double, true>(k, threadIdx.x % 4, n_face, n_elem, face_lr, face_code,
@@ -684,7 +702,8 @@ __global__ __launch_bounds__(256) void surface_combine_kernel(
 // team form, or the mode team for tetrahedra at p = 1 (volume tables staged
 // in LDS after the face tables).
 template <int DIM, int NP, int Q, int QV, bool MT, class T>
-__global__ __launch_bounds__(256) void surface_volume_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(f32_min_waves<T>(DIM, NP), 8)))
+void surface_volume_kernel(
     int64_t f_begin, int64_t f_end, int64_t n_face, int64_t n_elem,
     const int32_t *__restrict__ face_lr, const uint8_t *__restrict__ face_code,
     const double *__restrict__ face_geo, const double *__restrict__ tab_trace,

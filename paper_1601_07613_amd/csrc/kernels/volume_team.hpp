@@ -92,7 +92,7 @@ __device__ __forceinline__ void volume_team_core_geo(int r, const T (&Ji)[DIM * 
 #pragma unroll
         for (int j = 0; j < NP; ++j) {
 #pragma unroll
-            for (int d = 0; d < DIM; ++d) acc[j] = __builtin_fma(T(vd[(d * QV + q) * NP + j]), G[d], acc[j]);
+            for (int d = 0; d < DIM; ++d) acc[j] = dev_fma(T(vd[(d * QV + q) * NP + j]), G[d], acc[j]);
         }
     }
 #pragma unroll
