@@ -31,7 +31,13 @@ colors keep id order), ``"none"`` (1 only, identity element numbering) and
 the boundary faces of the first color are each put in Morton (Z-curve)
 order of their midpoints (ties by id) before step 2.  Midpoints are taken
 from the left element's coordinates and quantised to ``2^31`` (2D) or
-``2^21`` (3D) cells of their bounding box.
+``2^21`` (3D) cells of their bounding box.  ``"paired"`` -- a second
+extension: the first color's interior faces in the same Morton order, cut
+into blocks of ``PAIR_BLOCK`` faces (the last one shorter); block ``b`` with
+``n`` faces numbers its left elements ``2 PAIR_BLOCK b + i`` and its right
+elements ``2 PAIR_BLOCK b + n + i`` (``i < n``), so the two elements of a
+face are never more than ``2 PAIR_BLOCK`` ids apart; the left elements of
+the boundary faces of that color follow; later colors as in ``"paper"``.
 
 Returns ``elem_new[K]`` (new id of original element ``i``), ``face_order[E]``
 (original face id at each layout position) and ``color_off[F + 1]``.
@@ -44,6 +50,8 @@ orientation preserved.
 from __future__ import annotations
 
 import numpy as np
+
+PAIR_BLOCK = 16
 
 
 def morton_order(mesh, faces):
@@ -100,7 +108,7 @@ def make_layout(mesh, color, mode: str = "paper"):
     groups = []
     for c in range(n_colors):
         ids = [f for f in range(mesh.E) if color[f] == c]
-        if c == 0 and mode == "paper_sfc":
+        if c == 0 and mode in ("paper_sfc", "paired"):
             ids = morton_order(mesh, [f for f in ids if R[f] >= 0]) + morton_order(mesh, [f for f in ids if R[f] < 0])
         elif c == 0 and mode != "none":
             ids = [f for f in ids if R[f] >= 0] + [f for f in ids if R[f] < 0]
@@ -111,7 +119,20 @@ def make_layout(mesh, color, mode: str = "paper"):
     else:
         elem_new = np.full(mesh.K, -1, dtype=np.int64)
         nxt = 0
-        for ids in groups:
+        for c, ids in enumerate(groups):
+            if c == 0 and mode == "paired":
+                interior = [f for f in ids if R[f] >= 0]
+                for b0 in range(0, len(interior), PAIR_BLOCK):
+                    block = interior[b0:b0 + PAIR_BLOCK]
+                    for side in (L, R):
+                        for f in block:
+                            elem_new[side[f]] = nxt
+                            nxt += 1
+                for f in ids:
+                    if R[f] < 0:
+                        elem_new[L[f]] = nxt
+                        nxt += 1
+                continue
             for side in (L, R):
                 for f in ids:
                     e = side[f]
@@ -124,7 +145,7 @@ def make_layout(mesh, color, mode: str = "paper"):
     order = []
     off = [0]
     for c, ids in enumerate(groups):
-        if mode in ("paper", "paper_sfc") and c > 0:
+        if mode in ("paper", "paper_sfc", "paired") and c > 0:
             ids = sorted(ids, key=lambda f: elem_new[L[f]])
         order.extend(ids)
         off.append(len(order))
