@@ -45,7 +45,7 @@ def profiled_traffic(args, launch):
 
     same_launch = (launch.get("form") in ("default", "team_prefetch" if args.workload == "delaunay" else "default")
                    and launch.get("block") in (0, 256) and not launch.get("xcd_remap"))
-    default = (same_launch and args.seed == 2 and args.layout == "paper" and
+    default = (same_launch and args.seed == 2 and args.layout == "paired" and
                ((args.workload == "delaunay" and args.points == 500_000 and args.p == 2) or
                 (args.workload == "tets" and args.tet_n == 64 and args.p == 1)))
     if not default:
@@ -180,7 +180,7 @@ def extra_workloads(dgc, synth, torch, steps, warmup, log):
     # c2: 64^3 x 6 periodic Kuhn tetrahedra, p = 1, f64 and f32
     t = synth.kuhn_tets(64, seed=3)
     T = dgc.Mesh.build(t["elem_vert"], t["elem_xyz"])
-    cs = T.color(seed=0)
+    cs = T.color(seed=0, layout="paired")
     DT = dgc.DeviceMesh(T, 1)
     info = DT.info
     # the variants in the default launch; then the colored pass autotuned
@@ -210,25 +210,34 @@ def extra_workloads(dgc, synth, torch, steps, warmup, log):
         DT.rk_step(Ub, dt, precision="f32", ws=wb)
     torch.cuda.synchronize()
     diff = ((Ub - Ua) ** 2).sum(dim=(0, 2)).sqrt() / (Ua ** 2).sum(dim=(0, 2)).sqrt()
-    rk64 = time_call(lambda: DT.rk_step(Ua, dt, precision="f64", ws=wa), reps=5, warmup=1)
-    rk32 = time_call(lambda: DT.rk_step(Ub, dt, precision="f32", ws=wb), reps=5, warmup=1)
+    rk64 = time_call(lambda: DT.rk_step(Ua, dt, precision="f64", ws=wa), reps=20, warmup=3)
+    rk32 = time_call(lambda: DT.rk_step(Ub, dt, precision="f32", ws=wb), reps=20, warmup=3)
     rk_forms = {}
     for rf in ("fused_volume", "fused", "separate"):
         DT.set_rk_form(rf)
-        rk_forms["f64_" + rf] = time_call(lambda: DT.rk_step(Ua, dt, precision="f64", ws=wa), reps=5, warmup=1) * 1e3
-        rk_forms["f32_form_" + rf] = time_call(lambda: DT.rk_step(Ub, dt, precision="f32", ws=wb), reps=5,
-                                               warmup=1) * 1e3
+        rk_forms["f64_" + rf] = time_call(lambda: DT.rk_step(Ua, dt, precision="f64", ws=wa), reps=20,
+                                          warmup=3) * 1e3
+        rk_forms["f32_form_" + rf] = time_call(lambda: DT.rk_step(Ub, dt, precision="f32", ws=wb), reps=20,
+                                               warmup=3) * 1e3
     DT.set_rk_form("default")
+    del DT, Ua, Ub, wa, wb
+    # the paper's own layout of the same coloring (Section 5), autotuned too
+    T.set_colors(T.export("color"), layout="paper")
+    DTp = dgc.DeviceMesh(T, 1)
+    r64paper = surf_stats(DTp, info["n_elem"], info["n_face"], info["n_boundary"], 8, "f64", tune=True)
+    DTp.set_launch("default")
+    r64paperd = surf_stats(DTp, info["n_elem"], info["n_face"], info["n_boundary"], 8, "f64")
     out["c2_kuhn64_tets_p1"] = {
-        "n_elem": info["n_elem"], "n_face": info["n_face"], "n_colors": info["n_colors"],
+        "n_elem": info["n_elem"], "n_face": info["n_face"], "n_colors": info["n_colors"], "layout": "paired",
         "color_ms": cs["color_ms"], "f64": r64, "f32": r32, "f64_default_launch": r64d, "f64_pair_team_form": r64p,
         "f64_thread_form": r64t, "f64_variable_team_form": r64v,
+        "f64_paper_layout": r64paper, "f64_paper_layout_default_launch": r64paperd,
         "rk3_step_us": {"f64": rk64 * 1e3, "f32_form": rk32 * 1e3},
         "rk3_step_by_form_us": rk_forms,
         "f32_form_rel_L2_after_10_steps": [float(x) for x in diff.cpu()],
     }
     log("c2: %s" % out["c2_kuhn64_tets_p1"])
-    del DT, T, Ua, Ub, wa, wb
+    del DTp, T
 
     # quadrilaterals: 1024 x 1024 periodic parallelograms, p = 2 (N_p = 9), four colors
     g = synth.quad_grid(1024, jitter=0.1, seed=6)
@@ -467,7 +476,9 @@ def main(argv=None):
                     help="face-kernel form; 'auto' runs the launch autotuner before timing")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--xcd-remap", action="store_true")
-    ap.add_argument("--layout", choices=["paper", "paper_sfc", "renumber", "none"], default="paper")
+    ap.add_argument("--layout", choices=["paper", "paper_sfc", "paired", "renumber", "none"], default="paired",
+                    help="element numbering and face order: the paper's (Section 5), or the paired extension "
+                         "(first-color pairs in blocks of 16, Morton order; the default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cpu-pool", action="store_true",
                     help="skip the oracle timed over a pool of host processes")
@@ -514,7 +525,7 @@ def main(argv=None):
         for i in range(8):
             mb = synth.periodic_tri(250, seed=10 + i)
             Mb = dgc.Mesh.build(mb["elem_vert"], mb["elem_xyz"])
-            Mb.color(seed=i)
+            Mb.color(seed=i, layout="paired")
             Db = dgc.DeviceMesh(Mb, p)
             st = synth.density_wave_states(synth.element_centroid(mb["elem_xyz"]), vel=(0.5, 0.3))
             Ub = synth.perturbed_dofs(synth.element_measure(mb["elem_xyz"]), st, Db.n_p, eps=0.01, seed=i)
@@ -576,8 +587,12 @@ def main(argv=None):
     if args.only == "rk":
         # SSP-RK3 steps of one form (for counter runs of the step's kernels)
         D.set_rk_form(args.rk_form)
+        if args.form != "auto":
+            D.set_launch(args.form, args.block, args.xcd_remap)
         ws = D.workspace("rk", "colored")
         Ur = Ug.clone()
+        # clocks up: ~0.25 s of steps before the measurement
+        time_call(lambda: D.rk_step(Ur, 1e-7, ws=ws), reps=200, warmup=5)
         t_ms = timed(lambda: D.rk_step(Ur, 1e-7, ws=ws), args.steps, args.warmup, stream)[0]
         log("rk3 step (%s): %.1f us" % (args.rk_form, t_ms * 1e3))
         print(json.dumps({"rk3_step_us": t_ms * 1e3, "rk_form": args.rk_form, "n_elem": K, "p": args.p}))
@@ -640,7 +655,8 @@ def main(argv=None):
                                                   stream)[0] * 1e3
         from paper_1601_07613_amd.tune import autotune_rk
 
-        extra["rk3_step_autotuned_form"] = autotune_rk(D, Ur, 1e-7)[0]
+        best_rk, rk_res = autotune_rk(D, Ur, 1e-7, reps=max(args.steps // 5, 3))
+        extra["rk3_step_autotuned"] = {"form": best_rk, "us": min(ms for _, ms in rk_res) * 1e3}
         D.set_rk_form("default")
         wsr32 = D.workspace("rk", "colored", "f32")
         for rf in ("separate", "fused_volume"):
@@ -657,7 +673,7 @@ def main(argv=None):
         extra["colored_over_gather"] = extra["gather_us"] / (ms * 1e3)
         extra["colored_over_compact"] = extra["compact_us"] / (ms * 1e3)
         # the other layouts of the same coloring, same launch
-        for lay in ("paper", "paper_sfc", "renumber", "none"):
+        for lay in ("paper", "paper_sfc", "paired", "renumber", "none"):
             if lay == args.layout:
                 continue
             D2, _, Ug2, rhs2 = device_mesh(lay)

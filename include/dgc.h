@@ -70,6 +70,10 @@ enum { DGC_TRI = 0, DGC_QUAD = 1, DGC_TET = 2, DGC_MIXED = 3 };
 #define DGC_LAYOUT_NONE      0x40u /* faces grouped by color, elements unchanged */
 #define DGC_LAYOUT_PAPER_SFC 0x80u /* DGC_LAYOUT_PAPER with the first color's faces taken in
                                       Morton order of their midpoints (an extension) */
+#define DGC_LAYOUT_PAIRED   0x100u /* as DGC_LAYOUT_PAPER_SFC, but the first color's interior
+                                      faces are numbered in blocks of 16: block b of n faces gets
+                                      left elements 32b + i and right elements 32b + n + i
+                                      (an extension; boundary faces' left elements follow) */
 
 #define DGC_MAX_COLORS 8
 

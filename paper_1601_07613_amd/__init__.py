@@ -16,7 +16,7 @@ import numpy as np
 from . import _lib
 from ._lib import (  # noqa: F401
     DGC_COLOR_GREEDY_STD, DGC_COLOR_PAPER, DGC_F32, DGC_F64, DGC_LAYOUT_NONE, DGC_LAYOUT_PAPER,
-    DGC_LAYOUT_PAPER_SFC, DGC_LAYOUT_RENUMBER, DGC_MIXED, DGC_QUAD, DGC_SURF_ATOMIC, DGC_SURF_COLORED, DGC_SURF_COMPACT,
+    DGC_LAYOUT_PAIRED, DGC_LAYOUT_PAPER_SFC, DGC_LAYOUT_RENUMBER, DGC_MIXED, DGC_QUAD, DGC_SURF_ATOMIC, DGC_SURF_COLORED, DGC_SURF_COMPACT,
     DGC_SURF_GATHER, DGC_TET,
     DGC_TRI, DgcError,
 )
@@ -27,7 +27,7 @@ VARIANTS = {"colored": DGC_SURF_COLORED, "atomic": DGC_SURF_ATOMIC, "gather": DG
             "compact": DGC_SURF_COMPACT}
 PRECISIONS = {"f64": DGC_F64, "f32": DGC_F32}
 LAYOUTS = {"paper": DGC_LAYOUT_PAPER, "renumber": DGC_LAYOUT_RENUMBER, "none": DGC_LAYOUT_NONE,
-           "paper_sfc": DGC_LAYOUT_PAPER_SFC}
+           "paper_sfc": DGC_LAYOUT_PAPER_SFC, "paired": DGC_LAYOUT_PAIRED}
 ALGORITHMS = {"paper": DGC_COLOR_PAPER, "greedy": DGC_COLOR_GREEDY_STD}
 
 

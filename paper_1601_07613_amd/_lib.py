@@ -11,6 +11,7 @@ LIB_PATH = Path(__file__).resolve().parent / "libdgc.so"
 DGC_TRI, DGC_QUAD, DGC_TET, DGC_MIXED = 0, 1, 2, 3
 DGC_COLOR_PAPER, DGC_COLOR_GREEDY_STD = 0x01, 0x02
 DGC_LAYOUT_PAPER, DGC_LAYOUT_RENUMBER, DGC_LAYOUT_NONE, DGC_LAYOUT_PAPER_SFC = 0x10, 0x20, 0x40, 0x80
+DGC_LAYOUT_PAIRED = 0x100
 DGC_MAX_COLORS = 8
 DGC_SURF_COLORED, DGC_SURF_ATOMIC, DGC_SURF_GATHER, DGC_SURF_COMPACT = 0, 1, 2, 3
 DGC_F64, DGC_F32 = 0, 1

@@ -81,12 +81,12 @@ dgc_status dgc_color_edges(dgc_mesh *h, uint64_t seed, int64_t max_swaps, uint32
     if (!h) return fail(DGC_E_ARG, "dgc_color_edges: null mesh");
     dgc::Mesh &m = h->m;
     if (m.has_tree()) return fail(DGC_E_UNSUPPORTED, "refined meshes are colored by dgc_mesh_refine");
-    uint32_t alg = flags & 0x0Fu, lay = flags & 0xF0u;
+    uint32_t alg = flags & 0x0Fu, lay = flags & 0xFF0u;
     if (lay == 0) lay = DGC_LAYOUT_PAPER;
     if (alg == 0) alg = DGC_COLOR_PAPER;
     if ((alg != DGC_COLOR_PAPER && alg != DGC_COLOR_GREEDY_STD) ||
         (lay != DGC_LAYOUT_PAPER && lay != DGC_LAYOUT_RENUMBER && lay != DGC_LAYOUT_NONE &&
-         lay != DGC_LAYOUT_PAPER_SFC))
+         lay != DGC_LAYOUT_PAPER_SFC && lay != DGC_LAYOUT_PAIRED))
         return fail(DGC_E_ARG, "dgc_color_edges: bad flags");
     try {
         dgc_color_stats st{};
@@ -117,10 +117,10 @@ dgc_status dgc_color_edges(dgc_mesh *h, uint64_t seed, int64_t max_swaps, uint32
 dgc_status dgc_set_colors(dgc_mesh *h, const int8_t *colors, uint32_t layout_flags) {
     if (!h || !colors) return fail(DGC_E_ARG, "dgc_set_colors: null argument");
     dgc::Mesh &m = h->m;
-    uint32_t lay = layout_flags & 0xF0u;
+    uint32_t lay = layout_flags & 0xFF0u;
     if (lay == 0) lay = DGC_LAYOUT_PAPER;
     if (lay != DGC_LAYOUT_PAPER && lay != DGC_LAYOUT_RENUMBER && lay != DGC_LAYOUT_NONE &&
-        lay != DGC_LAYOUT_PAPER_SFC)
+        lay != DGC_LAYOUT_PAPER_SFC && lay != DGC_LAYOUT_PAIRED)
         return fail(DGC_E_ARG, "dgc_set_colors: bad layout flag");
     std::vector<int8_t> c(colors, colors + m.E);
     std::string why;

@@ -15,6 +15,17 @@
 // midpoints, interior faces still first.  Neighbouring pairs of the first
 // color then get neighbouring ids, so the right elements met by the later
 // colors lie close in memory to their left elements.
+//
+// DGC_LAYOUT_PAIRED (an extension, not in the paper): the first color's
+// interior faces in Morton order as above, taken in blocks of kPairBlock;
+// block b of n faces numbers its left elements 2 kPairBlock b + i and its
+// right elements 2 kPairBlock b + n + i (i < n), so a wave of face teams
+// still reads one contiguous run of left records and one of right records,
+// while the two elements of a face get ids at most 2 kPairBlock apart; its
+// boundary faces' left elements follow; later colors as in
+// DGC_LAYOUT_PAPER.  Spatial neighbours then get close ids on both sides of
+// every color, and the scattered right-element records of the later colors
+// share their cache lines with records read at about the same time.
 #include <algorithm>
 #include <cmath>
 
@@ -23,6 +34,10 @@
 namespace dgc {
 
 namespace {
+
+// first-color faces per block of the DGC_LAYOUT_PAIRED numbering: the faces
+// of one wave of four-lane face teams
+constexpr int kPairBlock = 16;
 
 // Morton code of each listed face's midpoint (taken from its left element's
 // coordinates), quantised on the bounding box of those midpoints.
@@ -77,13 +92,14 @@ dgc_status make_layout(Mesh &m, uint32_t flag) {
     const int nc = m.n_colors;
     if (nc <= 0) return fail(DGC_E_NOT_COLORED, "mesh is not colored");
     const bool renumber = flag != DGC_LAYOUT_NONE;
-    const bool reorder = flag == DGC_LAYOUT_PAPER || flag == DGC_LAYOUT_PAPER_SFC;
+    const bool reorder = flag == DGC_LAYOUT_PAPER || flag == DGC_LAYOUT_PAPER_SFC || flag == DGC_LAYOUT_PAIRED;
+    const bool morton = flag == DGC_LAYOUT_PAPER_SFC || flag == DGC_LAYOUT_PAIRED;
 
     std::vector<std::vector<int32_t>> groups(nc);
     for (int64_t f = 0; f < m.E; ++f) groups[m.color[f]].push_back((int32_t)f);
     if (renumber) {
         std::vector<int32_t> &g0 = groups[0];
-        if (flag == DGC_LAYOUT_PAPER_SFC) {
+        if (morton) {
             std::vector<int32_t> in, bd;
             for (int32_t f : g0) (m.face_R[f] >= 0 ? in : bd).push_back(f);
             sort_by_morton(m, in);
@@ -101,6 +117,21 @@ dgc_status make_layout(Mesh &m, uint32_t flag) {
     } else {
         int32_t next = 0;
         for (int c = 0; c < nc; ++c) {
+            if (c == 0 && flag == DGC_LAYOUT_PAIRED) {
+                // no element is numbered yet, and the faces of one color
+                // share no element; interior faces come first in groups[0]
+                const std::vector<int32_t> &g = groups[0];
+                size_t n_in = 0;
+                while (n_in < g.size() && m.face_R[g[n_in]] >= 0) ++n_in;
+                for (size_t b0 = 0; b0 < n_in; b0 += kPairBlock) {
+                    const size_t n = std::min(n_in - b0, (size_t)kPairBlock);
+                    for (size_t i = 0; i < n; ++i) m.elem_new[m.face_L[g[b0 + i]]] = next + (int32_t)i;
+                    for (size_t i = 0; i < n; ++i) m.elem_new[m.face_R[g[b0 + i]]] = next + (int32_t)(n + i);
+                    next += (int32_t)(2 * n);
+                }
+                for (size_t i = n_in; i < g.size(); ++i) m.elem_new[m.face_L[g[i]]] = next++;
+                continue;
+            }
             for (int32_t f : groups[c]) {
                 int32_t e = m.face_L[f];
                 if (m.elem_new[e] < 0) m.elem_new[e] = next++;

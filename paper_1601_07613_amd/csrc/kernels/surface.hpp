@@ -309,11 +309,12 @@ __device__ __forceinline__ void team_face(
     mid();
     if (!ok) return;
 
-    // the volume term of both elements, my variable (kVolume)
+    // the volume term of both elements, my variable (kVolume; the face
+    // record's 1/sqrt(det J) is the division's correctly rounded result)
     T vL[NP], vR[NP];
     if constexpr (MODE == kVolume) {
-        volume_team_core_geo<DIM, NP, QV, T>(r, JiL, sqL, va.vb, va.vd, cL_, vL);
-        if (R >= 0) volume_team_core_geo<DIM, NP, QV, T>(r, JiR, sqR, va.vb, va.vd, cR_, vR);
+        volume_team_core_geo<DIM, NP, QV, T>(r, JiL, sqL, isL, va.vb, va.vd, cL_, vL);
+        if (R >= 0) volume_team_core_geo<DIM, NP, QV, T>(r, JiR, sqR, isR, va.vb, va.vd, cR_, vR);
     }
     // my variable's traces on both sides
     T tL[Q], tR[Q];
@@ -496,8 +497,8 @@ __device__ __forceinline__ void mode_team_face(
     // the volume term of both elements, my mode (kVolume; tables in LDS)
     T vL[M], vR[M];
     if constexpr (MODE == kVolume) {
-        volume_mode_team_core_geo<DIM, NP, QV, T, T>(j, JiL, sqL, s_vb, s_vd, cL_, vL);
-        if (R >= 0) volume_mode_team_core_geo<DIM, NP, QV, T, T>(j, JiR, sqR, s_vb, s_vd, cR_, vR);
+        volume_mode_team_core_geo<DIM, NP, QV, T, T>(j, JiL, sqL, isL, s_vb, s_vd, cL_, vL);
+        if (R >= 0) volume_mode_team_core_geo<DIM, NP, QV, T, T>(j, JiR, sqR, isR, s_vb, s_vd, cR_, vR);
     }
     {
 #pragma unroll

@@ -50,17 +50,18 @@ __device__ __forceinline__ void load_elem_geo(int64_t k, int64_t n_elem, const d
     sq = elem_geo[DIM * DIM * n_elem + k];
 }
 
-// Lane r's share of an element's volume term from its geometry (Ji, sq): c
+// Lane r's share of an element's volume term from its geometry (Ji, sq and
+// inv_sq = 1 / sq, the value a face record already carries): c
 // holds the element's modes of variable r (zeros on lanes r >= M), out
 // receives the result for variable r (all lanes of the team must call; the
 // tables may live in global memory (f64) or in LDS).
 template <int DIM, int NP, int QV, class T, class TAB = double, int UNR = team_volume_unroll(NP)>
-__device__ __forceinline__ void volume_team_core_geo(int r, const T (&Ji)[DIM * DIM], double sq,
+__device__ __forceinline__ void volume_team_core_geo(int r, const T (&Ji)[DIM * DIM], double sq, double inv_sq,
                                                      const TAB *__restrict__ vb, const TAB *__restrict__ vd,
                                                      const T (&c)[NP], T (&out)[NP]) {
     constexpr int M = DIM + 2;
     constexpr int TEAM = volume_team_size<DIM>();
-    const T isq = T(1.0 / sq);
+    const T isq = T(inv_sq);
     // this lane's share of the physical flux F_r(u) = a u_e / rho + [r = 1 + e] p,
     // a = u_r (+ p for the energy): 0/1 selectors fixed per lane
     const T sel_e = r == M - 1 ? T(1) : T(0);
@@ -107,7 +108,7 @@ __device__ __forceinline__ void volume_team_core(int64_t k, int r, int64_t n_ele
     T Ji[DIM * DIM];
     double sq;
     load_elem_geo<DIM, T>(k, n_elem, elem_geo, Ji, sq);
-    volume_team_core_geo<DIM, NP, QV, T, TAB, UNR>(r, Ji, sq, vb, vd, c, out);
+    volume_team_core_geo<DIM, NP, QV, T, TAB, UNR>(r, Ji, sq, 1.0 / sq, vb, vd, c, out);
 }
 
 // element k, lane r of its team (all lanes of the team must call)
@@ -140,11 +141,12 @@ __device__ __forceinline__ void volume_team_elem(int64_t k, int r, int64_t n_ele
 // more than twice the registers.)  All four lanes of the quad must call.
 template <int DIM, int NP, int QV, class T, class TAB = double>
 __device__ __forceinline__ void volume_mode_team_core_geo(int j, const T (&Ji)[DIM * DIM], double sq,
-                                                          const TAB *__restrict__ vb, const TAB *__restrict__ vd,
-                                                          const T (&c)[DIM + 2], T (&out)[DIM + 2]) {
+                                                          double inv_sq, const TAB *__restrict__ vb,
+                                                          const TAB *__restrict__ vd, const T (&c)[DIM + 2],
+                                                          T (&out)[DIM + 2]) {
     static_assert(NP == 4, "mode teams need exactly four modes");
     constexpr int M = DIM + 2;
-    const T isq = T(1.0 / sq);
+    const T isq = T(inv_sq);
     T acc[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) acc[m] = 0;
@@ -185,7 +187,7 @@ __device__ __forceinline__ void volume_mode_team_core(int64_t k, int j, int64_t 
     T Ji[DIM * DIM];
     double sq;
     load_elem_geo<DIM, T>(k, n_elem, elem_geo, Ji, sq);
-    volume_mode_team_core_geo<DIM, NP, QV, T, TAB>(j, Ji, sq, vb, vd, c, out);
+    volume_mode_team_core_geo<DIM, NP, QV, T, TAB>(j, Ji, sq, 1.0 / sq, vb, vd, c, out);
 }
 
 template <int DIM, int NP, int QV, class T>

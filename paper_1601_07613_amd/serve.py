@@ -222,7 +222,7 @@ def _done_future(fn, *a):
 class GPUExecutor:
     """Runs requests on the GPU through libdgc (batched groups or single solves)."""
 
-    def __init__(self, precision: str = "f32", cfl: float = 0.1, seed: int = 0):
+    def __init__(self, precision: str = "f32", cfl: float = 0.1, seed: int = 0, layout: str = "paired"):
         import torch
 
         import paper_1601_07613_amd as dgc
@@ -232,6 +232,7 @@ class GPUExecutor:
         self.precision = precision
         self.cfl = cfl
         self.seed = seed
+        self.layout = layout
         self.batches = {}
         self.graphs = {}
         self.eager_steps = {}
@@ -246,7 +247,7 @@ class GPUExecutor:
         m, U0 = sreq.request_input(r.spec)
         dt = sreq.request_dt(r.spec, m, cfl=self.cfl)
         M = self.dgc.Mesh.build(m["elem_vert"], m["elem_xyz"])
-        M.color(seed=self.seed)
+        M.color(seed=self.seed, layout=self.layout)
         r.footprint = self.dgc.device_footprint(M, r.p, self.precision)
         r.dofs = U0.size
         r.host = (M, U0, dt)

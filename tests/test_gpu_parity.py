@@ -45,7 +45,7 @@ def _eps(kind, p):
 
 
 class Case:
-    def __init__(self, kind, size, seed, p, cseed=0, eps=None):
+    def __init__(self, kind, size, seed, p, cseed=0, eps=None, layout="paper"):
         eps = _eps(kind, p) if eps is None else eps
         import torch
 
@@ -55,7 +55,7 @@ class Case:
         self.O = build_mesh(m["elem_vert"], m["elem_xyz"])
         self.d = dg.Discretization(self.O, p)
         self.M = dgc.Mesh.build(m["elem_vert"], m["elem_xyz"])
-        self.stats = self.M.color(seed=cseed)
+        self.stats = self.M.color(seed=cseed, layout=layout)
         self.D = dgc.DeviceMesh(self.M, p)
         self.U = synth.perturbed_dofs(self.O.elem_measure, _states(m, self.O.K), self.d.n_p, eps=eps, seed=seed + 100)
         self.Ug = torch.from_numpy(self.D.to_layout(self.U)).cuda()
@@ -249,7 +249,7 @@ def test_volume_forms(kind, size, p):
 
 
 @pytest.mark.parametrize("algorithm", ["paper", "greedy"])
-@pytest.mark.parametrize("layout", ["paper", "paper_sfc", "renumber", "none"])
+@pytest.mark.parametrize("layout", ["paper", "paper_sfc", "paired", "renumber", "none"])
 def test_surface_other_layouts(layout, algorithm):
     """Every layout of the paper's coloring and of the standard greedy
     coloring (up to five colors on triangles, Section 1; the Table 7
@@ -501,8 +501,9 @@ def test_surface_stream_form_f32():
 
 @pytest.fixture(scope="module")
 def full_c1():
-    """The full Delaunay workload (~500 k Poisson-disc points, ~1 M triangles, p = 2)."""
-    c = Case("delaunay", 500_000, 2, 2, cseed=0, eps=0.01)
+    """The full Delaunay workload (~500 k Poisson-disc points, ~1 M triangles, p = 2)
+    in the paired layout the benchmark times."""
+    c = Case("delaunay", 500_000, 2, 2, cseed=0, eps=0.01, layout="paired")
     return c
 
 
@@ -522,6 +523,18 @@ def test_full_size_every_element(full_c1):
     other = c.to_host(c.surface("colored"))
     c.D.set_launch("default")
     _check(other, got, dg.surface_abs(c.d, c.U), "full-size thread form vs team form")
+    # the paper's own layout of the same coloring, every element against the oracle
+    import torch
+
+    colors = c.M.export("color")
+    c.M.set_colors(colors, layout="paper")
+    Dp = _dgc().DeviceMesh(c.M, 2)
+    c.M.set_colors(colors, layout="paired")
+    Ugp = torch.from_numpy(Dp.to_layout(c.U)).cuda()
+    rp = torch.zeros_like(Ugp)
+    Dp.surface_rhs(Ugp, rp)
+    torch.cuda.synchronize()
+    _check(Dp.from_layout(rp.cpu().numpy()), ref, dg.surface_abs(c.d, c.U), "full-size colored, paper layout")
 
 
 def test_full_size_rk_step(full_c1):
@@ -552,8 +565,9 @@ def test_full_size_rk_step(full_c1):
 @pytest.fixture(scope="module")
 def full_c2():
     """The full tetrahedral workload: 64^3 periodic cubes x 6 Kuhn tetrahedra
-    (1,572,864 tetrahedra), p = 1, density wave plus 1 % high-mode noise."""
-    return Case("tets", 64, 3, 1, cseed=0, eps=0.01)
+    (1,572,864 tetrahedra), p = 1, density wave plus 1 % high-mode noise, in
+    the paired layout the benchmark times."""
+    return Case("tets", 64, 3, 1, cseed=0, eps=0.01, layout="paired")
 
 
 def test_full_size_tets_every_element(full_c2):

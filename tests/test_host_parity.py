@@ -63,7 +63,7 @@ def test_coloring_and_layout_bit_exact(kind, size, seed, cseed):
     assert np.array_equal(M.export("color").astype(np.int64), color)
     for key in ("conflicts_after_greedy", "swaps", "loop_breaks", "deferrals", "count"):
         assert st[key] == ost[key], key
-    for mode in ("paper", "renumber", "none", "paper_sfc"):
+    for mode in ("paper", "renumber", "none", "paper_sfc", "paired"):
         M.set_colors(color, layout=mode)
         new, order, off = make_layout(O, color, mode)
         assert np.array_equal(M.export("elem_new"), new)
