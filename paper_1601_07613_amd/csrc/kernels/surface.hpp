@@ -313,8 +313,9 @@ __device__ __forceinline__ void team_face(
     // record's 1/sqrt(det J) is the division's correctly rounded result)
     T vL[NP], vR[NP];
     if constexpr (MODE == kVolume) {
-        volume_team_core_geo<DIM, NP, QV, T>(r, JiL, sqL, isL, va.vb, va.vd, cL_, vL);
-        if (R >= 0) volume_team_core_geo<DIM, NP, QV, T>(r, JiR, sqR, isR, va.vb, va.vd, cR_, vR);
+        constexpr int UNR = fused_volume_unroll(NP);
+        volume_team_core_geo<DIM, NP, QV, T, double, UNR>(r, JiL, sqL, isL, va.vb, va.vd, cL_, vL);
+        if (R >= 0) volume_team_core_geo<DIM, NP, QV, T, double, UNR>(r, JiR, sqR, isR, va.vb, va.vd, cR_, vR);
     }
     // my variable's traces on both sides
     T tL[Q], tR[Q];
