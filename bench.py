@@ -266,14 +266,15 @@ def extra_workloads(dgc, synth, torch, steps, warmup, log):
     del DQ, Qm, Uq, wq
 
     # the same grid numbered in a random order (an unstructured generator's
-    # numbering, Table 2's conflict fraction), paper layout and its Morton extension
+    # numbering, Table 2's conflict fraction), paper layout and its Morton and
+    # paired extensions
     gs = synth.shuffle_elements(g, seed=7)
     Qs = dgc.Mesh.build(gs["elem_vert"], gs["elem_xyz"])
     qss = Qs.color(seed=0)
     res = {"color_ms": qss["color_ms"], "conflicts_after_greedy": qss["conflicts_after_greedy"],
            "conflict_fraction": qss["conflicts_after_greedy"] / Qs.info()["n_face"], "swaps": qss["swaps"],
            "loop_breaks": qss["loop_breaks"]}
-    for lay in ("paper", "paper_sfc"):
+    for lay in ("paper", "paper_sfc", "paired"):
         Qs.set_colors(Qs.export("color"), layout=lay)
         DS = dgc.DeviceMesh(Qs, 2)
         info = DS.info
