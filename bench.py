@@ -239,12 +239,17 @@ def extra_workloads(dgc, synth, torch, steps, warmup, log):
     log("c2: %s" % out["c2_kuhn64_tets_p1"])
     del DTp, T
 
-    # quadrilaterals: 1024 x 1024 periodic parallelograms, p = 2 (N_p = 9), four colors
+    # quadrilaterals: 1024 x 1024 periodic parallelograms, p = 2 (N_p = 9), four
+    # colors, paired layout (the paper's layout of the same coloring beside it)
     g = synth.quad_grid(1024, jitter=0.1, seed=6)
     Qm = dgc.Mesh.build(g["elem_vert"], g["elem_xyz"])
     qs = Qm.color(seed=0)
+    DQp = dgc.DeviceMesh(Qm, 2)
+    info = DQp.info
+    rqp = surf_stats(DQp, info["n_elem"], info["n_face"], info["n_boundary"], 8, "f64", tune=True)
+    del DQp
+    Qm.set_colors(Qm.export("color"), layout="paired")
     DQ = dgc.DeviceMesh(Qm, 2)
-    info = DQ.info
     rq = surf_stats(DQ, info["n_elem"], info["n_face"], info["n_boundary"], 8, "f64", tune=True)
     rq32 = surf_stats(DQ, info["n_elem"], info["n_face"], info["n_boundary"], 4, "f32", tune=True)
     Uq = torch.zeros((DQ.K, 4, DQ.n_p), dtype=torch.float64, device="cuda")
@@ -253,13 +258,14 @@ def extra_workloads(dgc, synth, torch, steps, warmup, log):
     wq = DQ.workspace("rk", "colored")
     out["quads_1024sq_p2"] = {
         "n_elem": info["n_elem"], "n_face": info["n_face"], "n_colors": info["n_colors"],
-        "color_ms": qs["color_ms"], "conflicts_after_greedy": qs["conflicts_after_greedy"], "f64": rq, "f32": rq32,
-        "rk3_step_us": time_call(lambda: DQ.rk_step(Uq, 1e-7, ws=wq), reps=5, warmup=1) * 1e3,
+        "color_ms": qs["color_ms"], "conflicts_after_greedy": qs["conflicts_after_greedy"], "layout": "paired",
+        "f64": rq, "f32": rq32, "f64_paper_layout": rqp,
+        "rk3_step_us": time_call(lambda: DQ.rk_step(Uq, 1e-7, ws=wq), reps=10, warmup=2) * 1e3,
     }
     rk_forms = {}
     for rf in ("fused_volume", "fused"):
         DQ.set_rk_form(rf)
-        rk_forms[rf] = time_call(lambda: DQ.rk_step(Uq, 1e-7, ws=wq), reps=5, warmup=1) * 1e3
+        rk_forms[rf] = time_call(lambda: DQ.rk_step(Uq, 1e-7, ws=wq), reps=10, warmup=2) * 1e3
     DQ.set_rk_form("default")
     out["quads_1024sq_p2"]["rk3_step_by_form_us"] = rk_forms
     log("quads: %s" % out["quads_1024sq_p2"])
@@ -284,16 +290,22 @@ def extra_workloads(dgc, synth, torch, steps, warmup, log):
     log("quads, random numbering: %s" % res)
     del Qs, gs
 
-    # mixed: the same grid with the cells within 0.3 of the center split into triangles, p = 2
+    # mixed: the same grid with the cells within 0.3 of the center split into
+    # triangles, p = 2, paired layout (the paper's layout beside it)
     g = synth.hybrid_grid(1024, jitter=0.1, seed=6, radius=0.3)
     Hm = dgc.Mesh.build(g["elem_vert"], g["elem_xyz"])
     hs = Hm.color(seed=0)
     DH = dgc.DeviceMesh(Hm, 2)
     info = DH.info
+    rhp = surf_stats(DH, info["n_elem"], info["n_face"], info["n_boundary"], 8, "f64", tune=True)
+    del DH
+    Hm.set_colors(Hm.export("color"), layout="paired")
+    DH = dgc.DeviceMesh(Hm, 2)
     rh = surf_stats(DH, info["n_elem"], info["n_face"], info["n_boundary"], 8, "f64", tune=True)
     out["mixed_1024sq_p2"] = {"n_elem": info["n_elem"], "n_tri": g["n_tri"], "n_quad": g["n_quad"],
                               "n_face": info["n_face"], "n_colors": info["n_colors"], "color_ms": hs["color_ms"],
-                              "conflicts_after_greedy": hs["conflicts_after_greedy"], "f64": rh}
+                              "conflicts_after_greedy": hs["conflicts_after_greedy"], "layout": "paired", "f64": rh,
+                              "f64_paper_layout": rhp}
     log("mixed: %s" % out["mixed_1024sq_p2"])
     del DH, Hm
 
@@ -310,8 +322,13 @@ def extra_workloads(dgc, synth, torch, steps, warmup, log):
     DA = dgc.DeviceMesh(A, 2)
     info = DA.info
     r = surf_stats(DA, info["n_elem"], info["n_face"], info["n_boundary"], 8, "f64", tune=True)
+    # the same leaves and colors in the paired numbering
+    A.set_colors(A.export("color"), layout="paired")
+    DP = dgc.DeviceMesh(A, 2)
+    rp = surf_stats(DP, info["n_elem"], info["n_face"], info["n_boundary"], 8, "f64", tune=True)
+    del DP
     out["c3_amr_level3_p2"] = {"n_elem": info["n_elem"], "n_face": info["n_face"], "n_colors": info["n_colors"],
-                               "refine_s": refine_s, "f64": r}
+                               "refine_s": refine_s, "f64": r, "f64_paired_layout": rp}
     log("c3: %s" % out["c3_amr_level3_p2"])
     del DA, A
 

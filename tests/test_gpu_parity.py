@@ -272,6 +272,27 @@ def test_surface_other_layouts(layout, algorithm):
     _check(D.from_layout(rhs.cpu().numpy()), dg.surface_rhs(c.d, c.U), dg.surface_abs(c.d, c.U), "layout " + layout)
 
 
+@pytest.mark.parametrize("kind,size,p", [("quads", 12, 2), ("quadshuf", 20, 2), ("hybrid", 14, 2), ("tets", 5, 1),
+                                         ("tetbox", 4, 1), ("periodic", 16, 3)])
+def test_surface_paired_layout_other_kinds(kind, size, p):
+    """The paired numbering on parallelograms (grid and random numbering),
+    mixed meshes, tetrahedra (periodic and walled) and triangles at p = 3,
+    in the default launch: the colored pass and one RK3 step of the default
+    form against the oracle."""
+    import torch
+
+    c = Case(kind, size, 31, p, layout="paired")
+    c.D.set_launch("default")
+    got = c.to_host(c.surface("colored"))
+    _check(got, dg.surface_rhs(c.d, c.U), dg.surface_abs(c.d, c.U), "paired layout " + kind)
+    dt = 1e-4
+    ref = dg.rk3_step(c.d, c.U, dt)
+    U = c.Ug.clone()
+    c.D.rk_step(U, dt, ws=c.D.workspace("rk", "colored"))
+    torch.cuda.synchronize()
+    assert np.abs(c.to_host(U) - ref).max() <= TOL * np.abs(ref).max()
+
+
 def test_surface_accumulates_onto_volume_term():
     import torch
 
