@@ -603,17 +603,19 @@ def main(argv=None):
         return 0
 
     if args.only == "rk":
-        # SSP-RK3 steps of one form (for counter runs of the step's kernels)
+        # SSP-RK3 steps of one form and variant (for counter runs of the step's kernels)
         D.set_rk_form(args.rk_form)
         if args.form != "auto":
             D.set_launch(args.form, args.block, args.xcd_remap)
-        ws = D.workspace("rk", "colored")
+        rv = args.variant if args.variant in ("colored", "compact") else "colored"
+        ws = D.workspace("rk", rv)
         Ur = Ug.clone()
         # clocks up: ~0.25 s of steps before the measurement
-        time_call(lambda: D.rk_step(Ur, 1e-7, ws=ws), reps=200, warmup=5)
-        t_ms = timed(lambda: D.rk_step(Ur, 1e-7, ws=ws), args.steps, args.warmup, stream)[0]
-        log("rk3 step (%s): %.1f us" % (args.rk_form, t_ms * 1e3))
-        print(json.dumps({"rk3_step_us": t_ms * 1e3, "rk_form": args.rk_form, "n_elem": K, "p": args.p}))
+        time_call(lambda: D.rk_step(Ur, 1e-7, variant=rv, ws=ws), reps=200, warmup=5)
+        t_ms = timed(lambda: D.rk_step(Ur, 1e-7, variant=rv, ws=ws), args.steps, args.warmup, stream)[0]
+        log("rk3 step (%s, %s): %.1f us" % (args.rk_form, rv, t_ms * 1e3))
+        print(json.dumps({"rk3_step_us": t_ms * 1e3, "rk_form": args.rk_form, "variant": rv, "n_elem": K,
+                          "p": args.p}))
         return 0
 
     # clocks up: run the pass for ~0.5 s before any measurement
@@ -671,6 +673,10 @@ def main(argv=None):
         D.set_rk_form("fused_volume")
         extra["rk3_step_fused_volume_us"] = timed(lambda: D.rk_step(Ur, 1e-7, ws=wsr), max(args.steps // 5, 3), 2,
                                                   stream)[0] * 1e3
+        wsrc = D.workspace("rk", "compact")
+        extra["rk3_step_compact_us"] = timed(lambda: D.rk_step(Ur, 1e-7, variant="compact", ws=wsrc),
+                                             max(args.steps // 5, 3), 2, stream)[0] * 1e3
+        del wsrc
         from paper_1601_07613_amd.tune import autotune_rk
 
         best_rk, rk_res = autotune_rk(D, Ur, 1e-7, reps=max(args.steps // 5, 3))

@@ -406,7 +406,11 @@ dgc_status dgc_surface_rhs(const dgc_dmesh *dm, const void *U, void *rhs, int32_
 /* One SSP-RK3 step (Shu-Osher form) of U (device f64, updated in place):
  * three stages of volume term + surface term (`variant`) + combination,
  * launched as dm->rk_form says (the volume term and the combination may
- * ride on the first and last color's face kernels, see DGC_RK_*).
+ * ride on the first and last color's face kernels, see DGC_RK_*).  With
+ * DGC_SURF_COMPACT in f64 on conforming triangle and parallelogram meshes
+ * (any rk_form but DGC_RK_SEPARATE) a stage is two launches: the face pass, then one element
+ * pass that evaluates the volume term (the team form, whatever vol_form
+ * says), adds the face records and writes the stage combination.
  * DGC_F32 evaluates both terms on an f32 shadow of the stage state and
  * accumulates the stages in f64.  ws holds the stage states and the RHS
  * (DGC_WS_RK_STEP bytes, dgc_rk_workspace_layout).  Errors: DGC_E_ARG,

@@ -350,6 +350,48 @@ struct Impl {
             default: return fail(DGC_E_ARG, "unknown surface variant");
         }
     }
+
+    // One SSP-RK3 stage of the compact variant (f64, triangles and
+    // parallelograms): the face pass writes every face's record, then one
+    // element pass adds the volume term and the records and writes the
+    // stage combination.
+    static dgc_status compact_stage(const dgc_dmesh *dm, const dgc_table_info &ti, const double *U, void *ws,
+                                    size_t ws_bytes, const dgc_dev::CombineArgs &cmb, hipStream_t st) {
+        if constexpr (DIM == 2 && std::is_same<T, double>::value) {
+            const size_t need = (size_t)dm->n_face * dgc_dev::compact_stride<DIM, Q>() * sizeof(double);
+            if (!ws || ws_bytes < need)
+                return fail(DGC_E_WORKSPACE, "COMPACT needs a workspace of " + std::to_string(need) + " bytes");
+            if (!dm->elem_slots || dm->max_slots <= 0) return fail(DGC_E_ARG, "COMPACT needs elem_slots");
+            double *buf = static_cast<double *>(ws);
+            constexpr int TEAM = 4;
+            const size_t lds = 2 * (size_t)ti.n_codes * Q * NP * sizeof(double);
+            hipLaunchKernelGGL((dgc_dev::surface_team_kernel<DIM, NP, Q, dgc_dev::kFlux, double, false>),
+                               dim3(grid_for(dm->n_face * TEAM)), dim3(kBlock), lds, st, (int64_t)0, dm->n_face,
+                               dm->n_face, dm->n_elem, dm->face_lr, dm->face_code, dm->face_geo,
+                               dm->tables + ti.off_trace, dm->tables + ti.off_proj, ti.n_codes, U,
+                               static_cast<double *>(nullptr), buf, 0, kBlock);
+            dgc_status s = hip_check("compact face pass launch");
+            if (s != DGC_OK) return s;
+            // every element has as many face slots as faces (conforming
+            // triangles and parallelograms)
+            const int faces = dm->elem_type == DGC_TRI ? 3 : 4;
+            if (dm->max_slots != faces)
+                return fail(DGC_E_UNSUPPORTED, "the compact stage kernel needs one slot per face");
+            if (faces == 3)
+                hipLaunchKernelGGL((dgc_dev::compact_stage_kernel<DIM, NP, Q, QV, 3>),
+                                   dim3(grid_for(dm->n_elem * TEAM)), dim3(kBlock), lds / 2, st, dm->n_elem,
+                                   dm->n_face, dm->elem_slots, dm->elem_geo, dm->tables + ti.off_proj, ti.n_codes,
+                                   dm->tables + ti.off_vb, dm->tables + ti.off_vd, buf, U, cmb);
+            else
+                hipLaunchKernelGGL((dgc_dev::compact_stage_kernel<DIM, NP, Q, QV, 4>),
+                                   dim3(grid_for(dm->n_elem * TEAM)), dim3(kBlock), lds / 2, st, dm->n_elem,
+                                   dm->n_face, dm->elem_slots, dm->elem_geo, dm->tables + ti.off_proj, ti.n_codes,
+                                   dm->tables + ti.off_vb, dm->tables + ti.off_vd, buf, U, cmb);
+            return hip_check("compact stage launch");
+        } else {
+            return fail(DGC_E_UNSUPPORTED, "the compact stage kernel is built for f64 triangles and parallelograms");
+        }
+    }
 };
 
 template <class T, class F>
@@ -504,6 +546,21 @@ dgc_status dgc_rk_step(const dgc_dmesh *dm, double *U, double dt, int32_t varian
         return dispatch<double>(dm, 0, 0, [&](auto impl) {
             return decltype(impl)::rk_block(dm, ti, U, U1, U2, static_cast<double *>(rhs), dt, st);
         });
+    }
+    // the compact variant (f64, conforming triangle and parallelogram
+    // meshes): a face pass and one element pass per stage, the element pass
+    // also evaluating the volume term and writing the stage combination
+    if (variant == DGC_SURF_COMPACT && !shadow && dm->rk_form != DGC_RK_SEPARATE &&
+        (dm->elem_type == DGC_TRI || dm->elem_type == DGC_QUAD) &&
+        dm->max_slots == (dm->elem_type == DGC_TRI ? 3 : 4)) {
+        for (int stg = 0; stg < 3; ++stg) {
+            const dgc_dev::CombineArgs cmb{stg == 0 ? nullptr : U, stage_out[stg], a[stg], b[stg], dt};
+            s = dispatch<double>(dm, 0, 0, [&](auto impl) {
+                return decltype(impl)::compact_stage(dm, ti, stage_in[stg], sws, sws_bytes, cmb, st);
+            });
+            if (s != DGC_OK) return s;
+        }
+        return DGC_OK;
     }
     // the stage combination rides on the last color's face kernel, and the
     // volume term on the first color's, when every element has exactly one

@@ -787,6 +787,80 @@ __global__ __launch_bounds__(256) void compact_gather_kernel(
     for (int j = 0; j < NP; ++j) dst[j] = acc[j];
 }
 
+// One SSP-RK3 stage of the compact buffered variant in one element pass
+// (f64, 2D): element k's volume term (the team form, lane = variable), its
+// face records projected as in compact_gather_kernel, and the stage
+// combination out = a x + b (y + dt rhs) with y = U (x is not read when the
+// combination has none); the right-hand side is never stored.  Whole teams
+// share k, so the team exchanges of the volume term see every lane.
+template <int DIM, int NP, int Q, int QV, int MS>
+__global__ __launch_bounds__(256) void compact_stage_kernel(
+    int64_t n_elem, int64_t n_face, const int32_t *__restrict__ elem_slots,
+    const double *__restrict__ elem_geo, const double *__restrict__ tab_proj, int n_codes,
+    const double *__restrict__ vb, const double *__restrict__ vd, const double *__restrict__ flux,
+    const double *__restrict__ U, CombineArgs cmb) {
+    constexpr int M = DIM + 2;
+    constexpr int REC = M * NP;
+    constexpr int TEAM = volume_team_size<DIM>();
+    static_assert(TEAM >= M, "a team holds every variable");
+    constexpr int RS = compact_stride<DIM, Q>();
+    extern __shared__ unsigned char smem_raw[];
+    double *s_pr = reinterpret_cast<double *>(smem_raw);
+    for (int i = threadIdx.x; i < n_codes * Q * NP; i += blockDim.x) s_pr[i] = tab_proj[i];
+    __syncthreads();
+    const int r = threadIdx.x % TEAM;
+    const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / TEAM;
+    if (k >= n_elem) return;
+    const bool own = r < M;
+    // every read is issued before the volume term: the element's record and
+    // geometry, its face slots, then (once the slots are in) its faces'
+    // records, and the stage-0 state of the combination
+    double c[NP];
+    const double *u = U + (size_t)k * REC + r * NP;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) c[j] = own ? u[j] : 0.0;
+    double Ji[DIM * DIM];
+    double sq;
+    load_elem_geo<DIM, double>(k, n_elem, elem_geo, Ji, sq);
+    int32_t slot[MS];
+#pragma unroll
+    for (int s = 0; s < MS; ++s) slot[s] = elem_slots[(int64_t)s * n_elem + k];
+    double F[MS][Q];
+    int code[MS];
+#pragma unroll
+    for (int s = 0; s < MS; ++s) {
+        const bool ok = own && slot[s] >= 0 && slot[s] < 2 * n_face;
+        const double *rec = flux + (size_t)(ok ? slot[s] >> 1 : 0) * RS;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) F[s][q] = ok ? rec[q * M + r] : 0.0;
+        code[s] = ok ? (unpack_codes(rec[Q * M]) >> (8 * (slot[s] & 1))) & 0xFF : 0xFF;
+    }
+    const size_t base = (size_t)k * REC + r * NP;
+    double xs[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) xs[j] = (own && cmb.x) ? cmb.x[base + j] : c[j];
+    const double isq = 1.0 / sq;
+    double acc[NP];
+    volume_team_core_geo<DIM, NP, QV, double>(r, Ji, sq, isq, vb, vd, c, acc);
+    if (!own) return;
+#pragma unroll
+    for (int s = 0; s < MS; ++s) {
+        if (code[s] >= n_codes) continue;
+        const int side = slot[s] & 1;
+        const double *pr = s_pr + code[s] * Q * NP;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            double a = 0;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) a += pr[q * NP + j] * F[s][q];
+            a *= isq;
+            acc[j] = side ? acc[j] + a : acc[j] - a;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NP; ++j) combine_store(cmb, base + j, xs[j], c[j], acc[j]);
+}
+
 // Second pass of the buffered variant: rhs[k] += sum of element k's slots.
 template <int DIM, int NP, class T>
 __global__ __launch_bounds__(256) void gather_kernel(int64_t n_elem, int max_slots, int64_t n_slots_total,

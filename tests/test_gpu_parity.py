@@ -421,6 +421,44 @@ def test_rk3_step_forms_agree(kind, size, p):
     c.D.set_rk_form("default")
 
 
+@pytest.mark.parametrize("kind,size,p", [("delaunay", 6000, 2), ("periodic", 16, 1), ("periodic", 16, 3),
+                                         ("quads", 12, 2), ("quadbox", 11, 1)])
+def test_rk3_compact_stage(kind, size, p):
+    """The compact variant's step (a face pass and one element pass per stage,
+    the element pass adding the volume term and writing the combination)
+    against the oracle's step and, over 5 steps, against the compact step
+    with separate kernels and the colored default step (the same formulas;
+    only the order of sums differs)."""
+    import torch
+
+    c = Case(kind, size, 24, p)
+    st = synth.density_wave_states(synth.element_centroid(c.m["elem_xyz"]), vel=(0.5, 0.3))
+    U0h = synth.perturbed_dofs(c.O.elem_measure, st, c.d.n_p, eps=0.01, seed=6)
+    dt = 1e-4
+    ref = dg.rk3_step(c.d, U0h, dt)
+    U0 = torch.from_numpy(c.D.to_layout(U0h)).cuda()
+    U = U0.clone()
+    wsc = c.D.workspace("rk", "compact")
+    c.D.rk_step(U, dt, variant="compact", ws=wsc)
+    torch.cuda.synchronize()
+    assert np.abs(c.to_host(U) - ref).max() <= TOL * np.abs(ref).max()
+    out = {}
+    for name, variant, form in (("stage", "compact", "default"), ("separate", "compact", "separate"),
+                                ("colored", "colored", "default")):
+        c.D.set_rk_form(form)
+        U = U0.clone()
+        ws = c.D.workspace("rk", variant)
+        for _ in range(5):
+            c.D.rk_step(U, dt, variant=variant, ws=ws)
+        torch.cuda.synchronize()
+        out[name] = U
+    c.D.set_rk_form("default")
+    scale = out["colored"].abs().max().item()
+    assert not torch.equal(out["stage"], U0)
+    for name in ("separate", "colored"):
+        assert (out["stage"] - out[name]).abs().max().item() <= 1e-14 * scale, name
+
+
 @pytest.mark.parametrize("kind,size,p", [("delaunay", 6000, 2), ("periodic", 16, 1), ("tets", 5, 1),
                                          ("quadbox", 11, 1)])
 def test_rk3_f32_form_fused_volume(kind, size, p):
