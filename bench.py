@@ -267,6 +267,10 @@ def extra_workloads(dgc, synth, torch, steps, warmup, log):
         DQ.set_rk_form(rf)
         rk_forms[rf] = time_call(lambda: DQ.rk_step(Uq, 1e-7, ws=wq), reps=10, warmup=2) * 1e3
     DQ.set_rk_form("default")
+    wqc = DQ.workspace("rk", "compact")
+    rk_forms["compact_variant"] = time_call(lambda: DQ.rk_step(Uq, 1e-7, variant="compact", ws=wqc), reps=10,
+                                            warmup=2) * 1e3
+    del wqc
     out["quads_1024sq_p2"]["rk3_step_by_form_us"] = rk_forms
     log("quads: %s" % out["quads_1024sq_p2"])
     del DQ, Qm, Uq, wq
