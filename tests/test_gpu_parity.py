@@ -724,7 +724,7 @@ def test_rk3_f32_form_error_budget():
 
 # ------------------------------------------------- nonconforming (refined) mesh
 
-def _refined(n=24, levels=3, radius=0.15, p=2, cseed=0):
+def _refined(n=24, levels=3, radius=0.15, p=2, cseed=0, layout=None):
     from oracle import refine as R
     from oracle.coloring import color_faces
 
@@ -743,6 +743,8 @@ def _refined(n=24, levels=3, radius=0.15, p=2, cseed=0):
         M, _ = M.refine(flags)
     mesh, color, orient, levels_ = R.to_mesh(st)
     d = dg.Discretization(mesh, p)
+    if layout is not None:
+        M.set_colors(M.export("color"), layout=layout)
     D = dgc.DeviceMesh(M, p)
     print("refined mesh K", mesh.K, "E", mesh.E, "hanging", int((orient[:, 1] >= 2).sum()), flush=True)
     return mesh, d, D
@@ -784,6 +786,36 @@ def test_surface_refined_six_colors(variant, form):
     D.surface_rhs(Ug, rhs, variant=variant, ws=ws)
     torch.cuda.synchronize()
     _check(D.from_layout(rhs.cpu().numpy()), dg.surface_rhs(d, U), dg.surface_abs(d, U), "refined " + variant)
+
+
+def test_refined_paired_layout():
+    """The refined mesh (hanging faces, six colors, elements missing colors)
+    renumbered in the paired layout: every variant of the surface pass and
+    five SSP-RK3 steps against the oracle."""
+    import torch
+
+    mesh, d, D = _refined(n=16, levels=2, radius=0.2, p=2, layout="paired")
+    assert D.info["n_colors"] == 6
+    U = synth.perturbed_dofs(mesh.elem_measure, synth.shock_tube_states(mesh.elem_xyz.mean(axis=1)), d.n_p,
+                             eps=0.02, seed=23)
+    Ug = torch.from_numpy(D.to_layout(U)).cuda()
+    ref, scale = dg.surface_rhs(d, U), dg.surface_abs(d, U)
+    for variant in ("colored", "atomic", "gather", "compact"):
+        rhs = torch.zeros_like(Ug)
+        ws = D.workspace("surface", variant) if variant in ("gather", "compact") else None
+        D.surface_rhs(Ug, rhs, variant=variant, ws=ws)
+        torch.cuda.synchronize()
+        _check(D.from_layout(rhs.cpu().numpy()), ref, scale, "refined, paired layout, " + variant)
+    U0 = dg.project(d, lambda X: synth.isentropic_vortex(X, 0.0))
+    dt = dg.cfl_dt(d, U0, 0.1)
+    Ug = torch.from_numpy(D.to_layout(U0)).cuda()
+    ws = D.workspace("rk", "colored")
+    Uo = U0.copy()
+    for _ in range(5):
+        D.rk_step(Ug, dt, ws=ws)
+        Uo = dg.rk3_step(d, Uo, dt)
+    torch.cuda.synchronize()
+    assert np.abs(D.from_layout(Ug.cpu().numpy()) - Uo).max() / np.abs(Uo).max() <= TOL
 
 
 def test_rk3_refined_vortex_20_steps():

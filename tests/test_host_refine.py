@@ -174,3 +174,18 @@ def test_coarsen_all_the_way_back_to_the_base_coloring():
     assert M.info()["max_level"] == 0 and M.info()["n_colors"] == 3
     assert np.array_equal(M.export("color").astype(np.int64), base[1])
     assert np.array_equal(M.export("face_elem").reshape(-1, 2), base[0].face_elem)
+
+
+@pytest.mark.parametrize("mode", ["paired", "paper_sfc", "renumber", "none"])
+def test_refined_mesh_other_layouts_bit_exact(mode):
+    """A refined mesh (six colors, elements missing colors) laid out again in
+    every other mode: the library's numbering and face order equal the
+    oracle's."""
+    m = synth.periodic_tri(24, jitter=0.0, seed=4)
+    st, M = _run(m, 3, 0.15, 0)
+    mesh, color = _compare(st, M)
+    M.set_colors(color.astype(np.int8), layout=mode)
+    new, order, off = make_layout(mesh, color, mode)
+    assert np.array_equal(M.export("elem_new"), new)
+    assert np.array_equal(M.export("face_order"), order)
+    assert np.array_equal(M.export("color_off"), off)
