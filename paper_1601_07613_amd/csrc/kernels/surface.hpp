@@ -259,13 +259,16 @@ __device__ __forceinline__ void team_face(
     const bool rd = ok && own;
 
     // the right-hand-side reads of a colored update are issued up front with
-    // the DOF reads (PREFETCH)
+    // the DOF reads (PREFETCH); the right side's at N_p = 9 in f64 once the
+    // traces are formed (LATE_R), when the modes of both sides are dead: the
+    // kernel then fits three waves per SIMD instead of two
+    constexpr bool LATE_R = PREFETCH && MODE == kColored && sizeof(T) == 8 && NP == 9;
     T pre_L[NP], pre_R[NP];
     if (PREFETCH && RMW && rd) {
         const T *a = rhs + (size_t)L * REC + r * NP;
 #pragma unroll
         for (int j = 0; j < NP; ++j) pre_L[j] = a[j];
-        if (R >= 0) {
+        if (!LATE_R && R >= 0) {
             const T *b = rhs + (size_t)R * REC + r * NP;
 #pragma unroll
             for (int j = 0; j < NP; ++j) pre_R[j] = b[j];
@@ -338,6 +341,12 @@ __device__ __forceinline__ void team_face(
             for (int j = 0; j < NP; ++j) a += tr[q * NP + j] * cR_[j];
             tR[q] = a * T(isR);
         }
+    }
+
+    if (LATE_R && rd && R >= 0) {
+        const T *b = rhs + (size_t)R * REC + r * NP;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) pre_R[j] = b[j];
     }
 
     // full states at every point, my component of their flux
@@ -416,10 +425,11 @@ __device__ __forceinline__ void team_face(
 // Mode-team form of the face work for N_p = 4 (tetrahedra, p = 1): a team
 // of 4 lanes per face, lane j owns mode j of every conserved variable.  Each
 // lane forms its mode's share of all traces, the shares are summed across
-// the quad with DPP, every lane evaluates the flux of the full state and lane
-// j projects onto mode j.  Loads and stores of one record are 4 consecutive
-// values per instruction, and no lane idles (the variable-per-lane team
-// would need 8 lanes for M = 5).
+// the quad with DPP, lane j evaluates the flux of the full state at point j
+// (Q <= 4; a fourth lane repeats the last point), the quad broadcasts the
+// fluxes and lane j projects onto mode j.  Loads and stores of one record are
+// 4 consecutive values per instruction (the variable-per-lane team would
+// need 8 lanes for M = 5).
 template <int DIM, int NP, int Q, int MODE, class T, bool PREFETCH, int QV = 1, class Mid = NoMid>
 __device__ __forceinline__ void mode_team_face(
     int64_t k, int j, int64_t n_face, int64_t n_elem,
@@ -494,19 +504,27 @@ __device__ __forceinline__ void mode_team_face(
     mid();
     if (!ok) return;
 
-    T uL[Q][M], uR[Q][M];
     // the volume term of both elements, my mode (kVolume; tables in LDS)
     T vL[M], vR[M];
     if constexpr (MODE == kVolume) {
         volume_mode_team_core_geo<DIM, NP, QV, T, T>(j, JiL, sqL, isL, s_vb, s_vd, cL_, vL);
         if (R >= 0) volume_mode_team_core_geo<DIM, NP, QV, T, T>(j, JiR, sqR, isR, s_vb, s_vd, cR_, vR);
     }
-    {
+    // the traces at every point are sums over the quad of each lane's mode
+    // share; lane j keeps those of point min(j, Q - 1) and evaluates the flux
+    // there only, and the quad exchanges the fluxes for the projection
+    static_assert(Q <= 4, "one quadrature point per lane of the quad");
+    const int qo = j < Q ? j : Q - 1;
+    T uL[M], uR[M];
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const T t = s_tr[(cL * Q + q) * NP + j];
+    for (int m = 0; m < M; ++m) uL[m] = uR[m] = T(0);
 #pragma unroll
-            for (int m = 0; m < M; ++m) uL[q][m] = quad_sum(t * cL_[m]) * T(isL);
+    for (int q = 0; q < Q; ++q) {
+        const T t = s_tr[(cL * Q + q) * NP + j];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const T v = quad_sum(t * cL_[m]) * T(isL);
+            uL[m] = q == qo ? v : uL[m];
         }
     }
     if (R >= 0) {
@@ -514,15 +532,21 @@ __device__ __forceinline__ void mode_team_face(
         for (int q = 0; q < Q; ++q) {
             const T t = s_tr[(cR * Q + q) * NP + j];
 #pragma unroll
-            for (int m = 0; m < M; ++m) uR[q][m] = quad_sum(t * cR_[m]) * T(isR);
+            for (int m = 0; m < M; ++m) {
+                const T v = quad_sum(t * cR_[m]) * T(isR);
+                uR[m] = q == qo ? v : uR[m];
+            }
         }
     } else {
-#pragma unroll
-        for (int q = 0; q < Q; ++q) wall_ghost<DIM, T>(uL[q], n, uR[q]);
+        wall_ghost<DIM, T>(uL, n, uR);
     }
+    T Fo[M];
+    rusanov<DIM, T>(uL, uR, n, Fo);
     T F[Q][M];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) rusanov<DIM, T>(uL[q], uR[q], n, F[q]);
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int m = 0; m < M; ++m) F[q][m] = team_bcast<4>(Fo[m], q);
     {
         const T sL = T(len * isL);
         T *dst = MODE == kGather ? buf + (size_t)(2 * k) * REC : rhs + (size_t)L * REC;
