@@ -479,8 +479,9 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", choices=["delaunay", "tets"], default="delaunay",
-                    help="delaunay: ~1M triangles, p=2 (the headline); tets: 64^3 x 6 Kuhn tetrahedra, p=1")
+    ap.add_argument("--workload", choices=["delaunay", "tets", "quads"], default="delaunay",
+                    help="delaunay: ~1M triangles, p=2 (the headline); tets: 64^3 x 6 Kuhn tetrahedra, p=1; "
+                         "quads: 1024^2 periodic parallelograms, p=2")
     ap.add_argument("--points", type=int, default=500_000)
     ap.add_argument("--tet-n", type=int, default=64)
     ap.add_argument("--p", type=int, default=None)
@@ -564,6 +565,9 @@ def main(argv=None):
     t = time.perf_counter()
     if args.workload == "delaunay":
         m = synth.poisson_delaunay(args.points, seed=args.seed)
+        p = 2 if args.p is None else args.p
+    elif args.workload == "quads":
+        m = synth.quad_grid(1024, jitter=0.1, seed=6)
         p = 2 if args.p is None else args.p
     else:
         m = synth.kuhn_tets(args.tet_n, seed=3)
@@ -798,6 +802,9 @@ def main(argv=None):
                          "%d edges, %d wall edges), 2D Euler p=%d (N_p=%d, M=4), shock tube, colored surface pass, "
                          "%s layout" % (m["n_vert"], K, E, nb, args.p, D.n_p, args.layout))
             if args.workload == "delaunay" else
+            ("periodic 1024^2 jittered parallelograms (%d cells, %d edges), 2D Euler p=%d (N_p=%d, M=4), density "
+             "wave, colored surface pass, %s layout" % (K, E, args.p, D.n_p, args.layout))
+            if args.workload == "quads" else
             ("periodic %d^3 cubes x 6 Kuhn tetrahedra (%d tets, %d faces), 3D Euler p=%d (N_p=%d, M=5), density "
              "wave, colored surface pass, %s layout" % (args.tet_n, K, E, args.p, D.n_p, args.layout)),
             "n_elem": K, "n_face": E, "p": args.p, "n_colors": info["n_colors"], "variant": "colored",
