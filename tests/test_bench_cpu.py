@@ -52,3 +52,41 @@ def test_sweep_sizes_follow_the_paper_tables(fam):
     golden = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_tables.json")))
     sides = [s for s, _ in golden["figure9_conflicts"][fam]]
     assert bench.SWEEP_SIDES[fam] == tuple(sides)
+
+
+@pytest.mark.parametrize("profile,n_face,n_bnd,rec,dim,n_colors", [
+    ("surface_colored_team_prefetch_delaunay996k_p2_f64.md", 1_497_218, 3_520, 4 * 6, 2, 3),
+    ("surface_colored_mode_team_kuhn64_tets_p1_f64.md", 3_145_728, 0, 5 * 4, 3, 4),
+    ("surface_colored_team_prefetch_quads1024_p2_f64.md", 2_097_152, 0, 4 * 9, 2, 4),
+])
+def test_profiles_quote_the_benchmark_byte_counts(profile, n_face, n_bnd, rec, dim, n_colors):
+    """The algorithmic bytes per launch that each colored-pass profile divides
+    its counters by are the benchmark's own count for that workload."""
+    import re
+
+    text = open(os.path.join(ROOT, "profiles", profile)).read()
+    per_launch = bench.algorithmic_bytes(n_face, n_face - n_bnd, rec, 8, dim) // n_colors
+    quoted = re.search(r"Algorithmic bytes per launch: ([0-9,]+) B", text)
+    assert quoted is not None
+    assert int(quoted.group(1).replace(",", "")) == per_launch
+
+
+def test_profiled_traffic_matches_the_profile_of_the_committed_kernels():
+    """bench.py reports the counter traffic only for the configuration and
+    kernel sources the profile was taken with."""
+    import hashlib
+    import re
+    import types
+
+    args = types.SimpleNamespace(workload="delaunay", layout="paired", seed=2, points=500_000, p=2, tet_n=64)
+    launch = {"form": "default", "block": 256, "xcd_remap": False}
+    text = open(bench.PROFILES["delaunay"]).read()
+    sha = hashlib.sha256(b"".join(open(f, "rb").read() for f in bench.KERNEL_SOURCES)).hexdigest()[:16]
+    if re.search(r"kernel_source_sha256_16: ([0-9a-f]{16})", text).group(1) != sha:
+        pytest.skip("the kernel sources changed since the profile was taken")
+    traffic = int(re.search(r"traffic_bytes_per_launch: (\d+)", text).group(1))
+    assert bench.profiled_traffic(args, launch) == traffic
+    # another layout, launch or size: no figure
+    assert bench.profiled_traffic(types.SimpleNamespace(**{**vars(args), "layout": "paper"}), launch) is None
+    assert bench.profiled_traffic(args, {**launch, "xcd_remap": True}) is None
+    assert bench.profiled_traffic(types.SimpleNamespace(**{**vars(args), "points": 20_000}), launch) is None
