@@ -14,7 +14,10 @@ and a synchronisation, which a membership that changes every few steps
 would pay over and over).  Finished requests free their memory for the next
 admission: their group's batch and graph, which reference every member's
 arrays, are dropped before the next admission and rebuilt for the members
-that remain.  A request whose result is not finite fails alone.
+that remain.  The host waits for an iteration's device work one iteration
+later (a finishing request's download, a rebuild or a drop waits at once),
+so it admits and launches the next iteration while the device runs this
+one.  A request whose result is not finite fails alone.
 
 ``mode="sequential"`` is the plain baseline: one request at a time, each
 advanced by the single-mesh f64 step without batching or graphs.
@@ -174,7 +177,6 @@ class Server:
                 dirty.clear()
                 self.ex.sync()
                 st.iterations += 1
-                now = clock.now()
                 for p in sorted(active):
                     keep = []
                     for r in active[p]:
@@ -184,7 +186,7 @@ class Server:
                             continue
                         ok = self.ex.finish(r)
                         used -= r.footprint
-                        r.t_done = now
+                        r.t_done = clock.now()  # the result is on the host
                         if ok:
                             r.status = "done"
                             st.completed += 1
@@ -244,6 +246,7 @@ class GPUExecutor:
         self.eager_steps = {}
         self.captures = 0
         self.streams = {}  # one stream per group (default priority)
+        self.last_step = None  # event after the previous iteration's work
 
     # host work (worker threads): mesh, coloring, layout, initial DOFs; the
     # request supplies its time step, the library the device footprint
@@ -277,11 +280,16 @@ class GPUExecutor:
 
     def drop_group(self, p) -> None:
         """Let go of group p's batch descriptor and captured graph, which hold
-        the device arrays of every member, finished ones included."""
+        the device arrays of every member, finished ones included (after the
+        work that uses them)."""
+        self.torch.cuda.synchronize()
         self.batches.pop(p, None)
         self.graphs.pop(p, None)
 
     def rebuild(self, p, group) -> None:
+        # the group's previous descriptor and graph may still be in use by the
+        # iteration in flight
+        self.torch.cuda.synchronize()
         self.batches[p] = self.dgc.Batch([r.dev for r in group], precision=self.precision)
         self.graphs.pop(p, None)
         self.eager_steps[p] = 0
@@ -313,10 +321,25 @@ class GPUExecutor:
         D.rk_step(U, dt, precision="f64", ws=ws)
 
     def sync(self) -> None:
-        self.torch.cuda.synchronize()
+        """End of an iteration's launches: the caller's stream waits for every
+        group's stream, and the host waits for the previous iteration only,
+        so that it prepares the next iteration while this one runs (a
+        finishing request's download, a rebuild or a drop waits for the rest)."""
+        torch = self.torch
+        cur = torch.cuda.current_stream()
+        for s in self.streams.values():
+            cur.wait_stream(s)
+        ev = torch.cuda.Event()
+        ev.record(cur)
+        if self.last_step is not None:
+            self.last_step.synchronize()
+        self.last_step = ev
 
     def finish(self, r: Request) -> bool:
         D, U, ws, dt = r.dev
+        cur = self.torch.cuda.current_stream()
+        for s in self.streams.values():
+            cur.wait_stream(s)
         res = D.from_layout_device(U).cpu().numpy()
         r.result = res
         r.dev = None
